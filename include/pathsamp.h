@@ -1,0 +1,198 @@
+/*
+ * pathsamp -- 3-path sampling for the six connected 4-vertex induced subgraph
+ * counts (Jha, Seshadhri, Pinar, "Path Sampling: A Fast and Provable Method
+ * for Estimating 4-Vertex Subgraph Counts"), as HIP kernels for MI355X
+ * (gfx950) behind a C ABI.
+ *
+ * Motif numbering (the paper's Figure 1): 1 3-star, 2 3-path,
+ * 3 tailed-triangle, 4 4-cycle, 5 chordal-4-cycle, 6 4-clique.
+ *
+ * Conventions for every call:
+ *  - Every function returns a pm_status: PM_OK (0) or a negative code.  On
+ *    failure pm_last_error() holds a message for the calling thread.
+ *  - "stream" arguments are hipStream_t values passed as void*; NULL means
+ *    the default stream.  Calls that take a stream return after the results
+ *    they report are on the host (they synchronise that stream).
+ *  - The caller owns every buffer it passes in; the library never frees or
+ *    keeps a pointer to caller memory past the call.
+ *  - No C++ exception crosses this boundary.
+ */
+#ifndef PATHSAMP_H
+#define PATHSAMP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pm_status;
+
+#define PM_OK 0
+#define PM_EINVAL (-1)     /* null pointer, n < 0, k == 0, delta outside (0,1), size limit */
+#define PM_EGRAPH (-2)     /* CSR not an undirected simple graph (see pm_graph_create) */
+#define PM_EOVERFLOW (-3)  /* 2W, 2 Lambda or N_1 does not fit in 64 bits */
+#define PM_ENOMEM (-4)     /* device or host allocation failed */
+#define PM_EDEVICE (-5)    /* a HIP runtime call failed */
+#define PM_EBUSY (-6)      /* server: request does not fit the memory budget now */
+#define PM_ECANCELED (-7)  /* server: request cancelled */
+
+/* Tally slots.  3-path sampler: TRI (u' = v'), then motifs 2..6.
+ * Centered sampler: TRI (u' = v'), OPEN (not a centered 3-path), motifs 4..6. */
+#define PM_TALLY_TRI 0
+#define PM_TALLY_OPEN 1
+#define PM_NUM_TALLIES 8
+
+/* Flags of pm_graph_create. */
+#define PM_VALIDATE 1u        /* check offsets, ranges, self-loops, sorted rows */
+#define PM_CHECK_SYMMETRY 2u  /* also check that every edge appears in both rows */
+
+/* An input graph in CSR form.  row_offsets has n+1 entries, starting at 0
+ * and non-decreasing; cols has row_offsets[n] entries, each row strictly
+ * ascending.  The graph must be undirected (every edge stored in both rows)
+ * and simple (no self-loops, no repeated edge): the input of Section 2.
+ * on_device != 0 means both pointers are device memory of the current HIP
+ * device; otherwise they are host memory and are copied in. */
+typedef struct {
+    int64_t n;
+    const int64_t *row_offsets;
+    const int32_t *cols;
+    int32_t on_device;
+} pm_csr_view;
+
+/* Sampling parameters.  k_path samples of Algorithm 2 (3-path-sampler) and
+ * k_cent of Algorithm 4 (centered-sampler); sample ids first_id ..
+ * first_id + k - 1 of each sampler, so disjoint id ranges of one seed add up
+ * to one longer run.  delta is the per-motif failure probability of the
+ * error bars (Corollary 5.3), 0.01 for 99% bars. */
+typedef struct {
+    uint64_t k_path;
+    uint64_t k_cent;
+    uint64_t seed;
+    uint64_t first_id_path;
+    uint64_t first_id_cent;
+    double delta;
+} pm_params;
+
+/* Result of one count.  Arrays est/lo/hi/est_basic are indexed by motif
+ * number 1..6 (index 0 unused).  est_basic[4..6] are Algorithm 2's own
+ * estimates of the cycle-based motifs (the ones the paper discards). */
+typedef struct {
+    uint64_t tally_path[PM_NUM_TALLIES];
+    uint64_t tally_cent[PM_NUM_TALLIES];
+    uint64_t W;       /* sum over edges of (d_u - 1)(d_v - 1)      (Section 3) */
+    uint64_t Lambda;  /* sum over edges of L_{u,v} L_{v,u}         (Section 4) */
+    uint64_t N1;      /* sum over vertices of C(d_v, 3)           (Algorithm 2) */
+    uint64_t k_path;
+    uint64_t k_cent;
+    double est[7];
+    double lo[7];
+    double hi[7];
+    double est_basic[7];
+} pm_result;
+
+typedef struct {
+    int64_t n;
+    int64_t m;              /* undirected edges */
+    int64_t dmax;
+    int64_t isolated;       /* vertices of degree 0 */
+    uint64_t W;
+    uint64_t Lambda;
+    uint64_t N1;
+    uint64_t device_bytes;  /* resident device memory of the handle */
+} pm_graph_info;
+
+typedef struct pm_graph pm_graph;
+
+/* ------------------------------------------------------------------------ */
+/* One-shot                                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* The whole method on one graph (end of Section 4): prepare the graph with
+ * full validation, run both samplers with k samples each (seed, ids from 0),
+ * and fill estimates with 99% Corollary 5.3 bars.  Default stream. */
+pm_status pm_count_motifs(const pm_csr_view *csr, uint64_t k, uint64_t seed, pm_result *out);
+
+/* ------------------------------------------------------------------------ */
+/* Prepared graphs                                                           */
+/* ------------------------------------------------------------------------ */
+
+/* Prepare a graph on the current device: degrees, the degree-order relabel of
+ * Section 4 (u before v iff d_u < d_v, or equal degrees and smaller input id;
+ * rows re-sorted so that this order is integer order), the per-slot weights
+ * tau = (d_u - 1)(d_v - 1) of Section 3 and lambda = L_{u,v} L_{v,u} of
+ * Section 4 with their inclusive prefix sums, and N_1.
+ * Limits: n < 2^31, 2m < 2^32.  Errors: PM_EINVAL (null / limits),
+ * PM_EGRAPH (a failed check of flags), PM_EOVERFLOW, PM_ENOMEM, PM_EDEVICE.
+ * The handle owns its device memory; release with pm_graph_destroy.  A handle
+ * is immutable after creation: concurrent pm_count calls on it are safe. */
+pm_status pm_graph_create(const pm_csr_view *csr, uint32_t flags, void *stream, pm_graph **out);
+
+pm_status pm_graph_info_get(const pm_graph *g, pm_graph_info *out);
+
+/* Copy the prepared arrays to host buffers (any pointer may be NULL):
+ * off[n+1] and col[2m] of the relabelled graph, rank[n] (input id ->
+ * relabelled id), p_tau[2m] and p_lam[2m] (inclusive prefix sums over slots). */
+pm_status pm_graph_export(const pm_graph *g, int64_t *off, int32_t *col, int32_t *rank, uint64_t *p_tau,
+                          uint64_t *p_lam, void *stream);
+
+pm_status pm_graph_destroy(pm_graph *g);
+
+/* Run both samplers on a prepared graph and finalize on the host.  A sampler
+ * whose total weight is 0 (W = 0 or Lambda = 0) draws nothing: its tallies,
+ * estimates and bars are exactly 0.  k_path = k_cent = 0 is PM_EINVAL. */
+pm_status pm_count(const pm_graph *g, const pm_params *p, pm_result *out, void *stream);
+
+/* Tallies only (no host finalize), written to the device buffer
+ * tallies_dev[16] (path then centered, uint64) on the stream, without
+ * synchronising.  The buffer is overwritten, not accumulated. */
+pm_status pm_sample_async(const pm_graph *g, const pm_params *p, uint64_t *tallies_dev, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Host-side estimates and error bars                                        */
+/* ------------------------------------------------------------------------ */
+
+/* Estimates of Algorithms 2 and 4 and the bars of Corollary 5.3 from tallies
+ * (fills every field of out).  W, Lambda, N1 as in pm_result. */
+pm_status pm_finalize(const uint64_t tally_path[PM_NUM_TALLIES], const uint64_t tally_cent[PM_NUM_TALLIES],
+                      uint64_t W, uint64_t Lambda, uint64_t N1, uint64_t k_path, uint64_t k_cent, double delta,
+                      pm_result *out);
+
+/* (p_l, p_u) of Definition 5.2: the roots of k D(count/k, p) = ln(1/delta). */
+pm_status pm_chernoff_interval(uint64_t count, uint64_t k, double delta, double *p_lo, double *p_hi);
+
+/* Smallest k whose Corollary 5.3 bar around a proportion alpha stays within
+ * relative error rel_err at failure probability delta:
+ * k = ceil(ln(1/delta) / min(D(alpha, alpha(1+e)), D(alpha, alpha(1-e)))). */
+pm_status pm_samples_for_error(double rel_err, double delta, double alpha, uint64_t *k_out);
+
+/* ------------------------------------------------------------------------ */
+/* Diagnostics                                                               */
+/* ------------------------------------------------------------------------ */
+
+/* Philox4x32-10 block function evaluated on the device for count inputs of
+ * six words (c0 c1 c2 c3 k0 k1) each, host arrays in and out (4 words per
+ * input). */
+pm_status pm_philox_device(const uint32_t *in, uint32_t *out, int64_t count);
+
+/* Per-kernel timing with HIP events recorded on each launch's stream.
+ * pm_profile_enable clears the totals and switches recording on (1) or off
+ * (0); pm_profile_read waits for the recorded events and returns one entry
+ * per kernel name (count = number of names, entries beyond capacity are
+ * dropped).  Timing adds two event records per launch. */
+typedef struct {
+    char name[48];
+    uint64_t launches;
+    double total_ms;
+} pm_profile_entry;
+
+pm_status pm_profile_enable(int32_t on);
+pm_status pm_profile_read(pm_profile_entry *out, int32_t capacity, int32_t *count);
+
+const char *pm_status_string(pm_status s);
+const char *pm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PATHSAMP_H */

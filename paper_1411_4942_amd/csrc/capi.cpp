@@ -1,0 +1,158 @@
+// The C ABI of include/pathsamp.h: argument checks, error strings, and the
+// one-shot and prepared-graph entry points.  No exception leaves this file.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/pathsamp.h"
+
+struct pm_graph;
+
+namespace pm {
+
+static thread_local std::string t_last_error;
+
+void set_error(const std::string &msg) { t_last_error = msg; }
+
+pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm_graph **out);
+void graph_free(pm_graph *g, hipStream_t s);
+pm_status graph_export(const pm_graph *g, int64_t *off, int32_t *col, int32_t *rank, uint64_t *p_tau,
+                       uint64_t *p_lam, hipStream_t s);
+pm_status graph_info(const pm_graph *g, pm_graph_info *out);
+pm_status sample_async(const pm_graph *g, const pm_params *p, uint64_t *tallies_dev, hipStream_t s);
+pm_status finalize(const uint64_t tp[PM_NUM_TALLIES], const uint64_t tc[PM_NUM_TALLIES], uint64_t W,
+                   uint64_t Lambda, uint64_t N1, uint64_t k_path, uint64_t k_cent, double delta, pm_result *out);
+pm_status chernoff_interval(uint64_t count, uint64_t k, double delta, double *p_lo, double *p_hi);
+pm_status samples_for_error(double rel_err, double delta, double alpha, uint64_t *k_out);
+pm_status philox_device(const uint32_t *in, uint32_t *out, int64_t count);
+pm_status dev_alloc(void **p, size_t bytes, hipStream_t s);
+void dev_free(void *p, hipStream_t s);
+pm_status count_on_graph(const pm_graph *g, const pm_params *p, pm_result *out, hipStream_t s);
+
+}  // namespace pm
+
+#define PM_GUARD(body)                                          \
+    try {                                                       \
+        body                                                    \
+    } catch (const std::bad_alloc &) {                          \
+        pm::set_error("host allocation failed");                \
+        return PM_ENOMEM;                                       \
+    } catch (...) {                                             \
+        pm::set_error("unexpected internal error");             \
+        return PM_EDEVICE;                                      \
+    }
+
+extern "C" {
+
+const char *pm_status_string(pm_status s)
+{
+    switch (s) {
+    case PM_OK: return "PM_OK";
+    case PM_EINVAL: return "PM_EINVAL";
+    case PM_EGRAPH: return "PM_EGRAPH";
+    case PM_EOVERFLOW: return "PM_EOVERFLOW";
+    case PM_ENOMEM: return "PM_ENOMEM";
+    case PM_EDEVICE: return "PM_EDEVICE";
+    case PM_EBUSY: return "PM_EBUSY";
+    case PM_ECANCELED: return "PM_ECANCELED";
+    default: return "PM_UNKNOWN";
+    }
+}
+
+const char *pm_last_error(void) { return pm::t_last_error.c_str(); }
+
+pm_status pm_graph_create(const pm_csr_view *csr, uint32_t flags, void *stream, pm_graph **out)
+{
+    PM_GUARD(return pm::graph_create(csr, flags, (hipStream_t)stream, out);)
+}
+
+pm_status pm_graph_destroy(pm_graph *g)
+{
+    PM_GUARD({
+        if (!g) {
+            pm::set_error("null graph");
+            return PM_EINVAL;
+        }
+        pm::graph_free(g, nullptr);
+        hipError_t e = hipStreamSynchronize(nullptr);
+        if (e != hipSuccess) {
+            pm::set_error(std::string("pm_graph_destroy: ") + hipGetErrorString(e));
+            return PM_EDEVICE;
+        }
+        return PM_OK;
+    })
+}
+
+pm_status pm_graph_info_get(const pm_graph *g, pm_graph_info *out)
+{
+    PM_GUARD(return pm::graph_info(g, out);)
+}
+
+pm_status pm_graph_export(const pm_graph *g, int64_t *off, int32_t *col, int32_t *rank, uint64_t *p_tau,
+                          uint64_t *p_lam, void *stream)
+{
+    PM_GUARD(return pm::graph_export(g, off, col, rank, p_tau, p_lam, (hipStream_t)stream);)
+}
+
+pm_status pm_sample_async(const pm_graph *g, const pm_params *p, uint64_t *tallies_dev, void *stream)
+{
+    PM_GUARD(return pm::sample_async(g, p, tallies_dev, (hipStream_t)stream);)
+}
+
+pm_status pm_count(const pm_graph *g, const pm_params *p, pm_result *out, void *stream)
+{
+    PM_GUARD(return pm::count_on_graph(g, p, out, (hipStream_t)stream);)
+}
+
+pm_status pm_count_motifs(const pm_csr_view *csr, uint64_t k, uint64_t seed, pm_result *out)
+{
+    PM_GUARD({
+        if (!csr || !out || k == 0) {
+            pm::set_error("pm_count_motifs: null argument or k == 0");
+            return PM_EINVAL;
+        }
+        pm_graph *g = nullptr;
+        pm_status st = pm::graph_create(csr, PM_VALIDATE | PM_CHECK_SYMMETRY, nullptr, &g);
+        if (st != PM_OK) return st;
+        pm_params p;
+        std::memset(&p, 0, sizeof(p));
+        p.k_path = k;
+        p.k_cent = k;
+        p.seed = seed;
+        p.delta = 0.01;
+        st = pm::count_on_graph(g, &p, out, nullptr);
+        pm::graph_free(g, nullptr);
+        hipError_t e = hipStreamSynchronize(nullptr);
+        if (st == PM_OK && e != hipSuccess) {
+            pm::set_error(std::string("pm_count_motifs: ") + hipGetErrorString(e));
+            return PM_EDEVICE;
+        }
+        return st;
+    })
+}
+
+pm_status pm_finalize(const uint64_t tally_path[PM_NUM_TALLIES], const uint64_t tally_cent[PM_NUM_TALLIES],
+                      uint64_t W, uint64_t Lambda, uint64_t N1, uint64_t k_path, uint64_t k_cent, double delta,
+                      pm_result *out)
+{
+    PM_GUARD(return pm::finalize(tally_path, tally_cent, W, Lambda, N1, k_path, k_cent, delta, out);)
+}
+
+pm_status pm_chernoff_interval(uint64_t count, uint64_t k, double delta, double *p_lo, double *p_hi)
+{
+    PM_GUARD(return pm::chernoff_interval(count, k, delta, p_lo, p_hi);)
+}
+
+pm_status pm_samples_for_error(double rel_err, double delta, double alpha, uint64_t *k_out)
+{
+    PM_GUARD(return pm::samples_for_error(rel_err, delta, alpha, k_out);)
+}
+
+pm_status pm_philox_device(const uint32_t *in, uint32_t *out, int64_t count)
+{
+    PM_GUARD(return pm::philox_device(in, out, count);)
+}
+
+}  // extern "C"

@@ -1,0 +1,63 @@
+// Device-resident prepared graph (the pm_graph handle) and the view the
+// sampling kernels take.
+#pragma once
+
+#include "common.hpp"
+
+// Relabelled graph: vertex ids are positions in the degree order of Section 4
+// (degree, then input id), so "u before v" is integer u < v and every row is
+// sorted in that order.  Slot s is position s of the CSR; src[s] is its row.
+struct pm_graph {
+    int device = 0;
+    int64_t n = 0;
+    int64_t slots = 0;            // 2m
+    int64_t *off = nullptr;       // [n+1]
+    uint32_t *col = nullptr;      // [slots]
+    uint32_t *src = nullptr;      // [slots]
+    uint32_t *deg = nullptr;      // [n]
+    int32_t *rank = nullptr;      // [n] input id -> relabelled id
+    uint64_t *p_tau = nullptr;    // [slots] inclusive prefix of tau
+    uint64_t *p_lam = nullptr;    // [slots] inclusive prefix of lambda
+    uint32_t *guide_tau = nullptr;  // [nb_tau + 1]
+    uint32_t *guide_lam = nullptr;  // [nb_lam + 1]
+    uint32_t shift_tau = 0, shift_lam = 0;
+    uint64_t nb_tau = 0, nb_lam = 0;
+    uint64_t R_tau = 0;  // 2W
+    uint64_t R_lam = 0;  // 2 Lambda
+    uint64_t N1 = 0;
+    int64_t dmax = 0;
+    int64_t isolated = 0;
+    uint64_t bytes = 0;
+};
+
+namespace pm {
+
+// Everything one sampler needs about one graph.
+struct SamplerView {
+    const int64_t *off;
+    const uint32_t *col;
+    const uint32_t *src;
+    const uint64_t *P;       // inclusive prefix of the sampler's weights
+    const uint32_t *guide;   // guide[j] = first slot with P > j << shift
+    uint64_t R;              // total weight (0: sampler skipped)
+    uint32_t shift;
+};
+
+inline SamplerView view_of(const pm_graph *g, bool centered)
+{
+    SamplerView v;
+    v.off = g->off;
+    v.col = g->col;
+    v.src = g->src;
+    v.P = centered ? g->p_lam : g->p_tau;
+    v.guide = centered ? g->guide_lam : g->guide_tau;
+    v.R = centered ? g->R_lam : g->R_tau;
+    v.shift = centered ? g->shift_lam : g->shift_tau;
+    return v;
+}
+
+// device memory through the stream-ordered allocator
+pm_status dev_alloc(void **p, size_t bytes, hipStream_t s);
+void dev_free(void *p, hipStream_t s);
+
+}  // namespace pm

@@ -1,0 +1,706 @@
+// Graph preparation: validation, degrees, the degree-order relabel of
+// Section 4, tau/lambda weights with their prefix sums (Sections 3 and 4),
+// N_1 (Algorithm 2) and the guide tables of the edge draw.
+//
+// Relabel by two stable sorts and one transposition identity: with the rows
+// placed in the new order (G1, columns mapped but unsorted), a stable sort of
+// G1's entries by column yields them ordered by (column, row), which for a
+// symmetric graph is exactly the new CSR with every row ascending (the
+// transpose of a symmetric graph is itself).  A second stable sort of the
+// result's slots by column lists, at position q, the slot holding the reverse
+// of slot q: that permutation is at once the symmetry check and the reverse
+// slot map the lambda weights need.
+#include "graph.hpp"
+#include "profile.hpp"
+#include "radix.hpp"
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+namespace pm {
+
+enum : uint32_t {
+    ERR_OFFSETS = 1u,
+    ERR_RANGE = 2u,
+    ERR_LOOP = 4u,
+    ERR_ORDER = 8u,
+    ERR_ASYM = 16u,
+    ERR_OVF_TAU = 32u,
+    ERR_OVF_LAM = 64u,
+};
+
+struct PrepStats {
+    uint32_t err;
+    uint32_t dmax;
+    uint64_t isolated;
+    uint64_t n1_lo;
+    uint64_t n1_hi;
+    uint32_t nlong_tau;
+    uint32_t nlong_lam;
+};
+
+// ---------------------------------------------------------------------------
+// allocation
+// ---------------------------------------------------------------------------
+
+static std::mutex g_pool_mu;
+static bool g_pool_ready[64];
+
+pm_status dev_alloc(void **p, size_t bytes, hipStream_t s)
+{
+    int dev = 0;
+    PM_HIP(hipGetDevice(&dev));
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        if (dev >= 0 && dev < 64 && !g_pool_ready[dev]) {
+            hipMemPool_t pool;
+            if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+                uint64_t thr = UINT64_MAX;  // keep freed blocks for reuse
+                (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+            }
+            g_pool_ready[dev] = true;
+        }
+    }
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMallocAsync(p, bytes, s);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        set_error(std::string("hipMallocAsync(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? PM_ENOMEM : PM_EDEVICE;
+    }
+    return PM_OK;
+}
+
+void dev_free(void *p, hipStream_t s)
+{
+    if (p) (void)hipFreeAsync(p, s);
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_degrees(const int64_t *__restrict__ off, int64_t n, int64_t slots,
+                                                    uint32_t *__restrict__ deg, uint32_t *__restrict__ head,
+                                                    PrepStats *st)
+{
+    uint32_t err = 0, dmax = 0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        int64_t a = off[v], b = off[v + 1];
+        if (a < 0 || b < a || b > slots) {
+            err |= ERR_OFFSETS;
+            deg[v] = 0;
+            continue;
+        }
+        uint32_t d = (uint32_t)(b - a);
+        deg[v] = d;
+        if (d > 0) head[a] = (uint32_t)v;
+        dmax = d > dmax ? d : dmax;
+    }
+    if (err) atomicOr(&st->err, err);
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        uint32_t x = __shfl_xor(dmax, o, kWave);
+        dmax = x > dmax ? x : dmax;
+    }
+    if (lane_id() == 0) atomicMax(&st->dmax, dmax);
+}
+
+struct HeadIn {
+    const uint32_t *h;
+    __device__ __forceinline__ uint32_t operator()(int64_t i) const { return h[i]; }
+};
+struct StoreOut32 {
+    uint32_t *o;
+    __device__ __forceinline__ void operator()(int64_t i, uint32_t incl, uint32_t) const { o[i] = incl; }
+};
+
+// rows strictly ascending, columns in range, no self-loops (src = row of slot)
+__global__ __launch_bounds__(kBlock) void k_check_slots(const int32_t *__restrict__ col,
+                                                        const uint32_t *__restrict__ src, int64_t slots, int64_t n,
+                                                        PrepStats *st)
+{
+    uint32_t err = 0;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < slots;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        int32_t c = col[s];
+        uint32_t u = src[s];
+        if (c < 0 || (int64_t)c >= n)
+            err |= ERR_RANGE;
+        else if ((uint32_t)c == u)
+            err |= ERR_LOOP;
+        if (s > 0 && src[s - 1] == u && col[s - 1] >= c) err |= ERR_ORDER;
+    }
+    if (err) atomicOr(&st->err, err);
+}
+
+__global__ void k_iota(uint32_t *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = (uint32_t)i;
+}
+
+__global__ void k_rank_from_order(const uint32_t *__restrict__ order, int32_t *__restrict__ rank, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        rank[order[i]] = (int32_t)i;
+}
+
+struct DegIn {
+    const uint32_t *d;
+    __device__ __forceinline__ uint64_t operator()(int64_t i) const { return d[i]; }
+};
+struct OffOut {
+    int64_t *off;  // writes off[i+1]
+    __device__ __forceinline__ void operator()(int64_t i, uint64_t incl, uint64_t) const { off[i + 1] = (int64_t)incl; }
+};
+
+// G1: the input's slots moved into the rows of the new order (unsorted rows)
+__global__ __launch_bounds__(kBlock) void k_place_rows(const int64_t *__restrict__ off_in,
+                                                       const int32_t *__restrict__ col_in,
+                                                       const uint32_t *__restrict__ src_in,
+                                                       const int32_t *__restrict__ rank,
+                                                       const int64_t *__restrict__ off_new, int64_t slots,
+                                                       uint32_t *__restrict__ key, uint32_t *__restrict__ val)
+{
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < slots;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t u = src_in[s];
+        int32_t ru = rank[u];
+        int64_t dst = off_new[ru] + (s - off_in[u]);
+        key[dst] = (uint32_t)rank[col_in[s]];
+        val[dst] = (uint32_t)ru;
+    }
+}
+
+__global__ void k_copy_u32(const uint32_t *__restrict__ a, uint32_t *__restrict__ b, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = a[i];
+}
+
+// symmetric iff the slots sorted by (col, row) are the slots sorted by
+// (row, col) with the pair reversed
+__global__ __launch_bounds__(kBlock) void k_check_symmetry(const uint32_t *__restrict__ key2,
+                                                           const uint32_t *__restrict__ perm,
+                                                           const uint32_t *__restrict__ src,
+                                                           const uint32_t *__restrict__ col, int64_t slots,
+                                                           PrepStats *st)
+{
+    bool bad = false;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < slots;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        if (key2[q] != src[q] || src[perm[q]] != col[q]) bad = true;
+    }
+    if (bad) atomicOr(&st->err, (uint32_t)ERR_ASYM);
+}
+
+// Section 3: tau_s = (d_u - 1)(d_v - 1)
+struct TauIn {
+    const uint32_t *src, *col, *deg;
+    __device__ __forceinline__ uint64_t operator()(int64_t s) const
+    {
+        return (uint64_t)(deg[src[s]] - 1u) * (uint64_t)(deg[col[s]] - 1u);
+    }
+};
+
+// Section 4: lambda_s = L_{u,v} L_{v,u}; L_{u,v} = d_u - 1 - (position of v in
+// row u), the neighbours of u after v; the reverse slot gives L_{v,u}
+struct LamIn {
+    const uint32_t *src, *col, *deg, *rev;
+    const int64_t *off;
+    __device__ __forceinline__ uint64_t operator()(int64_t s) const
+    {
+        uint32_t u = src[s], v = col[s];
+        int64_t r = rev[s];
+        uint64_t luv = (uint64_t)((int64_t)deg[u] - 1 - (s - off[u]));
+        uint64_t lvu = (uint64_t)((int64_t)deg[v] - 1 - (r - off[v]));
+        return luv * lvu;
+    }
+};
+
+// inclusive prefix with wrap detection: incl < x happens iff the sum passed 2^64
+struct PrefixOut {
+    uint64_t *p;
+    PrepStats *st;
+    uint32_t flag;
+    __device__ __forceinline__ void operator()(int64_t i, uint64_t incl, uint64_t x) const
+    {
+        p[i] = incl;
+        if (incl < x) atomicOr(&st->err, flag);
+    }
+};
+
+// N_1 = sum_v C(d_v, 3) in 128 bits; isolated vertices
+__global__ __launch_bounds__(kBlock) void k_n1(const uint32_t *__restrict__ deg, int64_t n, PrepStats *st)
+{
+    unsigned __int128 acc = 0;
+    uint64_t iso = 0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t d = deg[v];
+        iso += d == 0;
+        if (d >= 3) {
+            uint64_t a = d, b = d - 1, c = d - 2;
+            if (a % 3 == 0) a /= 3; else if (b % 3 == 0) b /= 3; else c /= 3;
+            if ((a & 1) == 0) a >>= 1; else if ((b & 1) == 0) b >>= 1; else c >>= 1;
+            acc += (unsigned __int128)(a * b) * c;
+        }
+    }
+    uint64_t lo = (uint64_t)acc, hi = (uint64_t)(acc >> 64);
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        uint64_t olo = __shfl_xor(lo, o, kWave), ohi = __shfl_xor(hi, o, kWave);
+        uint64_t nlo = lo + olo;
+        hi = hi + ohi + (nlo < lo ? 1u : 0u);
+        lo = nlo;
+        iso += __shfl_xor(iso, o, kWave);
+    }
+    if (lane_id() == 0) {
+        unsigned long long old = atomicAdd((unsigned long long *)&st->n1_lo, (unsigned long long)lo);
+        uint64_t carry = (old + lo < old) ? 1u : 0u;
+        atomicAdd((unsigned long long *)&st->n1_hi, (unsigned long long)(hi + carry));
+        atomicAdd((unsigned long long *)&st->isolated, (unsigned long long)iso);
+    }
+}
+
+// guide[j] = first slot whose prefix exceeds j << shift; slot s covers the
+// buckets whose start lies in [P[s-1], P[s]).  Long ranges go to a list.
+__global__ __launch_bounds__(kBlock) void k_guide(const uint64_t *__restrict__ P, int64_t slots, uint32_t shift,
+                                                  uint32_t *__restrict__ guide, uint32_t *__restrict__ long_list,
+                                                  uint32_t *nlong)
+{
+    const uint64_t mask = (shift == 0) ? 0ull : ((1ull << shift) - 1ull);
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < slots;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t prev = s > 0 ? P[s - 1] : 0ull, cur = P[s];
+        if (cur <= prev) continue;
+        uint64_t j0 = (prev >> shift) + ((prev & mask) != 0 ? 1u : 0u);
+        uint64_t j1 = (cur - 1) >> shift;
+        if (j1 < j0) continue;
+        if (j1 - j0 < 64) {
+            for (uint64_t j = j0; j <= j1; ++j) guide[j] = (uint32_t)s;
+        } else {
+            uint32_t idx = atomicAdd(nlong, 1u);
+            long_list[idx] = (uint32_t)s;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_guide_long(const uint64_t *__restrict__ P, uint32_t shift,
+                                                       uint32_t *__restrict__ guide,
+                                                       const uint32_t *__restrict__ long_list,
+                                                       const uint32_t *nlong)
+{
+    const uint64_t mask = (shift == 0) ? 0ull : ((1ull << shift) - 1ull);
+    const uint32_t cnt = *nlong;
+    for (uint32_t e = blockIdx.x; e < cnt; e += gridDim.x) {
+        uint32_t s = long_list[e];
+        uint64_t prev = s > 0 ? P[s - 1] : 0ull, cur = P[s];
+        uint64_t j0 = (prev >> shift) + ((prev & mask) != 0 ? 1u : 0u);
+        uint64_t j1 = (cur - 1) >> shift;
+        for (uint64_t j = j0 + threadIdx.x; j <= j1; j += blockDim.x) guide[j] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct Temps {
+    hipStream_t s;
+    std::vector<void *> ptrs;
+    explicit Temps(hipStream_t st) : s(st) {}
+    ~Temps()
+    {
+        for (void *p : ptrs) dev_free(p, s);
+    }
+    template <typename T>
+    pm_status get(T **p, size_t count)
+    {
+        void *q = nullptr;
+        PM_TRY(dev_alloc(&q, count * sizeof(T), s));
+        ptrs.push_back(q);
+        *p = (T *)q;
+        return PM_OK;
+    }
+    void release(void *p)
+    {
+        for (auto &q : ptrs)
+            if (q == p) {
+                dev_free(q, s);
+                q = nullptr;
+            }
+    }
+    void keep(void *p)
+    {
+        for (auto &q : ptrs)
+            if (q == p) q = nullptr;
+    }
+};
+
+int grid_stream(int64_t n) { return grid_for(n, kBlock, 4096); }
+
+const char *err_text(uint32_t e)
+{
+    if (e & ERR_OFFSETS) return "row offsets decrease or leave [0, 2m]";
+    if (e & ERR_RANGE) return "a column is not a vertex id";
+    if (e & ERR_LOOP) return "self-loop";
+    if (e & ERR_ORDER) return "a row is not strictly ascending (unsorted or repeated edge)";
+    if (e & ERR_ASYM) return "adjacency is not symmetric (graph must be undirected)";
+    return "invalid graph";
+}
+
+// smallest shift with ((R-1) >> shift) + 1 <= target buckets
+void choose_guide(uint64_t R, int64_t slots, uint32_t *shift, uint64_t *nb)
+{
+    uint64_t target = (uint64_t)std::max<int64_t>(1, slots / 4);
+    uint32_t sh = 0;
+    while (sh < 63 && ((R - 1) >> sh) + 1 > target) ++sh;
+    *shift = sh;
+    *nb = ((R - 1) >> sh) + 1;
+}
+
+pm_status build_guide(const uint64_t *P, int64_t slots, uint64_t R, Temps &tmp, PrepStats *st_dev,
+                      uint32_t *nlong_dev, uint32_t **guide_out, uint32_t *shift_out, uint64_t *nb_out,
+                      uint64_t *bytes, hipStream_t s)
+{
+    *guide_out = nullptr;
+    *shift_out = 0;
+    *nb_out = 0;
+    if (R == 0) return PM_OK;
+    uint32_t shift;
+    uint64_t nb;
+    choose_guide(R, slots, &shift, &nb);
+    uint32_t *guide = nullptr;
+    PM_TRY(dev_alloc((void **)&guide, (nb + 1) * sizeof(uint32_t), s));
+    *guide_out = guide;
+    *bytes += (nb + 1) * sizeof(uint32_t);
+    uint32_t cap = (uint32_t)(nb / 64 + 2);
+    uint32_t *long_list = nullptr;
+    PM_TRY(tmp.get(&long_list, cap));
+    PM_TRY(fill_async<uint32_t>(guide + nb, (uint32_t)(slots - 1), 1, s));
+    ProfScope prof("guide", s);
+    hipLaunchKernelGGL(k_guide, dim3(grid_stream(slots)), dim3(kBlock), 0, s, P, slots, shift, guide, long_list,
+                       nlong_dev);
+    PM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_guide_long, dim3(std::min<uint32_t>(cap, 2048)), dim3(kBlock), 0, s, P, shift, guide,
+                       long_list, nlong_dev);
+    PM_HIP(hipGetLastError());
+    *shift_out = shift;
+    *nb_out = nb;
+    (void)st_dev;
+    return PM_OK;
+}
+
+}  // namespace
+
+void graph_free(pm_graph *g, hipStream_t s)
+{
+    if (!g) return;
+    dev_free(g->off, s);
+    dev_free(g->col, s);
+    dev_free(g->src, s);
+    dev_free(g->deg, s);
+    dev_free(g->rank, s);
+    dev_free(g->p_tau, s);
+    dev_free(g->p_lam, s);
+    dev_free(g->guide_tau, s);
+    dev_free(g->guide_lam, s);
+    delete g;
+}
+
+pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm_graph **out)
+{
+    (void)flags;  // every check always runs: later kernels rely on them
+    if (!csr || !out || !csr->row_offsets) {
+        set_error("null argument");
+        return PM_EINVAL;
+    }
+    *out = nullptr;
+    const int64_t n = csr->n;
+    if (n < 0 || n > (int64_t)INT32_MAX) {
+        set_error("n must lie in [0, 2^31)");
+        return PM_EINVAL;
+    }
+    ProfScope prof_total("prep_total", s);
+    Temps tmp(s);
+
+    // offsets bounds from the host side
+    int64_t first = 0, slots = 0;
+    if (csr->on_device) {
+        PM_HIP(hipMemcpyAsync(&first, csr->row_offsets, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        PM_HIP(hipMemcpyAsync(&slots, csr->row_offsets + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        PM_HIP(hipStreamSynchronize(s));
+    } else {
+        first = csr->row_offsets[0];
+        slots = csr->row_offsets[n];
+    }
+    if (first != 0 || slots < 0) {
+        set_error(err_text(ERR_OFFSETS));
+        return PM_EGRAPH;
+    }
+    if (slots >= (int64_t)UINT32_MAX) {
+        set_error("2m must be below 2^32");
+        return PM_EINVAL;
+    }
+    if (slots > 0 && !csr->cols) {
+        set_error("null cols");
+        return PM_EINVAL;
+    }
+
+    const int64_t *off_in = csr->row_offsets;
+    const int32_t *col_in = csr->cols;
+    if (!csr->on_device) {
+        int64_t *o = nullptr;
+        int32_t *c = nullptr;
+        PM_TRY(tmp.get(&o, (size_t)n + 1));
+        PM_TRY(tmp.get(&c, (size_t)std::max<int64_t>(slots, 1)));
+        PM_HIP(hipMemcpyAsync(o, csr->row_offsets, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s));
+        if (slots > 0) PM_HIP(hipMemcpyAsync(c, csr->cols, sizeof(int32_t) * slots, hipMemcpyHostToDevice, s));
+        off_in = o;
+        col_in = c;
+    }
+
+    pm_graph *g = new (std::nothrow) pm_graph();
+    if (!g) return PM_ENOMEM;
+    struct Guard {
+        pm_graph *g;
+        hipStream_t s;
+        ~Guard()
+        {
+            if (g) graph_free(g, s);
+        }
+    } guard{g, s};
+    PM_HIP(hipGetDevice(&g->device));
+    g->n = n;
+    g->slots = slots;
+
+    PrepStats *st = nullptr;
+    PM_TRY(tmp.get(&st, 1));
+    PM_TRY(fill_async<uint32_t>((uint32_t *)st, 0u, sizeof(PrepStats) / 4, s));
+    PrepStats hst;
+
+    const int64_t nn = std::max<int64_t>(n, 1), ss = std::max<int64_t>(slots, 1);
+    uint32_t *deg_in = nullptr, *head = nullptr;
+    PM_TRY(tmp.get(&deg_in, nn));
+    PM_TRY(tmp.get(&head, ss));
+    PM_TRY(fill_async<uint32_t>(head, 0u, slots, s));
+    if (n > 0) {
+        ProfScope prof("degrees", s);
+        hipLaunchKernelGGL(k_degrees, dim3(grid_stream(n)), dim3(kBlock), 0, s, off_in, n, slots, deg_in, head, st);
+        PM_HIP(hipGetLastError());
+    }
+    PM_HIP(hipMemcpyAsync(&hst, st, sizeof(hst), hipMemcpyDeviceToHost, s));
+    PM_HIP(hipStreamSynchronize(s));
+    if (hst.err) {
+        set_error(err_text(hst.err));
+        return PM_EGRAPH;
+    }
+    g->dmax = hst.dmax;
+
+    // row of every input slot, then the slot checks
+    uint32_t *src_in = nullptr;
+    PM_TRY(tmp.get(&src_in, ss));
+    {
+        char *scr = nullptr;
+        PM_TRY(tmp.get(&scr, ScanScratch<uint32_t>::bytes_for(slots, 16)));
+        ProfScope prof("row_scan", s);
+        PM_TRY((scan_launch<uint32_t, 16>(HeadIn{head}, StoreOut32{src_in}, slots, MaxOp<uint32_t>(), 0u, scr, s)));
+    }
+    tmp.release(head);
+    if (slots > 0) {
+        ProfScope prof("check_slots", s);
+        hipLaunchKernelGGL(k_check_slots, dim3(grid_stream(slots)), dim3(kBlock), 0, s, col_in, src_in, slots, n,
+                           st);
+        PM_HIP(hipGetLastError());
+    }
+    PM_HIP(hipMemcpyAsync(&hst, st, sizeof(hst), hipMemcpyDeviceToHost, s));
+    PM_HIP(hipStreamSynchronize(s));
+    if (hst.err) {
+        set_error(err_text(hst.err));
+        return PM_EGRAPH;
+    }
+
+    // vertex order: stable sort of ids by degree
+    char *rscr = nullptr;
+    PM_TRY(tmp.get(&rscr, radix_scratch_bytes(std::max<int64_t>(slots, n))));
+    uint32_t *vk0, *vv0, *vk1, *vv1;
+    PM_TRY(tmp.get(&vk0, nn));
+    PM_TRY(tmp.get(&vv0, nn));
+    PM_TRY(tmp.get(&vk1, nn));
+    PM_TRY(tmp.get(&vv1, nn));
+    if (n > 0) {
+        hipLaunchKernelGGL(k_copy_u32, dim3(grid_stream(n)), dim3(kBlock), 0, s, deg_in, vk0, n);
+        hipLaunchKernelGGL(k_iota, dim3(grid_stream(n)), dim3(kBlock), 0, s, vv0, n);
+        PM_HIP(hipGetLastError());
+    }
+    uint32_t *sorted_deg, *order;
+    PM_TRY(radix_sort(vk0, vv0, vk1, vv1, n, bits_for((uint64_t)g->dmax), rscr, s, &sorted_deg, &order));
+
+    PM_TRY(dev_alloc((void **)&g->rank, sizeof(int32_t) * nn, s));
+    PM_TRY(dev_alloc((void **)&g->deg, sizeof(uint32_t) * nn, s));
+    PM_TRY(dev_alloc((void **)&g->off, sizeof(int64_t) * (n + 1), s));
+    g->bytes += sizeof(int32_t) * nn + sizeof(uint32_t) * nn + sizeof(int64_t) * (n + 1);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_rank_from_order, dim3(grid_stream(n)), dim3(kBlock), 0, s, order, g->rank, n);
+        hipLaunchKernelGGL(k_copy_u32, dim3(grid_stream(n)), dim3(kBlock), 0, s, sorted_deg, g->deg, n);
+        PM_HIP(hipGetLastError());
+    }
+    PM_TRY(fill_async<int64_t>(g->off, 0, 1, s));
+    {
+        char *scr = nullptr;
+        PM_TRY(tmp.get(&scr, ScanScratch<uint64_t>::bytes_for(n, 16)));
+        PM_TRY((scan_launch<uint64_t, 16>(DegIn{g->deg}, OffOut{g->off}, n, SumOp<uint64_t>(), 0ull, scr, s)));
+    }
+    tmp.release(vk0);
+    tmp.release(vv0);
+    tmp.release(vk1);
+    tmp.release(vv1);
+
+    const int vbits = bits_for(n > 0 ? (uint64_t)(n - 1) : 0);
+    uint32_t *ka, *va, *kb, *vb;
+    PM_TRY(tmp.get(&ka, ss));
+    PM_TRY(tmp.get(&va, ss));
+    PM_TRY(tmp.get(&kb, ss));
+    PM_TRY(tmp.get(&vb, ss));
+    if (slots > 0) {
+        ProfScope prof("place_rows", s);
+        hipLaunchKernelGGL(k_place_rows, dim3(grid_stream(slots)), dim3(kBlock), 0, s, off_in, col_in, src_in,
+                           g->rank, g->off, slots, ka, va);
+        PM_HIP(hipGetLastError());
+    }
+    tmp.release(src_in);
+    uint32_t *src_fin, *col_fin;
+    PM_TRY(radix_sort(ka, va, kb, vb, slots, vbits, rscr, s, &src_fin, &col_fin));
+    g->src = src_fin;
+    g->col = col_fin;
+    tmp.keep(src_fin);
+    tmp.keep(col_fin);
+    g->bytes += 2 * sizeof(uint32_t) * ss;
+    uint32_t *fa = (src_fin == ka) ? kb : ka;  // the two buffers the sort left free
+    uint32_t *fb = (col_fin == va) ? vb : va;
+
+    // reverse slots and the symmetry check
+    uint32_t *k2a, *v2a;
+    PM_TRY(tmp.get(&k2a, ss));
+    PM_TRY(tmp.get(&v2a, ss));
+    if (slots > 0) {
+        hipLaunchKernelGGL(k_copy_u32, dim3(grid_stream(slots)), dim3(kBlock), 0, s, g->col, k2a, slots);
+        hipLaunchKernelGGL(k_iota, dim3(grid_stream(slots)), dim3(kBlock), 0, s, v2a, slots);
+        PM_HIP(hipGetLastError());
+    }
+    uint32_t *key2, *rev;
+    PM_TRY(radix_sort(k2a, v2a, fa, fb, slots, vbits, rscr, s, &key2, &rev));
+    if (slots > 0) {
+        ProfScope prof("check_symmetry", s);
+        hipLaunchKernelGGL(k_check_symmetry, dim3(grid_stream(slots)), dim3(kBlock), 0, s, key2, rev, g->src,
+                           g->col, slots, st);
+        PM_HIP(hipGetLastError());
+    }
+    PM_HIP(hipMemcpyAsync(&hst, st, sizeof(hst), hipMemcpyDeviceToHost, s));
+    PM_HIP(hipStreamSynchronize(s));
+    if (hst.err) {
+        set_error(err_text(hst.err));
+        return PM_EGRAPH;
+    }
+    tmp.release(key2);
+
+    // weights and their prefixes
+    PM_TRY(dev_alloc((void **)&g->p_tau, sizeof(uint64_t) * ss, s));
+    PM_TRY(dev_alloc((void **)&g->p_lam, sizeof(uint64_t) * ss, s));
+    g->bytes += 2 * sizeof(uint64_t) * ss;
+    {
+        char *scr = nullptr;
+        PM_TRY(tmp.get(&scr, ScanScratch<uint64_t>::bytes_for(slots, 16)));
+        {
+            ProfScope prof("tau_scan", s);
+            PM_TRY((scan_launch<uint64_t, 16>(TauIn{g->src, g->col, g->deg}, PrefixOut{g->p_tau, st, ERR_OVF_TAU},
+                                              slots, SumOp<uint64_t>(), 0ull, scr, s)));
+        }
+        char *scr2 = nullptr;
+        PM_TRY(tmp.get(&scr2, ScanScratch<uint64_t>::bytes_for(slots, 16)));
+        ProfScope prof("lambda_scan", s);
+        PM_TRY((scan_launch<uint64_t, 16>(LamIn{g->src, g->col, g->deg, rev, g->off},
+                                          PrefixOut{g->p_lam, st, ERR_OVF_LAM}, slots, SumOp<uint64_t>(), 0ull,
+                                          scr2, s)));
+    }
+    if (n > 0) {
+        hipLaunchKernelGGL(k_n1, dim3(grid_stream(n)), dim3(kBlock), 0, s, g->deg, n, st);
+        PM_HIP(hipGetLastError());
+    }
+    uint64_t R[2] = {0, 0};
+    if (slots > 0) {
+        PM_HIP(hipMemcpyAsync(&R[0], g->p_tau + slots - 1, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        PM_HIP(hipMemcpyAsync(&R[1], g->p_lam + slots - 1, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    }
+    PM_HIP(hipMemcpyAsync(&hst, st, sizeof(hst), hipMemcpyDeviceToHost, s));
+    PM_HIP(hipStreamSynchronize(s));
+    if (hst.err & (ERR_OVF_TAU | ERR_OVF_LAM)) {
+        set_error(hst.err & ERR_OVF_TAU ? "2W does not fit in 64 bits" : "2 Lambda does not fit in 64 bits");
+        return PM_EOVERFLOW;
+    }
+    if (hst.n1_hi != 0) {
+        set_error("N1 does not fit in 64 bits");
+        return PM_EOVERFLOW;
+    }
+    g->R_tau = R[0];
+    g->R_lam = R[1];
+    g->N1 = hst.n1_lo;
+    g->isolated = (int64_t)hst.isolated;
+
+    // guide tables of the edge draws
+    uint32_t *nlong = &st->nlong_tau;
+    PM_TRY(build_guide(g->p_tau, slots, g->R_tau, tmp, st, nlong, &g->guide_tau, &g->shift_tau, &g->nb_tau,
+                       &g->bytes, s));
+    nlong = &st->nlong_lam;
+    PM_TRY(build_guide(g->p_lam, slots, g->R_lam, tmp, st, nlong, &g->guide_lam, &g->shift_lam, &g->nb_lam,
+                       &g->bytes, s));
+    PM_HIP(hipStreamSynchronize(s));
+    guard.g = nullptr;
+    *out = g;
+    return PM_OK;
+}
+
+pm_status graph_export(const pm_graph *g, int64_t *off, int32_t *col, int32_t *rank, uint64_t *p_tau,
+                       uint64_t *p_lam, hipStream_t s)
+{
+    if (!g) {
+        set_error("null graph");
+        return PM_EINVAL;
+    }
+    if (off) PM_HIP(hipMemcpyAsync(off, g->off, sizeof(int64_t) * (g->n + 1), hipMemcpyDeviceToHost, s));
+    if (g->slots > 0) {
+        if (col) PM_HIP(hipMemcpyAsync(col, g->col, sizeof(int32_t) * g->slots, hipMemcpyDeviceToHost, s));
+        if (p_tau) PM_HIP(hipMemcpyAsync(p_tau, g->p_tau, sizeof(uint64_t) * g->slots, hipMemcpyDeviceToHost, s));
+        if (p_lam) PM_HIP(hipMemcpyAsync(p_lam, g->p_lam, sizeof(uint64_t) * g->slots, hipMemcpyDeviceToHost, s));
+    }
+    if (rank && g->n > 0) PM_HIP(hipMemcpyAsync(rank, g->rank, sizeof(int32_t) * g->n, hipMemcpyDeviceToHost, s));
+    PM_HIP(hipStreamSynchronize(s));
+    return PM_OK;
+}
+
+}  // namespace pm
+
+namespace pm {
+
+pm_status graph_info(const pm_graph *g, pm_graph_info *out)
+{
+    if (!g || !out) {
+        set_error("null argument");
+        return PM_EINVAL;
+    }
+    out->n = g->n;
+    out->m = g->slots / 2;
+    out->dmax = g->dmax;
+    out->isolated = g->isolated;
+    out->W = g->R_tau / 2;
+    out->Lambda = g->R_lam / 2;
+    out->N1 = g->N1;
+    out->device_bytes = g->bytes;
+    return PM_OK;
+}
+
+}  // namespace pm

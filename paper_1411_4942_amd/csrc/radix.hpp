@@ -1,0 +1,217 @@
+// Stable LSD radix sort of (uint32 key, uint32 value) pairs, 8-bit digits.
+//
+// One pass = three launches: per-tile digit histograms (digit-major layout),
+// an exclusive scan of those counts (the single-pass scan), and a stable
+// scatter.  The scatter ranks each tile's 4096 elements in input order with
+// wave ballots (8 ballots give every lane the mask of lanes holding the same
+// digit), per-wave digit counts in LDS and a running per-digit base, stages
+// the tile digit-sorted in LDS, then writes each digit run contiguously.
+#pragma once
+
+#include "profile.hpp"
+#include "scan.hpp"
+
+namespace pm {
+
+constexpr int kRadixItems = 16;
+constexpr int kRadixTile = kBlock * kRadixItems;  // 4096
+constexpr int kRadixBins = 256;
+
+__global__ __launch_bounds__(kBlock) void radix_histogram(const uint32_t *__restrict__ keys, int64_t N, int shift,
+                                                          uint32_t mask, uint32_t *__restrict__ counts,
+                                                          int64_t tiles)
+{
+    __shared__ uint32_t hist[kRadixBins];
+    hist[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+#pragma unroll
+    for (int i = 0; i < kRadixItems; ++i) {
+        int64_t idx = base + (int64_t)i * kBlock + threadIdx.x;
+        if (idx < N) atomicAdd(&hist[(keys[idx] >> shift) & mask], 1u);
+    }
+    __syncthreads();
+    counts[(int64_t)threadIdx.x * tiles + blockIdx.x] = hist[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kBlock) void radix_scatter(const uint32_t *__restrict__ keys_in,
+                                                        const uint32_t *__restrict__ vals_in, int64_t N, int shift,
+                                                        uint32_t mask, const uint32_t *__restrict__ offsets,
+                                                        int64_t tiles, uint32_t *__restrict__ keys_out,
+                                                        uint32_t *__restrict__ vals_out)
+{
+    __shared__ uint32_t s_key[kRadixTile];
+    __shared__ uint32_t s_val[kRadixTile];
+    __shared__ uint32_t s_wcnt[kBlock / kWave][kRadixBins];
+    __shared__ uint32_t s_run[kRadixBins];     // elements of each digit ranked so far
+    __shared__ uint32_t s_start[kRadixBins];   // first LDS slot of each digit in the tile
+    __shared__ uint32_t s_goff[kRadixBins];    // first output position of each digit
+    __shared__ uint32_t s_wsum[kBlock / kWave];
+
+    const int t = threadIdx.x;
+    const int w = t / kWave;
+    const int lane = lane_id();
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+
+    for (int i = 0; i < kBlock / kWave; ++i) s_wcnt[i][t] = 0;
+    s_run[t] = 0;
+    s_goff[t] = offsets[(int64_t)t * tiles + blockIdx.x];
+
+    uint32_t key[kRadixItems], val[kRadixItems], dig[kRadixItems], rank[kRadixItems];
+#pragma unroll
+    for (int i = 0; i < kRadixItems; ++i) {
+        int64_t idx = base + (int64_t)i * kBlock + t;
+        bool ok = idx < N;
+        key[i] = ok ? keys_in[idx] : 0u;
+        val[i] = ok ? vals_in[idx] : 0u;
+        dig[i] = (key[i] >> shift) & mask;
+    }
+    __syncthreads();
+
+    // stable rank within the tile: element order is (i, thread)
+#pragma unroll
+    for (int i = 0; i < kRadixItems; ++i) {
+        int64_t idx = base + (int64_t)i * kBlock + t;
+        bool ok = idx < N;
+        uint64_t peers = __ballot(ok);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            uint64_t bal = __ballot((dig[i] >> b) & 1u);
+            peers &= ((dig[i] >> b) & 1u) ? bal : ~bal;
+        }
+        uint32_t r_in_wave = __popcll(peers & lt_mask);
+        if (ok && r_in_wave == 0) s_wcnt[w][dig[i]] = __popcll(peers);
+        __syncthreads();
+        if (ok) {
+            uint32_t r = s_run[dig[i]] + r_in_wave;
+            for (int ww = 0; ww < w; ++ww) r += s_wcnt[ww][dig[i]];
+            rank[i] = r;
+        }
+        __syncthreads();
+        {
+            uint32_t add = 0;
+            for (int ww = 0; ww < kBlock / kWave; ++ww) {
+                add += s_wcnt[ww][t];
+                s_wcnt[ww][t] = 0;
+            }
+            s_run[t] += add;
+        }
+        __syncthreads();
+    }
+
+    // exclusive scan of the tile's digit counts (s_run now holds the counts)
+    {
+        uint32_t c = s_run[t];
+        uint32_t incl = c;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            uint32_t o = __shfl_up(incl, d, kWave);
+            if (lane >= d) incl += o;
+        }
+        if (lane == kWave - 1) s_wsum[w] = incl;
+        __syncthreads();
+        uint32_t pre = 0;
+        for (int ww = 0; ww < w; ++ww) pre += s_wsum[ww];
+        s_start[t] = pre + incl - c;
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int i = 0; i < kRadixItems; ++i) {
+        int64_t idx = base + (int64_t)i * kBlock + t;
+        if (idx < N) {
+            uint32_t pos = s_start[dig[i]] + rank[i];
+            s_key[pos] = key[i];
+            s_val[pos] = val[i];
+        }
+    }
+    __syncthreads();
+
+    const int64_t tile_n = (N - base) < kRadixTile ? (N - base) : kRadixTile;
+#pragma unroll
+    for (int i = 0; i < kRadixItems; ++i) {
+        int p = i * kBlock + t;
+        if (p < tile_n) {
+            uint32_t k = s_key[p];
+            uint32_t d = (k >> shift) & mask;
+            uint32_t dst = s_goff[d] + (uint32_t)(p - s_start[d]);
+            keys_out[dst] = k;
+            vals_out[dst] = s_val[p];
+        }
+    }
+}
+
+struct CountIn {
+    const uint32_t *c;
+    __device__ __forceinline__ uint32_t operator()(int64_t i) const { return c[i]; }
+};
+
+struct ExclusiveOut {
+    uint32_t *o;
+    __device__ __forceinline__ void operator()(int64_t i, uint32_t incl, uint32_t x) const { o[i] = incl - x; }
+};
+
+inline int bits_for(uint64_t max_key)
+{
+    int b = 0;
+    while (b < 64 && (max_key >> b) != 0) ++b;
+    return b;
+}
+
+// Device scratch needed by radix_sort for N elements.
+inline size_t radix_scratch_bytes(int64_t N)
+{
+    int64_t tiles = (N + kRadixTile - 1) / kRadixTile;
+    if (tiles < 1) tiles = 1;
+    int64_t cnt = tiles * kRadixBins;
+    return (size_t)cnt * 2 * sizeof(uint32_t) + ScanScratch<uint32_t>::bytes_for(cnt, 8) + 1024;
+}
+
+// Sort (keys, vals) by the low `bits` bits of the keys, stably.  Ping-pongs
+// between (k0, v0) and (k1, v1); on return *out_k / *out_v point at the
+// buffers holding the result.  N < 2^32.
+inline pm_status radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t N, int bits,
+                            void *scratch, hipStream_t s, uint32_t **out_k, uint32_t **out_v)
+{
+    *out_k = k0;
+    *out_v = v0;
+    if (N <= 1 || bits <= 0) return PM_OK;
+    const int64_t tiles = (N + kRadixTile - 1) / kRadixTile;
+    const int64_t cnt = tiles * kRadixBins;
+    uint32_t *counts = (uint32_t *)scratch;
+    uint32_t *offs = counts + cnt;
+    void *scan_scr = (void *)(((uintptr_t)(offs + cnt) + 255) & ~(uintptr_t)255);
+    uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
+    for (int shift = 0; shift < bits; shift += 8) {
+        int nb = bits - shift < 8 ? bits - shift : 8;
+        uint32_t mask = (1u << nb) - 1u;
+        {
+            ProfScope prof("radix_histogram", s);
+            hipLaunchKernelGGL(radix_histogram, dim3((unsigned)tiles), dim3(kBlock), 0, s, ki, N, shift, mask, counts,
+                               tiles);
+            PM_HIP(hipGetLastError());
+        }
+        {
+            ProfScope prof("radix_count_scan", s);
+            PM_TRY((scan_launch<uint32_t, 8>(CountIn{counts}, ExclusiveOut{offs}, cnt, SumOp<uint32_t>(), 0u,
+                                             scan_scr, s)));
+        }
+        {
+            ProfScope prof("radix_scatter", s);
+            hipLaunchKernelGGL(radix_scatter, dim3((unsigned)tiles), dim3(kBlock), 0, s, ki, vi, N, shift, mask,
+                               offs, tiles, ko, vo);
+            PM_HIP(hipGetLastError());
+        }
+        uint32_t *tk = ki, *tv = vi;
+        ki = ko;
+        vi = vo;
+        ko = tk;
+        vo = tv;
+    }
+    *out_k = ki;
+    *out_v = vi;
+    return PM_OK;
+}
+
+}  // namespace pm

@@ -1,0 +1,262 @@
+"""ctypes binding of libpathsamp.so (the C ABI of include/pathsamp.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+Device buffers are torch tensors (``data_ptr()``), streams are torch streams
+(``cuda_stream``); host buffers are numpy arrays.  There is no fallback: if the
+library cannot be loaded, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpathsamp.so")
+
+PM_OK, PM_EINVAL, PM_EGRAPH, PM_EOVERFLOW, PM_ENOMEM, PM_EDEVICE, PM_EBUSY, PM_ECANCELED = 0, -1, -2, -3, -4, -5, -6, -7
+PM_VALIDATE, PM_CHECK_SYMMETRY = 1, 2
+NUM_TALLIES = 8
+
+
+class PathSampError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: status {status}: {message}")
+        self.status = status
+
+
+class CsrView(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("row_offsets", ctypes.c_void_p), ("cols", ctypes.c_void_p),
+                ("on_device", ctypes.c_int32)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("k_path", ctypes.c_uint64), ("k_cent", ctypes.c_uint64), ("seed", ctypes.c_uint64),
+                ("first_id_path", ctypes.c_uint64), ("first_id_cent", ctypes.c_uint64), ("delta", ctypes.c_double)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("tally_path", ctypes.c_uint64 * NUM_TALLIES), ("tally_cent", ctypes.c_uint64 * NUM_TALLIES),
+                ("W", ctypes.c_uint64), ("Lambda", ctypes.c_uint64), ("N1", ctypes.c_uint64),
+                ("k_path", ctypes.c_uint64), ("k_cent", ctypes.c_uint64),
+                ("est", ctypes.c_double * 7), ("lo", ctypes.c_double * 7), ("hi", ctypes.c_double * 7),
+                ("est_basic", ctypes.c_double * 7)]
+
+    def to_dict(self) -> dict:
+        return {
+            "tally_path": [int(x) for x in self.tally_path],
+            "tally_cent": [int(x) for x in self.tally_cent],
+            "W": int(self.W), "Lambda": int(self.Lambda), "N1": int(self.N1),
+            "k_path": int(self.k_path), "k_cent": int(self.k_cent),
+            "est": list(self.est), "lo": list(self.lo), "hi": list(self.hi), "est_basic": list(self.est_basic),
+        }
+
+
+class ProfileEntry(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double)]
+
+
+class GraphInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("dmax", ctypes.c_int64), ("isolated", ctypes.c_int64),
+                ("W", ctypes.c_uint64), ("Lambda", ctypes.c_uint64), ("N1", ctypes.c_uint64),
+                ("device_bytes", ctypes.c_uint64)]
+
+
+_lib = None
+
+# name -> (restype, argtypes); kept in step with include/pathsamp.h
+_P = ctypes.c_void_p
+_SIGNATURES = {
+    "pm_count_motifs": (ctypes.c_int32, [ctypes.POINTER(CsrView), ctypes.c_uint64, ctypes.c_uint64,
+                                         ctypes.POINTER(Result)]),
+    "pm_graph_create": (ctypes.c_int32, [ctypes.POINTER(CsrView), ctypes.c_uint32, _P, ctypes.POINTER(_P)]),
+    "pm_graph_info_get": (ctypes.c_int32, [_P, ctypes.POINTER(GraphInfo)]),
+    "pm_graph_export": (ctypes.c_int32, [_P, _P, _P, _P, _P, _P, _P]),
+    "pm_graph_destroy": (ctypes.c_int32, [_P]),
+    "pm_count": (ctypes.c_int32, [_P, ctypes.POINTER(Params), ctypes.POINTER(Result), _P]),
+    "pm_sample_async": (ctypes.c_int32, [_P, ctypes.POINTER(Params), _P, _P]),
+    "pm_finalize": (ctypes.c_int32, [_P, _P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                     ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(Result)]),
+    "pm_chernoff_interval": (ctypes.c_int32, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double,
+                                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "pm_samples_for_error": (ctypes.c_int32, [ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                              ctypes.POINTER(ctypes.c_uint64)]),
+    "pm_philox_device": (ctypes.c_int32, [_P, _P, ctypes.c_int64]),
+    "pm_profile_enable": (ctypes.c_int32, [ctypes.c_int32]),
+    "pm_profile_read": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "pm_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
+    "pm_last_error": (ctypes.c_char_p, []),
+}
+
+
+def lib():
+    """Load libpathsamp.so (building it first only if it does not exist)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        from . import build as _build
+
+        _build.build()
+    handle = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(handle, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = handle
+    return handle
+
+
+def _check(status: int, where: str):
+    if status != PM_OK:
+        msg = lib().pm_last_error().decode(errors="replace")
+        raise PathSampError(status, where, msg)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _csr_view(off, col):
+    """CsrView over torch CUDA tensors or host numpy arrays; returns the
+    view and the objects that keep the memory alive."""
+    try:
+        import torch
+    except ImportError:  # pragma: no cover
+        torch = None
+    if torch is not None and isinstance(off, torch.Tensor):
+        if off.dtype != torch.int64 or col.dtype != torch.int32:
+            raise TypeError("row_offsets must be int64 and cols int32")
+        if not (off.is_cuda and col.is_cuda):
+            off_np = off.cpu().numpy()
+            col_np = col.cpu().numpy()
+            return _csr_view(off_np, col_np)
+        off = off.contiguous()
+        col = col.contiguous()
+        v = CsrView(off.numel() - 1, off.data_ptr(), col.data_ptr() if col.numel() else None, 1)
+        return v, (off, col)
+    off = np.ascontiguousarray(off, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    v = CsrView(off.size - 1, off.ctypes.data, col.ctypes.data if col.size else None, 0)
+    return v, (off, col)
+
+
+class Graph:
+    """A prepared graph resident on the current device (pm_graph handle)."""
+
+    def __init__(self, off, col, flags: int = PM_VALIDATE | PM_CHECK_SYMMETRY, stream=None):
+        L = lib()
+        view, self._keep = _csr_view(off, col)
+        h = ctypes.c_void_p()
+        _check(L.pm_graph_create(ctypes.byref(view), flags, _stream_ptr(stream), ctypes.byref(h)),
+               "pm_graph_create")
+        self._keep = None
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        gi = GraphInfo()
+        _check(lib().pm_graph_info_get(self._h, ctypes.byref(gi)), "pm_graph_info_get")
+        return {f: int(getattr(gi, f)) for f, _ in GraphInfo._fields_}
+
+    def export(self, stream=None) -> dict:
+        gi = self.info()
+        n, slots = gi["n"], 2 * gi["m"]
+        off = np.zeros(n + 1, np.int64)
+        col = np.zeros(max(slots, 1), np.int32)
+        rank = np.zeros(max(n, 1), np.int32)
+        pt = np.zeros(max(slots, 1), np.uint64)
+        pl = np.zeros(max(slots, 1), np.uint64)
+        _check(lib().pm_graph_export(self._h, off.ctypes.data, col.ctypes.data, rank.ctypes.data, pt.ctypes.data,
+                                     pl.ctypes.data, _stream_ptr(stream)), "pm_graph_export")
+        return {"off": off, "col": col[:slots], "rank": rank[:n], "p_tau": pt[:slots], "p_lam": pl[:slots]}
+
+    def count(self, k_path: int, k_cent: int | None = None, seed: int = 1, first_path: int = 0,
+              first_cent: int = 0, delta: float = 0.01, stream=None) -> dict:
+        p = Params(k_path, k_path if k_cent is None else k_cent, seed, first_path, first_cent, delta)
+        r = Result()
+        _check(lib().pm_count(self._h, ctypes.byref(p), ctypes.byref(r), _stream_ptr(stream)), "pm_count")
+        return r.to_dict()
+
+    def sample_async(self, tallies, k_path: int, k_cent: int, seed: int, first_path: int = 0, first_cent: int = 0,
+                     stream=None):
+        """Enqueue both samplers; tallies is a CUDA uint64/int64 tensor of 16."""
+        if tallies.numel() < 2 * NUM_TALLIES or not tallies.is_cuda:
+            raise ValueError("tallies must be a CUDA tensor of at least 16 64-bit integers")
+        p = Params(k_path, k_cent, seed, first_path, first_cent, 0.01)
+        _check(lib().pm_sample_async(self._h, ctypes.byref(p), ctypes.c_void_p(tallies.data_ptr()),
+                                     _stream_ptr(stream)), "pm_sample_async")
+
+    def destroy(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _check(lib().pm_graph_destroy(self._h), "pm_graph_destroy")
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def count_motifs(off, col, k: int, seed: int = 1) -> dict:
+    """pm_count_motifs: prepare, sample k + k, finalize (99% bars)."""
+    view, keep = _csr_view(off, col)
+    r = Result()
+    _check(lib().pm_count_motifs(ctypes.byref(view), k, seed, ctypes.byref(r)), "pm_count_motifs")
+    del keep
+    return r.to_dict()
+
+
+def finalize(tally_path, tally_cent, W: int, Lambda: int, N1: int, k_path: int, k_cent: int,
+             delta: float = 0.01) -> dict:
+    tp = np.ascontiguousarray(tally_path, dtype=np.uint64)
+    tc = np.ascontiguousarray(tally_cent, dtype=np.uint64)
+    r = Result()
+    _check(lib().pm_finalize(tp.ctypes.data, tc.ctypes.data, W, Lambda, N1, k_path, k_cent, delta, ctypes.byref(r)),
+           "pm_finalize")
+    return r.to_dict()
+
+
+def chernoff_interval(count: int, k: int, delta: float):
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    _check(lib().pm_chernoff_interval(count, k, delta, ctypes.byref(lo), ctypes.byref(hi)), "pm_chernoff_interval")
+    return lo.value, hi.value
+
+
+def samples_for_error(rel_err: float, delta: float, alpha: float) -> int:
+    k = ctypes.c_uint64()
+    _check(lib().pm_samples_for_error(rel_err, delta, alpha, ctypes.byref(k)), "pm_samples_for_error")
+    return int(k.value)
+
+
+def philox_device(inputs) -> np.ndarray:
+    """Device Philox4x32-10 on rows (c0 c1 c2 c3 k0 k1); returns rows of 4 words."""
+    a = np.ascontiguousarray(inputs, dtype=np.uint32).reshape(-1, 6)
+    out = np.zeros((a.shape[0], 4), np.uint32)
+    _check(lib().pm_philox_device(a.ctypes.data, out.ctypes.data, a.shape[0]), "pm_philox_device")
+    return out
+
+
+def profile_enable(on: bool = True):
+    """Clear per-kernel totals and switch HIP-event timing on or off."""
+    _check(lib().pm_profile_enable(1 if on else 0), "pm_profile_enable")
+
+
+def profile_read() -> dict:
+    """{kernel name: (launches, total ms)} since the last profile_enable."""
+    cnt = ctypes.c_int32()
+    _check(lib().pm_profile_read(None, 0, ctypes.byref(cnt)), "pm_profile_read")
+    arr = (ProfileEntry * max(cnt.value, 1))()
+    _check(lib().pm_profile_read(ctypes.cast(arr, ctypes.c_void_p), cnt.value, ctypes.byref(cnt)), "pm_profile_read")
+    return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(cnt.value)}

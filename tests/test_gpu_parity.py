@@ -1,0 +1,240 @@
+"""GPU parity: the HIP path against the oracle, element by element.
+
+Prepared arrays (relabelled CSR, rank, tau/lambda prefixes, W, Lambda, N_1)
+and per-pattern sample tallies must be bit-exact; estimates within 1e-12
+relative, bars within 1e-9 (both computed on the host from identical
+integers).  Inputs are seeded synthetic graphs; every case prints its name
+before touching the GPU.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import finalize as ofin
+from paper_1411_4942_amd import pathsamp as ps
+from paper_1411_4942_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def _dev(off, col):
+    return (torch.from_numpy(np.ascontiguousarray(off, np.int64)).cuda(),
+            torch.from_numpy(np.ascontiguousarray(col, np.int32)).cuda())
+
+
+def _graphs():
+    gs = [
+        ("K6", synth.complete(6)),
+        ("K12", synth.complete(12)),
+        ("C9", synth.cycle(9)),
+        ("C4", synth.cycle(4)),
+        ("star7", synth.star(7)),
+        ("K3,3", synth.complete_bipartite(3, 3)),
+        ("K2,40", synth.complete_bipartite(2, 40)),
+        ("P8", synth.path(8)),
+        ("matching", synth.csr_from_edges(12, [0, 2, 4, 6], [1, 3, 5, 7])),
+        ("empty5", synth.empty(5)),
+        ("single_vertex", synth.empty(1)),
+    ]
+    for seed in range(40):
+        rng = np.random.default_rng(seed)
+        n = int(rng.integers(5, 40))
+        m = int(rng.integers(n - 1, min(n * (n - 1) // 2, 4 * n) + 1))
+        gs.append((f"gnm{seed}", synth.erdos_renyi(n, m, seed)))
+    gs.append(("chunglu_3k", synth.chung_lu(3000, 20000, 2.2, 300.0, 3)))
+    gs.append(("rmat_s12", synth.rmat(12, 16, seed=2)))
+    gs.append(("er_tiles", synth.erdos_renyi(9000, 70000, 4)))  # > several scan/radix tiles, ragged tail
+    return gs
+
+
+GRAPHS = _graphs()
+
+
+def _check_prep(name, off, col):
+    og = oracle.Graph(off, col)
+    g = ps.Graph(*_dev(off, col))
+    info = g.info()
+    ex = g.export()
+    assert info["n"] == og.n and 2 * info["m"] == og.slots, name
+    assert np.array_equal(ex["off"], og.off), name
+    assert np.array_equal(ex["col"], og.col), name
+    assert np.array_equal(ex["rank"], og.rank), name
+    assert np.array_equal(ex["p_tau"], og.p_tau), name
+    assert np.array_equal(ex["p_lam"], og.p_lam), name
+    assert info["W"] * 2 == og.R_tau and info["Lambda"] * 2 == og.R_lam and info["N1"] == og.N1, name
+    deg = np.diff(off)
+    assert info["dmax"] == (int(deg.max()) if deg.size else 0)
+    assert info["isolated"] == int((deg == 0).sum())
+    return og, g
+
+
+@pytest.mark.parametrize("name,graph", GRAPHS, ids=[g[0] for g in GRAPHS])
+def test_prep_and_tallies_bit_exact(name, graph):
+    _say("prep+tallies", name)
+    off, col = graph
+    og, g = _check_prep(name, off, col)
+    for seed, kp, kc, fp, fc in [(1, 20000, 20000, 0, 0), (0xDEADBEEFCAFEF00D, 777, 1234, 5, 2 ** 33 + 7)]:
+        got = g.count(kp, kc, seed=seed, first_path=fp, first_cent=fc)
+        assert got["tally_path"] == og.sample_path(seed, kp, fp).tolist(), (name, seed)
+        assert got["tally_cent"] == og.sample_centered(seed, kc, fc).tolist(), (name, seed)
+        want = ofin.finalize(got["tally_path"], got["tally_cent"], og.R_tau, og.R_lam, og.N1, kp, kc)
+        for i in range(1, 7):
+            assert got["est"][i] == pytest.approx(want["est"][i], rel=1e-12, abs=1e-9)
+            assert got["est_basic"][i] == pytest.approx(want["est_basic"][i], rel=1e-12, abs=1e-9)
+    g.destroy()
+
+
+def test_enumeration_exactness_on_device():
+    """With k = R (whole range of r realised by many ids) the sampled tallies
+    are multinomial, but the GPU and oracle still agree id by id."""
+    off, col = synth.complete(7)
+    og = oracle.Graph(off, col)
+    g = ps.Graph(*_dev(off, col))
+    got = g.count(100000, 100000, seed=3)
+    assert got["tally_path"][0] + got["tally_path"][6] == 100000
+    assert got["tally_path"] == og.sample_path(3, 100000).tolist()
+
+
+def test_config1_er_2000_20000():
+    """ER G(2000, 20000), k = 1e5 per sampler, Philox seed 1, in the launch
+    configuration the benchmark uses (pm_count)."""
+    _say("config1")
+    off, col = synth.erdos_renyi(2000, 20000, 1)
+    og, g = _check_prep("config1", off, col)
+    got = g.count(100_000, 100_000, seed=1)
+    tp = og.sample_path(1, 100_000).tolist()
+    tc = og.sample_centered(1, 100_000).tolist()
+    assert got["tally_path"] == tp and got["tally_cent"] == tc
+    want = ofin.finalize(tp, tc, og.R_tau, og.R_lam, og.N1, 100_000, 100_000)
+    for i in range(1, 7):
+        assert got["est"][i] == pytest.approx(want["est"][i], rel=1e-12, abs=1e-9)
+        for key in ("lo", "hi"):
+            assert got[key][i] == pytest.approx(want[key][i], rel=1e-9, abs=1e-6)
+    C, _ = oracle.exact_formula(off, col)
+    for i in (1, 2):
+        assert abs(got["est"][i] - C[i]) <= 0.01 * C[i]
+    for i in range(1, 7):
+        assert got["lo"][i] - 1e-6 <= C[i] <= got["hi"][i] + 1e-6
+
+
+def test_count_motifs_one_shot_host_and_device_inputs():
+    off, col = synth.erdos_renyi(2000, 20000, 1)
+    a = ps.count_motifs(off, col, k=50_000, seed=9)       # host buffers
+    b = ps.count_motifs(*_dev(off, col), k=50_000, seed=9)  # device buffers
+    assert a == b
+    og = oracle.Graph(off, col)
+    assert a["tally_path"] == og.sample_path(9, 50_000).tolist()
+    assert a["tally_cent"] == og.sample_centered(9, 50_000).tolist()
+
+
+def test_id_ranges_concatenate_on_device():
+    off, col = synth.chung_lu(5000, 40000, 2.3, 200.0, 11)
+    g = ps.Graph(*_dev(off, col))
+    full = g.count(300_000, 300_000, seed=5)
+    a = g.count(100_000, 50_000, seed=5)
+    b = g.count(200_000, 250_000, seed=5, first_path=100_000, first_cent=50_000)
+    assert full["tally_path"] == [x + y for x, y in zip(a["tally_path"], b["tally_path"])]
+    assert full["tally_cent"] == [x + y for x, y in zip(a["tally_cent"], b["tally_cent"])]
+
+
+def test_sample_async_into_tensor():
+    off, col = synth.erdos_renyi(500, 3000, 2)
+    og = oracle.Graph(off, col)
+    g = ps.Graph(*_dev(off, col))
+    t = torch.full((16,), 12345, dtype=torch.int64, device="cuda")
+    g.sample_async(t, 4000, 3000, seed=77)
+    torch.cuda.synchronize()
+    got = t.cpu().numpy().astype(np.uint64)
+    assert got[:8].tolist() == og.sample_path(77, 4000).tolist()
+    assert got[8:].tolist() == og.sample_centered(77, 3000).tolist()
+
+
+def test_philox_device_matches_oracle():
+    rng = np.random.default_rng(99)
+    rows = rng.integers(0, 2 ** 32, size=(512, 6), dtype=np.uint64).astype(np.uint32)
+    got = ps.philox_device(rows)
+    for r, o in zip(rows, got):
+        assert o.tolist() == oracle.philox4x32_10(r[:4], r[4:]).tolist()
+
+
+def _bad_graphs():
+    off, col = synth.complete(5)
+    out = []
+    c = col.copy()
+    c[0], c[1] = c[1], c[0]
+    out.append(("unsorted", off, c, ps.PM_EGRAPH))
+    c = col.copy()
+    c[1] = c[0]
+    out.append(("duplicate", off, c, ps.PM_EGRAPH))
+    c = col.copy()
+    c[0] = 0
+    out.append(("self_loop", off, c, ps.PM_EGRAPH))
+    c = col.copy()
+    c[-1] = 77
+    out.append(("out_of_range", off, c, ps.PM_EGRAPH))
+    c = col.copy()
+    c[-1] = -3
+    out.append(("negative", off, c, ps.PM_EGRAPH))
+    out.append(("asymmetric", np.array([0, 1, 2, 3], np.int64), np.array([1, 2, 1], np.int32), ps.PM_EGRAPH))
+    o = off.copy()
+    o[2] = o[3] + 1
+    out.append(("offsets_decrease", o, col, ps.PM_EGRAPH))
+    o = off.copy()
+    o[0] = 1
+    out.append(("offsets_not_zero", o, col, ps.PM_EGRAPH))
+    return out
+
+
+@pytest.mark.parametrize("name,off,col,status", _bad_graphs(), ids=[b[0] for b in _bad_graphs()])
+def test_invalid_graphs_are_rejected(name, off, col, status):
+    _say("invalid", name)
+    assert oracle.validate(off, col) != oracle.OK
+    with pytest.raises(ps.PathSampError) as e:
+        ps.Graph(*_dev(off, col))
+    assert e.value.status == status
+
+
+def test_argument_errors():
+    off, col = synth.complete(5)
+    g = ps.Graph(*_dev(off, col))
+    with pytest.raises(ps.PathSampError) as e:
+        g.count(0, 0)
+    assert e.value.status == ps.PM_EINVAL
+    with pytest.raises(ps.PathSampError) as e:
+        g.count(10, 10, delta=0.0)
+    assert e.value.status == ps.PM_EINVAL
+    with pytest.raises(ps.PathSampError) as e:
+        ps.count_motifs(off, col, k=0)
+    assert e.value.status == ps.PM_EINVAL
+
+
+def test_n1_overflow_is_reported():
+    leaves = 5_300_000
+    off, col = synth.star(leaves)
+    with pytest.raises(ps.PathSampError) as e:
+        ps.Graph(*_dev(off, col))
+    assert e.value.status == ps.PM_EOVERFLOW
+
+
+def test_zero_weight_samplers_are_exact_zero():
+    for name, (off, col) in [("star", synth.star(30)), ("matching", synth.csr_from_edges(6, [0, 2], [1, 3])),
+                             ("path", synth.path(30))]:
+        _say("zero-weight", name)
+        og = oracle.Graph(off, col)
+        r = ps.count_motifs(off, col, k=1000, seed=1)
+        C, _ = oracle.exact_formula(off, col)
+        if og.R_tau == 0:
+            assert r["tally_path"] == [0] * 8
+            assert r["est"][2:4] == [0.0, 0.0]
+            assert r["est"][1] == C[1]
+        if og.R_lam == 0:
+            assert r["tally_cent"] == [0] * 8
+            assert r["est"][4:] == [0.0, 0.0, 0.0]
