@@ -180,55 +180,54 @@ __global__ void k_copy_u32(const uint32_t *__restrict__ a, uint32_t *__restrict_
         b[i] = a[i];
 }
 
-// symmetric iff the slots sorted by (col, row) are the slots sorted by
-// (row, col) with the pair reversed
+// Symmetry, half 1: listing the slots by (col, row) must list the rows in
+// the order of the slots' own rows (in-degree = out-degree everywhere and
+// the reverse slot of q has column src[q]).  Half 2 (the reverse slot lies in
+// row col[q]) is checked inside WeightsIn, which loads that row's bounds.
 __global__ __launch_bounds__(kBlock) void k_check_symmetry(const uint32_t *__restrict__ key2,
-                                                           const uint32_t *__restrict__ perm,
-                                                           const uint32_t *__restrict__ src,
-                                                           const uint32_t *__restrict__ col, int64_t slots,
+                                                           const uint32_t *__restrict__ src, int64_t slots,
                                                            PrepStats *st)
 {
     bool bad = false;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < slots;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        if (key2[q] != src[q] || src[perm[q]] != col[q]) bad = true;
-    }
+         q += (int64_t)gridDim.x * blockDim.x)
+        bad |= key2[q] != src[q];
     if (bad) atomicOr(&st->err, (uint32_t)ERR_ASYM);
 }
 
-// Section 3: tau_s = (d_u - 1)(d_v - 1)
-struct TauIn {
-    const uint32_t *src, *col, *deg;
-    __device__ __forceinline__ uint64_t operator()(int64_t s) const
-    {
-        return (uint64_t)(deg[src[s]] - 1u) * (uint64_t)(deg[col[s]] - 1u);
-    }
-};
-
+// Section 3: tau_s = (d_u - 1)(d_v - 1).
 // Section 4: lambda_s = L_{u,v} L_{v,u}; L_{u,v} = d_u - 1 - (position of v in
-// row u), the neighbours of u after v; the reverse slot gives L_{v,u}
-struct LamIn {
+// row u) counts the neighbours of u after v; the reverse slot r gives L_{v,u}.
+// Both weights of a slot come out of one pass over (src, col, rev).
+struct WeightsIn {
     const uint32_t *src, *col, *deg, *rev;
     const int64_t *off;
-    __device__ __forceinline__ uint64_t operator()(int64_t s) const
+    PrepStats *st;
+    __device__ __forceinline__ U64x2 operator()(int64_t s) const
     {
-        uint32_t u = src[s], v = col[s];
-        int64_t r = rev[s];
-        uint64_t luv = (uint64_t)((int64_t)deg[u] - 1 - (s - off[u]));
-        uint64_t lvu = (uint64_t)((int64_t)deg[v] - 1 - (r - off[v]));
-        return luv * lvu;
+        const uint32_t u = src[s], v = col[s];
+        const int64_t r = rev[s];
+        const int64_t du = deg[u], dv = deg[v];
+        const int64_t ou = off[u], ov = off[v];
+        if (r < ov || r >= ov + dv) atomicOr(&st->err, (uint32_t)ERR_ASYM);
+        const uint64_t tau = (uint64_t)(du - 1) * (uint64_t)(dv - 1);
+        const uint64_t luv = (uint64_t)(du - 1 - (s - ou));
+        const uint64_t lvu = (uint64_t)(dv - 1 - (r - ov));
+        return U64x2{tau, luv * lvu};
     }
 };
 
-// inclusive prefix with wrap detection: incl < x happens iff the sum passed 2^64
-struct PrefixOut {
-    uint64_t *p;
+// inclusive prefixes with wrap detection: incl < x happens iff the running
+// sum passed 2^64
+struct WeightsOut {
+    uint64_t *p_tau, *p_lam;
     PrepStats *st;
-    uint32_t flag;
-    __device__ __forceinline__ void operator()(int64_t i, uint64_t incl, uint64_t x) const
+    __device__ __forceinline__ void operator()(int64_t i, U64x2 incl, U64x2 x) const
     {
-        p[i] = incl;
-        if (incl < x) atomicOr(&st->err, flag);
+        p_tau[i] = incl.a;
+        p_lam[i] = incl.b;
+        if (incl.a < x.a) atomicOr(&st->err, (uint32_t)ERR_OVF_TAU);
+        if (incl.b < x.b) atomicOr(&st->err, (uint32_t)ERR_OVF_LAM);
     }
 };
 
@@ -596,36 +595,23 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
     PM_TRY(radix_sort(k2a, v2a, fa, fb, slots, vbits, rscr, s, &key2, &rev));
     if (slots > 0) {
         ProfScope prof("check_symmetry", s);
-        hipLaunchKernelGGL(k_check_symmetry, dim3(grid_stream(slots)), dim3(kBlock), 0, s, key2, rev, g->src,
-                           g->col, slots, st);
+        hipLaunchKernelGGL(k_check_symmetry, dim3(grid_stream(slots)), dim3(kBlock), 0, s, key2, g->src, slots, st);
         PM_HIP(hipGetLastError());
-    }
-    PM_HIP(hipMemcpyAsync(&hst, st, sizeof(hst), hipMemcpyDeviceToHost, s));
-    PM_HIP(hipStreamSynchronize(s));
-    if (hst.err) {
-        set_error(err_text(hst.err));
-        return PM_EGRAPH;
     }
     tmp.release(key2);
 
-    // weights and their prefixes
+    // weights and their prefixes (nothing below indexes memory through them
+    // until the checks are read back)
     PM_TRY(dev_alloc((void **)&g->p_tau, sizeof(uint64_t) * ss, s));
     PM_TRY(dev_alloc((void **)&g->p_lam, sizeof(uint64_t) * ss, s));
     g->bytes += 2 * sizeof(uint64_t) * ss;
     {
         char *scr = nullptr;
-        PM_TRY(tmp.get(&scr, ScanScratch<uint64_t>::bytes_for(slots, 16)));
-        {
-            ProfScope prof("tau_scan", s);
-            PM_TRY((scan_launch<uint64_t, 16>(TauIn{g->src, g->col, g->deg}, PrefixOut{g->p_tau, st, ERR_OVF_TAU},
-                                              slots, SumOp<uint64_t>(), 0ull, scr, s)));
-        }
-        char *scr2 = nullptr;
-        PM_TRY(tmp.get(&scr2, ScanScratch<uint64_t>::bytes_for(slots, 16)));
-        ProfScope prof("lambda_scan", s);
-        PM_TRY((scan_launch<uint64_t, 16>(LamIn{g->src, g->col, g->deg, rev, g->off},
-                                          PrefixOut{g->p_lam, st, ERR_OVF_LAM}, slots, SumOp<uint64_t>(), 0ull,
-                                          scr2, s)));
+        PM_TRY(tmp.get(&scr, ScanScratch<U64x2>::bytes_for(slots, 16)));
+        ProfScope prof("weights_scan", s);
+        PM_TRY((scan_launch<U64x2, 16>(WeightsIn{g->src, g->col, g->deg, rev, g->off, st},
+                                       WeightsOut{g->p_tau, g->p_lam, st}, slots, PairSumOp(), U64x2{0, 0}, scr,
+                                       s)));
     }
     if (n > 0) {
         hipLaunchKernelGGL(k_n1, dim3(grid_stream(n)), dim3(kBlock), 0, s, g->deg, n, st);
@@ -638,6 +624,10 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
     }
     PM_HIP(hipMemcpyAsync(&hst, st, sizeof(hst), hipMemcpyDeviceToHost, s));
     PM_HIP(hipStreamSynchronize(s));
+    if (hst.err & ERR_ASYM) {
+        set_error(err_text(hst.err));
+        return PM_EGRAPH;
+    }
     if (hst.err & (ERR_OVF_TAU | ERR_OVF_LAM)) {
         set_error(hst.err & ERR_OVF_TAU ? "2W does not fit in 64 bits" : "2 Lambda does not fit in 64 bits");
         return PM_EOVERFLOW;
