@@ -166,6 +166,12 @@ pm_status pm_chernoff_interval(uint64_t count, uint64_t k, double delta, double 
  * k = ceil(ln(1/delta) / min(D(alpha, alpha(1+e)), D(alpha, alpha(1-e)))). */
 pm_status pm_samples_for_error(double rel_err, double delta, double alpha, uint64_t *k_out);
 
+/* Launch shape of the two sampling kernels for this process: samples each
+ * lane advances together (1, 2 or 4; more loads in flight per lane, more
+ * registers) and resident blocks per compute unit (1..64).  Tallies do not
+ * depend on the shape.  Default 2 and 8. */
+pm_status pm_set_sampler_shape(int32_t samples_per_lane, int32_t blocks_per_cu);
+
 /* ------------------------------------------------------------------------ */
 /* Diagnostics                                                               */
 /* ------------------------------------------------------------------------ */

@@ -30,6 +30,7 @@ pm_status philox_device(const uint32_t *in, uint32_t *out, int64_t count);
 pm_status dev_alloc(void **p, size_t bytes, hipStream_t s);
 void dev_free(void *p, hipStream_t s);
 pm_status count_on_graph(const pm_graph *g, const pm_params *p, pm_result *out, hipStream_t s);
+pm_status set_sampler_shape(int32_t samples_per_lane, int32_t blocks_per_cu);
 
 }  // namespace pm
 
@@ -148,6 +149,11 @@ pm_status pm_chernoff_interval(uint64_t count, uint64_t k, double delta, double 
 pm_status pm_samples_for_error(double rel_err, double delta, double alpha, uint64_t *k_out)
 {
     PM_GUARD(return pm::samples_for_error(rel_err, delta, alpha, k_out);)
+}
+
+pm_status pm_set_sampler_shape(int32_t samples_per_lane, int32_t blocks_per_cu)
+{
+    PM_GUARD(return pm::set_sampler_shape(samples_per_lane, blocks_per_cu);)
 }
 
 pm_status pm_philox_device(const uint32_t *in, uint32_t *out, int64_t count)

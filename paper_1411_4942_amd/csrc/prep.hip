@@ -217,6 +217,20 @@ struct WeightsIn {
     }
 };
 
+// the weights are parked in the prefix arrays between the two passes
+struct WeightsStore {
+    uint64_t *p_tau, *p_lam;
+    __device__ __forceinline__ void operator()(int64_t i, U64x2 x) const
+    {
+        p_tau[i] = x.a;
+        p_lam[i] = x.b;
+    }
+};
+struct WeightsLoad {
+    const uint64_t *p_tau, *p_lam;
+    __device__ __forceinline__ U64x2 operator()(int64_t i) const { return U64x2{p_tau[i], p_lam[i]}; }
+};
+
 // inclusive prefixes with wrap detection: incl < x happens iff the running
 // sum passed 2^64
 struct WeightsOut {
@@ -231,15 +245,18 @@ struct WeightsOut {
     }
 };
 
-// N_1 = sum_v C(d_v, 3) in 128 bits; isolated vertices
+// N_1 = sum_v C(d_v, 3) in 128 bits; isolated vertices.  One pair of
+// atomics per block.
 __global__ __launch_bounds__(kBlock) void k_n1(const uint32_t *__restrict__ deg, int64_t n, PrepStats *st)
 {
+    __shared__ uint64_t s_lo[kBlock / kWave], s_hi[kBlock / kWave], s_iso[kBlock / kWave];
     unsigned __int128 acc = 0;
     uint64_t iso = 0;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         uint64_t d = deg[v];
         iso += d == 0;
         if (d >= 3) {
+            // C(d,3) = d (d-1) (d-2) / 6: divide the factors first, exactly
             uint64_t a = d, b = d - 1, c = d - 2;
             if (a % 3 == 0) a /= 3; else if (b % 3 == 0) b /= 3; else c /= 3;
             if ((a & 1) == 0) a >>= 1; else if ((b & 1) == 0) b >>= 1; else c >>= 1;
@@ -255,7 +272,23 @@ __global__ __launch_bounds__(kBlock) void k_n1(const uint32_t *__restrict__ deg,
         lo = nlo;
         iso += __shfl_xor(iso, o, kWave);
     }
+    const int w = threadIdx.x / kWave;
     if (lane_id() == 0) {
+        s_lo[w] = lo;
+        s_hi[w] = hi;
+        s_iso[w] = iso;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        lo = s_lo[0];
+        hi = s_hi[0];
+        iso = s_iso[0];
+        for (int i = 1; i < kBlock / kWave; ++i) {
+            uint64_t nlo = lo + s_lo[i];
+            hi += s_hi[i] + (nlo < lo ? 1u : 0u);
+            lo = nlo;
+            iso += s_iso[i];
+        }
         unsigned long long old = atomicAdd((unsigned long long *)&st->n1_lo, (unsigned long long)lo);
         uint64_t carry = (old + lo < old) ? 1u : 0u;
         atomicAdd((unsigned long long *)&st->n1_hi, (unsigned long long)(hi + carry));
@@ -609,12 +642,13 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
         char *scr = nullptr;
         PM_TRY(tmp.get(&scr, ScanScratch<U64x2>::bytes_for(slots, 16)));
         ProfScope prof("weights_scan", s);
-        PM_TRY((scan_launch<U64x2, 16>(WeightsIn{g->src, g->col, g->deg, rev, g->off, st},
-                                       WeightsOut{g->p_tau, g->p_lam, st}, slots, PairSumOp(), U64x2{0, 0}, scr,
-                                       s)));
+        PM_TRY((scan_launch_stored<U64x2, 16>(WeightsIn{g->src, g->col, g->deg, rev, g->off, st},
+                                              WeightsStore{g->p_tau, g->p_lam}, WeightsLoad{g->p_tau, g->p_lam},
+                                              WeightsOut{g->p_tau, g->p_lam, st}, slots, PairSumOp(), U64x2{0, 0},
+                                              scr, s)));
     }
     if (n > 0) {
-        hipLaunchKernelGGL(k_n1, dim3(grid_stream(n)), dim3(kBlock), 0, s, g->deg, n, st);
+        hipLaunchKernelGGL(k_n1, dim3(grid_for(n, kBlock, 1024)), dim3(kBlock), 0, s, g->deg, n, st);
         PM_HIP(hipGetLastError());
     }
     uint64_t R[2] = {0, 0};

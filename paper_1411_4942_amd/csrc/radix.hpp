@@ -1,11 +1,11 @@
 // Stable LSD radix sort of (uint32 key, uint32 value) pairs, 8-bit digits.
 //
 // One pass = three launches: per-tile digit histograms (digit-major layout),
-// an exclusive scan of those counts (the single-pass scan), and a stable
-// scatter.  The scatter ranks each tile's 4096 elements in input order with
-// wave ballots (8 ballots give every lane the mask of lanes holding the same
-// digit), per-wave digit counts in LDS and a running per-digit base, stages
-// the tile digit-sorted in LDS, then writes each digit run contiguously.
+// an exclusive scan of those counts, and a stable scatter.  The scatter ranks
+// each wave's 1024 elements in input order with ballots (8 ballots give every
+// lane the mask of lanes holding the same digit) and per-wave digit counters
+// in LDS, combines the four waves per digit, stages the tile digit-sorted in
+// LDS, then writes each digit run contiguously.
 #pragma once
 
 #include "profile.hpp"
@@ -17,21 +17,35 @@ constexpr int kRadixItems = 16;
 constexpr int kRadixTile = kBlock * kRadixItems;  // 4096
 constexpr int kRadixBins = 256;
 
+// Tile layout shared by both kernels: wave w owns elements
+// [w * 1024, (w + 1) * 1024) of the tile, as 16 coalesced rows of 64, so the
+// element order inside a tile is (wave, row, lane).
+constexpr int kRadixWaveSpan = kWave * kRadixItems;  // 1024
+
+__device__ __forceinline__ int64_t radix_index(int64_t tile, int w, int i, int lane)
+{
+    return tile * kRadixTile + (int64_t)w * kRadixWaveSpan + (int64_t)i * kWave + lane;
+}
+
 __global__ __launch_bounds__(kBlock) void radix_histogram(const uint32_t *__restrict__ keys, int64_t N, int shift,
                                                           uint32_t mask, uint32_t *__restrict__ counts,
                                                           int64_t tiles)
 {
-    __shared__ uint32_t hist[kRadixBins];
-    hist[threadIdx.x] = 0;
+    __shared__ uint32_t hist[kBlock / kWave][kRadixBins];
+    const int t = threadIdx.x, w = t / kWave, lane = lane_id();
+#pragma unroll
+    for (int i = 0; i < kBlock / kWave; ++i) hist[i][t] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
 #pragma unroll
     for (int i = 0; i < kRadixItems; ++i) {
-        int64_t idx = base + (int64_t)i * kBlock + threadIdx.x;
-        if (idx < N) atomicAdd(&hist[(keys[idx] >> shift) & mask], 1u);
+        int64_t idx = radix_index(blockIdx.x, w, i, lane);
+        if (idx < N) atomicAdd(&hist[w][(keys[idx] >> shift) & mask], 1u);
     }
     __syncthreads();
-    counts[(int64_t)threadIdx.x * tiles + blockIdx.x] = hist[threadIdx.x];
+    uint32_t c = 0;
+#pragma unroll
+    for (int i = 0; i < kBlock / kWave; ++i) c += hist[i][t];
+    counts[(int64_t)t * tiles + blockIdx.x] = c;
 }
 
 __global__ __launch_bounds__(kBlock) void radix_scatter(const uint32_t *__restrict__ keys_in,
@@ -42,26 +56,24 @@ __global__ __launch_bounds__(kBlock) void radix_scatter(const uint32_t *__restri
 {
     __shared__ uint32_t s_key[kRadixTile];
     __shared__ uint32_t s_val[kRadixTile];
-    __shared__ uint32_t s_wcnt[kBlock / kWave][kRadixBins];
-    __shared__ uint32_t s_run[kRadixBins];     // elements of each digit ranked so far
-    __shared__ uint32_t s_start[kRadixBins];   // first LDS slot of each digit in the tile
-    __shared__ uint32_t s_goff[kRadixBins];    // first output position of each digit
+    __shared__ uint32_t s_cnt[kBlock / kWave][kRadixBins];  // per-wave digit counts, then wave offsets
+    __shared__ uint32_t s_start[kRadixBins];                // first LDS slot of each digit in the tile
+    __shared__ uint32_t s_goff[kRadixBins];                 // first output position of each digit
     __shared__ uint32_t s_wsum[kBlock / kWave];
 
     const int t = threadIdx.x;
     const int w = t / kWave;
     const int lane = lane_id();
-    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
 
-    for (int i = 0; i < kBlock / kWave; ++i) s_wcnt[i][t] = 0;
-    s_run[t] = 0;
+#pragma unroll
+    for (int i = 0; i < kBlock / kWave; ++i) s_cnt[i][t] = 0;
     s_goff[t] = offsets[(int64_t)t * tiles + blockIdx.x];
 
     uint32_t key[kRadixItems], val[kRadixItems], dig[kRadixItems], rank[kRadixItems];
 #pragma unroll
     for (int i = 0; i < kRadixItems; ++i) {
-        int64_t idx = base + (int64_t)i * kBlock + t;
+        int64_t idx = radix_index(blockIdx.x, w, i, lane);
         bool ok = idx < N;
         key[i] = ok ? keys_in[idx] : 0u;
         val[i] = ok ? vals_in[idx] : 0u;
@@ -69,10 +81,12 @@ __global__ __launch_bounds__(kBlock) void radix_scatter(const uint32_t *__restri
     }
     __syncthreads();
 
-    // stable rank within the tile: element order is (i, thread)
+    // stable rank inside the wave's 1024 elements: lanes holding the same
+    // digit find each other with 8 ballots; the group's lowest lane bumps the
+    // wave's counter for that digit (one wave: LDS reads precede the write)
 #pragma unroll
     for (int i = 0; i < kRadixItems; ++i) {
-        int64_t idx = base + (int64_t)i * kBlock + t;
+        int64_t idx = radix_index(blockIdx.x, w, i, lane);
         bool ok = idx < N;
         uint64_t peers = __ballot(ok);
 #pragma unroll
@@ -80,55 +94,46 @@ __global__ __launch_bounds__(kBlock) void radix_scatter(const uint32_t *__restri
             uint64_t bal = __ballot((dig[i] >> b) & 1u);
             peers &= ((dig[i] >> b) & 1u) ? bal : ~bal;
         }
-        uint32_t r_in_wave = __popcll(peers & lt_mask);
-        if (ok && r_in_wave == 0) s_wcnt[w][dig[i]] = __popcll(peers);
-        __syncthreads();
-        if (ok) {
-            uint32_t r = s_run[dig[i]] + r_in_wave;
-            for (int ww = 0; ww < w; ++ww) r += s_wcnt[ww][dig[i]];
-            rank[i] = r;
-        }
-        __syncthreads();
-        {
-            uint32_t add = 0;
-            for (int ww = 0; ww < kBlock / kWave; ++ww) {
-                add += s_wcnt[ww][t];
-                s_wcnt[ww][t] = 0;
-            }
-            s_run[t] += add;
-        }
-        __syncthreads();
+        const uint32_t below = __popcll(peers & lt_mask);
+        const uint32_t base = s_cnt[w][dig[i]];
+        rank[i] = base + below;
+        if (ok && below == 0) s_cnt[w][dig[i]] = base + (uint32_t)__popcll(peers);
     }
+    __syncthreads();
 
-    // exclusive scan of the tile's digit counts (s_run now holds the counts)
-    {
-        uint32_t c = s_run[t];
-        uint32_t incl = c;
+    // per digit (thread t): offsets of the four waves, tile total
+    uint32_t c0 = s_cnt[0][t], c1 = s_cnt[1][t], c2 = s_cnt[2][t], c3 = s_cnt[3][t];
+    const uint32_t total = c0 + c1 + c2 + c3;
+    uint32_t incl = total;
 #pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            uint32_t o = __shfl_up(incl, d, kWave);
-            if (lane >= d) incl += o;
-        }
-        if (lane == kWave - 1) s_wsum[w] = incl;
-        __syncthreads();
-        uint32_t pre = 0;
-        for (int ww = 0; ww < w; ++ww) pre += s_wsum[ww];
-        s_start[t] = pre + incl - c;
+    for (int d = 1; d < kWave; d <<= 1) {
+        uint32_t o = __shfl_up(incl, d, kWave);
+        if (lane >= d) incl += o;
     }
+    if (lane == kWave - 1) s_wsum[w] = incl;
+    __syncthreads();
+    uint32_t pre = 0;
+    for (int ww = 0; ww < w; ++ww) pre += s_wsum[ww];
+    s_start[t] = pre + incl - total;
+    s_cnt[0][t] = 0;
+    s_cnt[1][t] = c0;
+    s_cnt[2][t] = c0 + c1;
+    s_cnt[3][t] = c0 + c1 + c2;
     __syncthreads();
 
 #pragma unroll
     for (int i = 0; i < kRadixItems; ++i) {
-        int64_t idx = base + (int64_t)i * kBlock + t;
+        int64_t idx = radix_index(blockIdx.x, w, i, lane);
         if (idx < N) {
-            uint32_t pos = s_start[dig[i]] + rank[i];
+            uint32_t pos = s_start[dig[i]] + s_cnt[w][dig[i]] + rank[i];
             s_key[pos] = key[i];
             s_val[pos] = val[i];
         }
     }
     __syncthreads();
 
-    const int64_t tile_n = (N - base) < kRadixTile ? (N - base) : kRadixTile;
+    const int64_t tile_n = (N - (int64_t)blockIdx.x * kRadixTile) < kRadixTile ? (N - (int64_t)blockIdx.x * kRadixTile)
+                                                                             : kRadixTile;
 #pragma unroll
     for (int i = 0; i < kRadixItems; ++i) {
         int p = i * kBlock + t;

@@ -12,29 +12,63 @@
 #include "profile.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <mutex>
 
 namespace pm {
 
-// b in row a?  Searches the row of the smaller id.
-__device__ __forceinline__ uint32_t adjacent(const int64_t *__restrict__ off, const uint32_t *__restrict__ col,
-                                             uint32_t a, uint32_t b)
+// One sample's state.  Positions are below 2^32 (the library's size limit),
+// so slots and row bounds are held as uint32.
+struct Draw {
+    uint64_t r;       // uniform in [0, R)
+    uint32_t lo, hi;  // edge-draw search window, then lo = the slot
+};
+
+// Membership test "key in row": binary search with early exit.
+struct Member {
+    uint32_t lo, hi, key, found;
+};
+
+__device__ __forceinline__ void member_init(Member &m, const int64_t *__restrict__ off, uint32_t a, uint32_t b)
 {
-    const uint32_t x = a < b ? a : b, y = a < b ? b : a;
-    int64_t lo = off[x];
-    const int64_t end = off[x + 1];
-    int64_t hi = end;
-    while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (col[mid] < y)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return (lo < end && col[lo] == y) ? 1u : 0u;
+    // search the row of the smaller id: after the relabel it is the shorter one
+    const uint32_t x = a < b ? a : b;
+    m.key = a < b ? b : a;
+    m.lo = (uint32_t)off[x];
+    m.hi = (uint32_t)off[x + 1];
+    m.found = 0;
 }
 
-template <bool CENTERED>
+// Advance every live search by one probe; the U probes are issued together.
+template <int N>
+__device__ __forceinline__ bool member_step(Member (&m)[N], const uint32_t *__restrict__ col)
+{
+    uint32_t mid[N], c[N];
+#pragma unroll
+    for (int t = 0; t < N; ++t) mid[t] = m[t].lo < m[t].hi ? (m[t].lo + m[t].hi) >> 1 : 0u;
+#pragma unroll
+    for (int t = 0; t < N; ++t) c[t] = col[mid[t]];
+    bool live = false;
+#pragma unroll
+    for (int t = 0; t < N; ++t) {
+        if (m[t].lo < m[t].hi) {
+            if (c[t] == m[t].key) {
+                m[t].found = 1;
+                m[t].lo = m[t].hi;
+            } else if (c[t] < m[t].key) {
+                m[t].lo = mid[t] + 1;
+            } else {
+                m[t].hi = mid[t];
+            }
+        }
+        live |= m[t].lo < m[t].hi;
+    }
+    return live;
+}
+
+// U independent samples per lane, advanced in lockstep so that each lane has
+// U (or 3U) loads in flight at every dependent step of the chain.
+template <bool CENTERED, int U>
 __global__ __launch_bounds__(kBlock) void k_sample(SamplerView g, uint64_t seed, uint64_t first, uint64_t k,
                                                    unsigned long long *__restrict__ tally)
 {
@@ -42,68 +76,152 @@ __global__ __launch_bounds__(kBlock) void k_sample(SamplerView g, uint64_t seed,
 #pragma unroll
     for (int c = 0; c < PM_NUM_TALLIES; ++c) cnt[c] = 0;
 
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += stride) {
-        const uint64_t r = draw_bounded(seed, CENTERED ? 1u : 0u, first + i, g.R);
+    const uint64_t nthreads = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t tag = CENTERED ? 1u : 0u;
 
-        // edge draw: s = min{s : P[s] > r}
-        const uint64_t j = r >> g.shift;
-        uint32_t lo = g.guide[j], hi = g.guide[j + 1];
-        while (lo < hi) {
-            uint32_t mid = (lo + hi) >> 1;
-            if (g.P[mid] > r)
-                hi = mid;
-            else
-                lo = mid + 1;
+    for (uint64_t base = 0; base < k; base += nthreads * U) {
+        bool act[U];
+        Draw d[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const uint64_t i = base + (uint64_t)q * nthreads + tid;
+            act[q] = i < k;
+            d[q].r = act[q] ? draw_bounded(seed, tag, first + i, g.R) : 0ull;
         }
-        const uint32_t s = lo;
-        const uint32_t u = g.src[s], v = g.col[s];
-        const uint64_t below = s ? g.P[s - 1] : 0ull;
-        const uint64_t o = r - below;
-        const int64_t ou = g.off[u], du = g.off[u + 1] - ou;
-        const int64_t ov = g.off[v], dv = g.off[v + 1] - ov;
-
-        uint32_t up, vp;
-        if (!CENTERED) {
-            // o in [0, (d_u-1)(d_v-1)): u' is the a-th of N(u)\{v}, v' the b-th of N(v)\{u}
-            uint64_t a, b;
-            divmod_small(o, (uint32_t)(dv - 1), a, b);
-            up = g.col[ou + (int64_t)a];
-            if (up == v) up = g.col[ou + du - 1];
-            vp = g.col[ov + (int64_t)b];
-            if (vp == u) vp = g.col[ov + dv - 1];
-        } else {
-            // o in [0, L_uv L_vu): u' among the L_uv neighbours of u after v,
-            // v' among the L_vu neighbours of v after u (row suffixes)
-            const uint64_t lam = g.P[s] - below;
-            const uint32_t luv = (uint32_t)(du - 1 - ((int64_t)s - ou));
-            uint64_t lvu, rem, a, b;
-            divmod_small(lam, luv, lvu, rem);
-            divmod_small(o, (uint32_t)lvu, a, b);
-            up = g.col[(int64_t)s + 1 + (int64_t)a];
-            vp = g.col[ov + (dv - (int64_t)lvu) + (int64_t)b];
+        // edge draw: s = min{s : P[s] > r}, window from the guide table
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const uint64_t j = d[q].r >> g.shift;
+            d[q].lo = act[q] ? g.guide[j] : 0u;
+            d[q].hi = act[q] ? g.guide[j + 1] : 0u;
         }
-
-        uint32_t cls;
-        if (up == vp) {
-            cls = PM_TALLY_TRI;
-        } else if (!CENTERED) {
-            const uint32_t x = adjacent(g.off, g.col, up, v);
-            const uint32_t y = adjacent(g.off, g.col, u, vp);
-            const uint32_t z = adjacent(g.off, g.col, up, vp);
-            const uint32_t e = x + y + z;
-            // 3 edges: 3-path; 4: 4-cycle if the closing edge, else tailed
-            // triangle; 5: chordal-4-cycle; 6: 4-clique
-            cls = e == 0 ? 2u : e == 1 ? (z ? 4u : 3u) : e == 2 ? 5u : 6u;
-        } else {
-            if (!adjacent(g.off, g.col, up, vp)) {
-                cls = PM_TALLY_OPEN;
-            } else {
-                cls = 4u + adjacent(g.off, g.col, up, v) + adjacent(g.off, g.col, u, vp);
+        for (bool live = true; live;) {
+            uint32_t mid[U];
+            uint64_t pv[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) mid[q] = (d[q].lo + d[q].hi) >> 1;
+#pragma unroll
+            for (int q = 0; q < U; ++q) pv[q] = g.P[mid[q]];
+            live = false;
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                if (d[q].lo < d[q].hi) {
+                    if (pv[q] > d[q].r)
+                        d[q].hi = mid[q];
+                    else
+                        d[q].lo = mid[q] + 1;
+                }
+                live |= d[q].lo < d[q].hi;
             }
         }
+        uint32_t u[U], v[U];
+        uint64_t below[U], cur[U];
 #pragma unroll
-        for (int c = 0; c < PM_NUM_TALLIES; ++c) cnt[c] += (cls == (uint32_t)c);
+        for (int q = 0; q < U; ++q) {
+            const uint32_t s = d[q].lo;
+            u[q] = g.src[s];
+            v[q] = g.col[s];
+            below[q] = s ? g.P[s - 1] : 0ull;
+            if (CENTERED) cur[q] = g.P[s];
+        }
+        uint32_t ou[U], du[U], ov[U], dv[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            ou[q] = (uint32_t)g.off[u[q]];
+            du[q] = (uint32_t)g.off[u[q] + 1] - ou[q];
+            ov[q] = (uint32_t)g.off[v[q]];
+            dv[q] = (uint32_t)g.off[v[q] + 1] - ov[q];
+        }
+        uint32_t up[U], vp[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            if (!act[q]) {  // an idle lane's slot may have zero weight: no divisions
+                up[q] = vp[q] = 0;
+                continue;
+            }
+            const uint64_t o = d[q].r - below[q];
+            const uint32_t s = d[q].lo;
+            const uint32_t j = s - ou[q];  // position of v in row u
+            if (!CENTERED) {
+                // o in [0, (d_u-1)(d_v-1)): u' is the a-th of N(u)\{v} (v's
+                // own position stands for the row's last entry), v' the b-th of
+                // N(v)\{u}
+                uint64_t a, b;
+                divmod_small(o, dv[q] - 1, a, b);
+                up[q] = g.col[ou[q] + ((uint32_t)a == j ? du[q] - 1 : (uint32_t)a)];
+                vp[q] = g.col[ov[q] + (uint32_t)b];
+            } else {
+                // o in [0, L_uv L_vu): u' among the L_uv neighbours of u after
+                // v, v' among the L_vu neighbours of v after u (row suffixes)
+                const uint32_t luv = du[q] - 1 - j;
+                uint64_t lvu, rem, a, b;
+                divmod_small(cur[q] - below[q], luv, lvu, rem);
+                divmod_small(o, (uint32_t)lvu, a, b);
+                up[q] = g.col[s + 1 + (uint32_t)a];
+                vp[q] = g.col[ov[q] + (dv[q] - (uint32_t)lvu) + (uint32_t)b];
+            }
+        }
+        if (!CENTERED) {
+#pragma unroll
+            for (int q = 0; q < U; ++q)
+                if (act[q] && vp[q] == u[q]) vp[q] = g.col[ov[q] + dv[q] - 1];
+        }
+
+        uint32_t cls[U];
+        if (!CENTERED) {
+            // x = [u'~v], y = [u~v'], z = [u'~v'], all 3U searches together
+            Member m[3 * U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                member_init(m[3 * q + 0], g.off, up[q], v[q]);
+                member_init(m[3 * q + 1], g.off, u[q], vp[q]);
+                member_init(m[3 * q + 2], g.off, up[q], vp[q]);
+                if (!act[q] || up[q] == vp[q]) m[3 * q].hi = m[3 * q].lo, m[3 * q + 1].hi = m[3 * q + 1].lo,
+                                                m[3 * q + 2].hi = m[3 * q + 2].lo;
+            }
+            while (member_step(m, g.col)) {
+            }
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const uint32_t x = m[3 * q].found, y = m[3 * q + 1].found, z = m[3 * q + 2].found;
+                const uint32_t e = x + y + z;
+                // 3 edges: 3-path; 4: 4-cycle with the closing edge, else
+                // tailed triangle; 5: chordal-4-cycle; 6: 4-clique
+                cls[q] = up[q] == vp[q] ? (uint32_t)PM_TALLY_TRI
+                                        : (e == 0 ? 2u : e == 1 ? (z ? 4u : 3u) : e == 2 ? 5u : 6u);
+            }
+        } else {
+            // centered iff u'~v' (Definition 4.1); then the chords x, y
+            Member mz[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                member_init(mz[q], g.off, up[q], vp[q]);
+                if (!act[q] || up[q] == vp[q]) mz[q].hi = mz[q].lo;
+            }
+            while (member_step(mz, g.col)) {
+            }
+            Member mc[2 * U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                member_init(mc[2 * q + 0], g.off, up[q], v[q]);
+                member_init(mc[2 * q + 1], g.off, u[q], vp[q]);
+                if (!act[q] || !mz[q].found) mc[2 * q].hi = mc[2 * q].lo, mc[2 * q + 1].hi = mc[2 * q + 1].lo;
+            }
+            while (member_step(mc, g.col)) {
+            }
+#pragma unroll
+            for (int q = 0; q < U; ++q)
+                cls[q] = up[q] == vp[q] ? (uint32_t)PM_TALLY_TRI
+                                        : (!mz[q].found ? (uint32_t)PM_TALLY_OPEN
+                                                        : 4u + mc[2 * q].found + mc[2 * q + 1].found);
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q)
+            if (act[q]) {
+#pragma unroll
+                for (int c = 0; c < PM_NUM_TALLIES; ++c) cnt[c] += (cls[q] == (uint32_t)c);
+            }
     }
 
 #pragma unroll
@@ -111,6 +229,30 @@ __global__ __launch_bounds__(kBlock) void k_sample(SamplerView g, uint64_t seed,
         uint32_t t = wave_sum_u32(cnt[c]);
         if (lane_id() == 0 && t) atomicAdd(&tally[c], (unsigned long long)t);
     }
+}
+
+// launch shape of the samplers (pm_set_sampler_shape)
+static std::atomic<int> g_samples_per_lane{2};
+static std::atomic<int> g_blocks_per_cu{8};
+
+pm_status set_sampler_shape(int32_t samples_per_lane, int32_t blocks_per_cu)
+{
+    if (!(samples_per_lane == 1 || samples_per_lane == 2 || samples_per_lane == 4) || blocks_per_cu < 1 ||
+        blocks_per_cu > 64) {
+        set_error("sampler shape: samples_per_lane in {1,2,4}, blocks_per_cu in [1,64]");
+        return PM_EINVAL;
+    }
+    g_samples_per_lane.store(samples_per_lane);
+    g_blocks_per_cu.store(blocks_per_cu);
+    return PM_OK;
+}
+
+template <bool CENTERED, int U>
+static void launch_k_sample(unsigned blocks, hipStream_t s, const SamplerView &v, uint64_t seed, uint64_t first,
+                            uint64_t k, uint64_t *tally)
+{
+    hipLaunchKernelGGL((k_sample<CENTERED, U>), dim3(blocks), dim3(kBlock), 0, s, v, seed, first, k,
+                       (unsigned long long *)tally);
 }
 
 static int cu_count(int dev)
@@ -132,16 +274,19 @@ static pm_status launch_sampler(const pm_graph *g, bool centered, uint64_t seed,
 {
     const SamplerView v = view_of(g, centered);
     if (v.R == 0 || k == 0) return PM_OK;
-    const uint64_t want = (k + kBlock - 1) / kBlock;
-    const uint64_t cap = (uint64_t)cu_count(g->device) * 16;
+    const int U = g_samples_per_lane.load();
+    const uint64_t want = (k + (uint64_t)kBlock * U - 1) / ((uint64_t)kBlock * U);
+    const uint64_t cap = (uint64_t)cu_count(g->device) * (uint64_t)g_blocks_per_cu.load();
     const unsigned blocks = (unsigned)std::max<uint64_t>(1, std::min(want, cap));
     ProfScope prof(centered ? "sample_centered" : "sample_path", s);
-    if (centered)
-        hipLaunchKernelGGL(k_sample<true>, dim3(blocks), dim3(kBlock), 0, s, v, seed, first, k,
-                           (unsigned long long *)tally);
-    else
-        hipLaunchKernelGGL(k_sample<false>, dim3(blocks), dim3(kBlock), 0, s, v, seed, first, k,
-                           (unsigned long long *)tally);
+    switch (U * 2 + (centered ? 1 : 0)) {
+    case 2: launch_k_sample<false, 1>(blocks, s, v, seed, first, k, tally); break;
+    case 3: launch_k_sample<true, 1>(blocks, s, v, seed, first, k, tally); break;
+    case 4: launch_k_sample<false, 2>(blocks, s, v, seed, first, k, tally); break;
+    case 5: launch_k_sample<true, 2>(blocks, s, v, seed, first, k, tally); break;
+    case 8: launch_k_sample<false, 4>(blocks, s, v, seed, first, k, tally); break;
+    default: launch_k_sample<true, 4>(blocks, s, v, seed, first, k, tally); break;
+    }
     PM_HIP(hipGetLastError());
     return PM_OK;
 }

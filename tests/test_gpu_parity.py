@@ -238,3 +238,22 @@ def test_zero_weight_samplers_are_exact_zero():
         if og.R_lam == 0:
             assert r["tally_cent"] == [0] * 8
             assert r["est"][4:] == [0.0, 0.0, 0.0]
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 8), (2, 8), (2, 64), (4, 3), (4, 16)])
+def test_sampler_launch_shape_does_not_change_tallies(shape):
+    """Samples are a function of (seed, tag, id) only: every launch shape of
+    the sampling kernels gives the oracle's tallies."""
+    _say("shape", shape)
+    off, col = synth.chung_lu(20000, 150000, 2.2, 800.0, 5)
+    og = oracle.Graph(off, col)
+    g = ps.Graph(*_dev(off, col))
+    try:
+        ps.set_sampler_shape(*shape)
+        got = g.count(123_457, 98_765, seed=2024, first_path=17, first_cent=5)
+    finally:
+        ps.set_sampler_shape(2, 8)
+    assert got["tally_path"] == og.sample_path(2024, 123_457, 17).tolist()
+    assert got["tally_cent"] == og.sample_centered(2024, 98_765, 5).tolist()
+    with pytest.raises(ps.PathSampError):
+        ps.set_sampler_shape(3, 8)
