@@ -184,6 +184,8 @@ def _bad_graphs():
     c[-1] = -3
     out.append(("negative", off, c, ps.PM_EGRAPH))
     out.append(("asymmetric", np.array([0, 1, 2, 3], np.int64), np.array([1, 2, 1], np.int32), ps.PM_EGRAPH))
+    # a directed 3-cycle: in-degree equals out-degree everywhere, still not symmetric
+    out.append(("directed_cycle", np.array([0, 1, 2, 3], np.int64), np.array([1, 2, 0], np.int32), ps.PM_EGRAPH))
     o = off.copy()
     o[2] = o[3] + 1
     out.append(("offsets_decrease", o, col, ps.PM_EGRAPH))
