@@ -6,14 +6,15 @@
 
 // Relabelled graph: vertex ids are positions in the degree order of Section 4
 // (degree, then input id), so "u before v" is integer u < v and every row is
-// sorted in that order.  Slot s is position s of the CSR; src[s] is its row.
+// sorted in that order.  Slot s is position s of the CSR; edge[s] holds its
+// row in the low and its column in the high 32 bits (one load for both).
 struct pm_graph {
     int device = 0;
     int64_t n = 0;
     int64_t slots = 0;            // 2m
     int64_t *off = nullptr;       // [n+1]
     uint32_t *col = nullptr;      // [slots]
-    uint32_t *src = nullptr;      // [slots]
+    uint64_t *edge = nullptr;     // [slots] row | col << 32
     uint32_t *deg = nullptr;      // [n]
     int32_t *rank = nullptr;      // [n] input id -> relabelled id
     uint64_t *p_tau = nullptr;    // [slots] inclusive prefix of tau
@@ -36,7 +37,7 @@ namespace pm {
 struct SamplerView {
     const int64_t *off;
     const uint32_t *col;
-    const uint32_t *src;
+    const uint64_t *edge;    // row | col << 32 per slot
     const uint64_t *P;       // inclusive prefix of the sampler's weights
     const uint32_t *guide;   // guide[j] = first slot with P > j << shift
     uint64_t R;              // total weight (0: sampler skipped)
@@ -48,7 +49,7 @@ inline SamplerView view_of(const pm_graph *g, bool centered)
     SamplerView v;
     v.off = g->off;
     v.col = g->col;
-    v.src = g->src;
+    v.edge = g->edge;
     v.P = centered ? g->p_lam : g->p_tau;
     v.guide = centered ? g->guide_lam : g->guide_tau;
     v.R = centered ? g->R_lam : g->R_tau;

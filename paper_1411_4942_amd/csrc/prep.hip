@@ -185,13 +185,13 @@ __global__ void k_copy_u32(const uint32_t *__restrict__ a, uint32_t *__restrict_
 // the reverse slot of q has column src[q]).  Half 2 (the reverse slot lies in
 // row col[q]) is checked inside WeightsIn, which loads that row's bounds.
 __global__ __launch_bounds__(kBlock) void k_check_symmetry(const uint32_t *__restrict__ key2,
-                                                           const uint32_t *__restrict__ src, int64_t slots,
+                                                           const uint64_t *__restrict__ edge, int64_t slots,
                                                            PrepStats *st)
 {
     bool bad = false;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < slots;
          q += (int64_t)gridDim.x * blockDim.x)
-        bad |= key2[q] != src[q];
+        bad |= key2[q] != (uint32_t)edge[q];
     if (bad) atomicOr(&st->err, (uint32_t)ERR_ASYM);
 }
 
@@ -200,12 +200,14 @@ __global__ __launch_bounds__(kBlock) void k_check_symmetry(const uint32_t *__res
 // row u) counts the neighbours of u after v; the reverse slot r gives L_{v,u}.
 // Both weights of a slot come out of one pass over (src, col, rev).
 struct WeightsIn {
-    const uint32_t *src, *col, *deg, *rev;
+    const uint64_t *edge;
+    const uint32_t *deg, *rev;
     const int64_t *off;
     PrepStats *st;
     __device__ __forceinline__ U64x2 operator()(int64_t s) const
     {
-        const uint32_t u = src[s], v = col[s];
+        const uint64_t e = edge[s];
+        const uint32_t u = (uint32_t)e, v = (uint32_t)(e >> 32);
         const int64_t r = rev[s];
         const int64_t du = deg[u], dv = deg[v];
         const int64_t ou = off[u], ov = off[v];
@@ -434,7 +436,7 @@ void graph_free(pm_graph *g, hipStream_t s)
     if (!g) return;
     dev_free(g->off, s);
     dev_free(g->col, s);
-    dev_free(g->src, s);
+    dev_free(g->edge, s);
     dev_free(g->deg, s);
     dev_free(g->rank, s);
     dev_free(g->p_tau, s);
@@ -525,13 +527,8 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
         hipLaunchKernelGGL(k_degrees, dim3(grid_stream(n)), dim3(kBlock), 0, s, off_in, n, slots, deg_in, head, st);
         PM_HIP(hipGetLastError());
     }
-    PM_HIP(hipMemcpyAsync(&hst, st, sizeof(hst), hipMemcpyDeviceToHost, s));
-    PM_HIP(hipStreamSynchronize(s));
-    if (hst.err) {
-        set_error(err_text(hst.err));
-        return PM_EGRAPH;
-    }
-    g->dmax = hst.dmax;
+    // (bad offsets only skip head writes: the row scan and the slot checks
+    // below stay in bounds, and both verdicts are read back together)
 
     // row of every input slot, then the slot checks
     uint32_t *src_in = nullptr;
@@ -555,6 +552,7 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
         set_error(err_text(hst.err));
         return PM_EGRAPH;
     }
+    g->dmax = hst.dmax;
 
     // vertex order: stable sort of ids by degree
     char *rscr = nullptr;
@@ -606,32 +604,29 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
     }
     tmp.release(src_in);
     uint32_t *src_fin, *col_fin;
-    PM_TRY(radix_sort(ka, va, kb, vb, slots, vbits, rscr, s, &src_fin, &col_fin));
-    g->src = src_fin;
+    PM_TRY(dev_alloc((void **)&g->edge, sizeof(uint64_t) * ss, s));
+    PM_TRY(radix_sort(ka, va, kb, vb, slots, vbits, rscr, s, &src_fin, &col_fin, g->edge));
     g->col = col_fin;
-    tmp.keep(src_fin);
     tmp.keep(col_fin);
-    g->bytes += 2 * sizeof(uint32_t) * ss;
-    uint32_t *fa = (src_fin == ka) ? kb : ka;  // the two buffers the sort left free
-    uint32_t *fb = (col_fin == va) ? vb : va;
+    g->bytes += (sizeof(uint32_t) + sizeof(uint64_t)) * ss;
+    uint32_t *vfree = (col_fin == va) ? vb : va;  // keys went into edge: ka, kb are free too
 
     // reverse slots and the symmetry check
-    uint32_t *k2a, *v2a;
-    PM_TRY(tmp.get(&k2a, ss));
+    uint32_t *v2a;
     PM_TRY(tmp.get(&v2a, ss));
     if (slots > 0) {
-        hipLaunchKernelGGL(k_copy_u32, dim3(grid_stream(slots)), dim3(kBlock), 0, s, g->col, k2a, slots);
+        hipLaunchKernelGGL(k_copy_u32, dim3(grid_stream(slots)), dim3(kBlock), 0, s, g->col, kb, slots);
         hipLaunchKernelGGL(k_iota, dim3(grid_stream(slots)), dim3(kBlock), 0, s, v2a, slots);
         PM_HIP(hipGetLastError());
     }
     uint32_t *key2, *rev;
-    PM_TRY(radix_sort(k2a, v2a, fa, fb, slots, vbits, rscr, s, &key2, &rev));
+    PM_TRY(radix_sort(kb, v2a, ka, vfree, slots, vbits, rscr, s, &key2, &rev));
     if (slots > 0) {
         ProfScope prof("check_symmetry", s);
-        hipLaunchKernelGGL(k_check_symmetry, dim3(grid_stream(slots)), dim3(kBlock), 0, s, key2, g->src, slots, st);
+        hipLaunchKernelGGL(k_check_symmetry, dim3(grid_stream(slots)), dim3(kBlock), 0, s, key2, g->edge, slots,
+                           st);
         PM_HIP(hipGetLastError());
     }
-    tmp.release(key2);
 
     // weights and their prefixes (nothing below indexes memory through them
     // until the checks are read back)
@@ -642,7 +637,7 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
         char *scr = nullptr;
         PM_TRY(tmp.get(&scr, ScanScratch<U64x2>::bytes_for(slots, 16)));
         ProfScope prof("weights_scan", s);
-        PM_TRY((scan_launch_stored<U64x2, 16>(WeightsIn{g->src, g->col, g->deg, rev, g->off, st},
+        PM_TRY((scan_launch_stored<U64x2, 16>(WeightsIn{g->edge, g->deg, rev, g->off, st},
                                               WeightsStore{g->p_tau, g->p_lam}, WeightsLoad{g->p_tau, g->p_lam},
                                               WeightsOut{g->p_tau, g->p_lam, st}, slots, PairSumOp(), U64x2{0, 0},
                                               scr, s)));

@@ -27,6 +27,19 @@ __device__ __forceinline__ int64_t radix_index(int64_t tile, int w, int i, int l
     return tile * kRadixTile + (int64_t)w * kRadixWaveSpan + (int64_t)i * kWave + lane;
 }
 
+// Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.  Give
+// every XCD a contiguous run of tiles so that the digit runs that neighbouring
+// tiles write next to each other meet in the same L2 and leave it as whole
+// lines.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb)
+{
+    const int64_t x = b % kXcds, i = b / kXcds;
+    const int64_t per = nb / kXcds, extra = nb % kXcds;
+    return x * per + (x < extra ? x : extra) + i;
+}
+
 __global__ __launch_bounds__(kBlock) void radix_histogram(const uint32_t *__restrict__ keys, int64_t N, int shift,
                                                           uint32_t mask, uint32_t *__restrict__ counts,
                                                           int64_t tiles)
@@ -48,11 +61,14 @@ __global__ __launch_bounds__(kBlock) void radix_histogram(const uint32_t *__rest
     counts[(int64_t)t * tiles + blockIdx.x] = c;
 }
 
+// keys_out may be null when pair_out is given: then pair_out[dst] =
+// key | val << 32 replaces the key array (vals_out is always written).
 __global__ __launch_bounds__(kBlock) void radix_scatter(const uint32_t *__restrict__ keys_in,
                                                         const uint32_t *__restrict__ vals_in, int64_t N, int shift,
                                                         uint32_t mask, const uint32_t *__restrict__ offsets,
                                                         int64_t tiles, uint32_t *__restrict__ keys_out,
-                                                        uint32_t *__restrict__ vals_out)
+                                                        uint32_t *__restrict__ vals_out,
+                                                        uint64_t *__restrict__ pair_out)
 {
     __shared__ uint32_t s_key[kRadixTile];
     __shared__ uint32_t s_val[kRadixTile];
@@ -65,15 +81,16 @@ __global__ __launch_bounds__(kBlock) void radix_scatter(const uint32_t *__restri
     const int w = t / kWave;
     const int lane = lane_id();
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    const int64_t tile = xcd_tile(blockIdx.x, tiles);
 
 #pragma unroll
     for (int i = 0; i < kBlock / kWave; ++i) s_cnt[i][t] = 0;
-    s_goff[t] = offsets[(int64_t)t * tiles + blockIdx.x];
+    s_goff[t] = offsets[(int64_t)t * tiles + tile];
 
     uint32_t key[kRadixItems], val[kRadixItems], dig[kRadixItems], rank[kRadixItems];
 #pragma unroll
     for (int i = 0; i < kRadixItems; ++i) {
-        int64_t idx = radix_index(blockIdx.x, w, i, lane);
+        int64_t idx = radix_index(tile, w, i, lane);
         bool ok = idx < N;
         key[i] = ok ? keys_in[idx] : 0u;
         val[i] = ok ? vals_in[idx] : 0u;
@@ -86,7 +103,7 @@ __global__ __launch_bounds__(kBlock) void radix_scatter(const uint32_t *__restri
     // wave's counter for that digit (one wave: LDS reads precede the write)
 #pragma unroll
     for (int i = 0; i < kRadixItems; ++i) {
-        int64_t idx = radix_index(blockIdx.x, w, i, lane);
+        int64_t idx = radix_index(tile, w, i, lane);
         bool ok = idx < N;
         uint64_t peers = __ballot(ok);
 #pragma unroll
@@ -123,7 +140,7 @@ __global__ __launch_bounds__(kBlock) void radix_scatter(const uint32_t *__restri
 
 #pragma unroll
     for (int i = 0; i < kRadixItems; ++i) {
-        int64_t idx = radix_index(blockIdx.x, w, i, lane);
+        int64_t idx = radix_index(tile, w, i, lane);
         if (idx < N) {
             uint32_t pos = s_start[dig[i]] + s_cnt[w][dig[i]] + rank[i];
             s_key[pos] = key[i];
@@ -132,8 +149,7 @@ __global__ __launch_bounds__(kBlock) void radix_scatter(const uint32_t *__restri
     }
     __syncthreads();
 
-    const int64_t tile_n = (N - (int64_t)blockIdx.x * kRadixTile) < kRadixTile ? (N - (int64_t)blockIdx.x * kRadixTile)
-                                                                             : kRadixTile;
+    const int64_t tile_n = (N - tile * kRadixTile) < kRadixTile ? (N - tile * kRadixTile) : kRadixTile;
 #pragma unroll
     for (int i = 0; i < kRadixItems; ++i) {
         int p = i * kBlock + t;
@@ -141,8 +157,12 @@ __global__ __launch_bounds__(kBlock) void radix_scatter(const uint32_t *__restri
             uint32_t k = s_key[p];
             uint32_t d = (k >> shift) & mask;
             uint32_t dst = s_goff[d] + (uint32_t)(p - s_start[d]);
-            keys_out[dst] = k;
-            vals_out[dst] = s_val[p];
+            const uint32_t vv = s_val[p];
+            if (pair_out)
+                pair_out[dst] = (uint64_t)k | ((uint64_t)vv << 32);
+            else
+                keys_out[dst] = k;
+            vals_out[dst] = vv;
         }
     }
 }
@@ -175,13 +195,31 @@ inline size_t radix_scratch_bytes(int64_t N)
 
 // Sort (keys, vals) by the low `bits` bits of the keys, stably.  Ping-pongs
 // between (k0, v0) and (k1, v1); on return *out_k / *out_v point at the
-// buffers holding the result.  N < 2^32.
+// buffers holding the result.  With pair_out, the last pass writes the keys
+// interleaved with the values into pair_out instead (*out_k is then null).
+// N < 2^32.
+__global__ void radix_pair_copy(const uint32_t *__restrict__ k, const uint32_t *__restrict__ v, int64_t N,
+                                uint64_t *__restrict__ pair)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+        pair[i] = (uint64_t)k[i] | ((uint64_t)v[i] << 32);
+}
+
 inline pm_status radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t N, int bits,
-                            void *scratch, hipStream_t s, uint32_t **out_k, uint32_t **out_v)
+                            void *scratch, hipStream_t s, uint32_t **out_k, uint32_t **out_v,
+                            uint64_t *pair_out = nullptr)
 {
     *out_k = k0;
     *out_v = v0;
-    if (N <= 1 || bits <= 0) return PM_OK;
+    if (N <= 1 || bits <= 0) {
+        if (pair_out && N > 0) {
+            hipLaunchKernelGGL(radix_pair_copy, dim3(grid_for(N, kBlock, 4096)), dim3(kBlock), 0, s, k0, v0, N,
+                               pair_out);
+            PM_HIP(hipGetLastError());
+            *out_k = nullptr;
+        }
+        return PM_OK;
+    }
     const int64_t tiles = (N + kRadixTile - 1) / kRadixTile;
     const int64_t cnt = tiles * kRadixBins;
     uint32_t *counts = (uint32_t *)scratch;
@@ -203,9 +241,11 @@ inline pm_status radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *
                                              scan_scr, s)));
         }
         {
+            const bool last = shift + 8 >= bits;
+            uint64_t *po = (last && pair_out) ? pair_out : nullptr;
             ProfScope prof("radix_scatter", s);
             hipLaunchKernelGGL(radix_scatter, dim3((unsigned)tiles), dim3(kBlock), 0, s, ki, vi, N, shift, mask,
-                               offs, tiles, ko, vo);
+                               offs, tiles, po ? nullptr : ko, vo, po);
             PM_HIP(hipGetLastError());
         }
         uint32_t *tk = ki, *tv = vi;
@@ -214,7 +254,7 @@ inline pm_status radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *
         ko = tk;
         vo = tv;
     }
-    *out_k = ki;
+    *out_k = pair_out ? nullptr : ki;
     *out_v = vi;
     return PM_OK;
 }

@@ -39,6 +39,24 @@ __device__ __forceinline__ void member_init(Member &m, const int64_t *__restrict
     m.found = 0;
 }
 
+// Same, when one endpoint's row bounds are already in registers: the row of
+// the smaller id is searched, so the offsets load happens only when `other`
+// is the smaller one.
+__device__ __forceinline__ void member_init_known(Member &m, const int64_t *__restrict__ off, uint32_t known,
+                                                  uint32_t klo, uint32_t khi, uint32_t other)
+{
+    if (known < other) {
+        m.lo = klo;
+        m.hi = khi;
+        m.key = other;
+    } else {
+        m.lo = (uint32_t)off[other];
+        m.hi = (uint32_t)off[other + 1];
+        m.key = known;
+    }
+    m.found = 0;
+}
+
 // Advance every live search by one probe; the U probes are issued together.
 template <int N>
 __device__ __forceinline__ bool member_step(Member (&m)[N], const uint32_t *__restrict__ col)
@@ -120,8 +138,9 @@ __global__ __launch_bounds__(kBlock) void k_sample(SamplerView g, uint64_t seed,
 #pragma unroll
         for (int q = 0; q < U; ++q) {
             const uint32_t s = d[q].lo;
-            u[q] = g.src[s];
-            v[q] = g.col[s];
+            const uint64_t e = g.edge[s];
+            u[q] = (uint32_t)e;
+            v[q] = (uint32_t)(e >> 32);
             below[q] = s ? g.P[s - 1] : 0ull;
             if (CENTERED) cur[q] = g.P[s];
         }
@@ -174,8 +193,8 @@ __global__ __launch_bounds__(kBlock) void k_sample(SamplerView g, uint64_t seed,
             Member m[3 * U];
 #pragma unroll
             for (int q = 0; q < U; ++q) {
-                member_init(m[3 * q + 0], g.off, up[q], v[q]);
-                member_init(m[3 * q + 1], g.off, u[q], vp[q]);
+                member_init_known(m[3 * q + 0], g.off, v[q], ov[q], ov[q] + dv[q], up[q]);
+                member_init_known(m[3 * q + 1], g.off, u[q], ou[q], ou[q] + du[q], vp[q]);
                 member_init(m[3 * q + 2], g.off, up[q], vp[q]);
                 if (!act[q] || up[q] == vp[q]) m[3 * q].hi = m[3 * q].lo, m[3 * q + 1].hi = m[3 * q + 1].lo,
                                                 m[3 * q + 2].hi = m[3 * q + 2].lo;
@@ -204,8 +223,9 @@ __global__ __launch_bounds__(kBlock) void k_sample(SamplerView g, uint64_t seed,
             Member mc[2 * U];
 #pragma unroll
             for (int q = 0; q < U; ++q) {
-                member_init(mc[2 * q + 0], g.off, up[q], v[q]);
-                member_init(mc[2 * q + 1], g.off, u[q], vp[q]);
+                // v < u' and u < v' by construction: the rows of v and u
+                member_init_known(mc[2 * q + 0], g.off, v[q], ov[q], ov[q] + dv[q], up[q]);
+                member_init_known(mc[2 * q + 1], g.off, u[q], ou[q], ou[q] + du[q], vp[q]);
                 if (!act[q] || !mz[q].found) mc[2 * q].hi = mc[2 * q].lo, mc[2 * q + 1].hi = mc[2 * q + 1].lo;
             }
             while (member_step(mc, g.col)) {
@@ -232,8 +252,8 @@ __global__ __launch_bounds__(kBlock) void k_sample(SamplerView g, uint64_t seed,
 }
 
 // launch shape of the samplers (pm_set_sampler_shape)
-static std::atomic<int> g_samples_per_lane{2};
-static std::atomic<int> g_blocks_per_cu{8};
+static std::atomic<int> g_samples_per_lane{1};
+static std::atomic<int> g_blocks_per_cu{4};
 
 pm_status set_sampler_shape(int32_t samples_per_lane, int32_t blocks_per_cu)
 {

@@ -254,7 +254,7 @@ def test_sampler_launch_shape_does_not_change_tallies(shape):
         ps.set_sampler_shape(*shape)
         got = g.count(123_457, 98_765, seed=2024, first_path=17, first_cent=5)
     finally:
-        ps.set_sampler_shape(2, 8)
+        ps.set_sampler_shape(1, 4)
     assert got["tally_path"] == og.sample_path(2024, 123_457, 17).tolist()
     assert got["tally_cent"] == og.sample_centered(2024, 98_765, 5).tolist()
     with pytest.raises(ps.PathSampError):
