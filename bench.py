@@ -29,6 +29,46 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_SAMPLE = 132
 
 
+def source_hash() -> str:
+    """Hash of the HIP library sources: counters taken on other sources are stale."""
+    import glob
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1411_4942_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic():
+    """Per-dispatch HBM bytes measured with rocprofv3 counters (profiles/traffic.json),
+    or None when the library sources changed since they were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    return t if t.get("source_hash") == source_hash() else None
+
+
+def roofline_for(name, kern, alg_entry, traffic):
+    alg_bytes, symbol = alg_entry
+    achieved = alg_bytes / (kern["avg_ms"] * 1e-3) / 1e9
+    tr = None
+    if traffic:
+        cands = [v for key, v in traffic["kernels"].items() if key.startswith(symbol)]
+        if cands:
+            best = max(cands, key=lambda v: v["fetch_bytes"])
+            tr = best["fetch_bytes"] + best["write_bytes"]
+    return {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": tr, "algorithmic_bytes": alg_bytes,
+            "avg_launch_ms": kern["avg_ms"],
+            "traffic_over_algorithmic": (tr / alg_bytes) if tr else None}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -127,22 +167,22 @@ def main():
     # per-kernel averages (HIP events on the launch stream)
     kernels = {name: {"launches": n, "avg_ms": ms / n, "ms_per_step": ms / args.steps}
                for name, (n, ms) in prof.items()}
-    dom = max((kv for kv in kernels.items() if kv[0] != "prep_total"), key=lambda kv: kv[1]["ms_per_step"])
-    samp_ms = [kernels[n]["avg_ms"] for n in ("sample_path", "sample_centered") if n in kernels]
-    samp_avg_ms = sum(samp_ms) / len(samp_ms)
-    achieved_samp = BYTES_PER_SAMPLE * k / (samp_avg_ms * 1e-3) / 1e9
-    roofline = {
-        "bound": "hbm",
-        "kernel": "sample_path/sample_centered",
-        "achieved": achieved_samp,
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": achieved_samp / HBM_PEAK_GBS,
-        "traffic": None,
-        "bytes_per_unit": BYTES_PER_SAMPLE,
-        "units_per_launch": k,
-        "avg_launch_ms": samp_avg_ms,
+    slots = 2 * info["m"]
+    # algorithmic bytes per launch of the kernels the roofline can name
+    alg = {
+        "sample_path": (BYTES_PER_SAMPLE * k, "pm::k_sample<false,"),
+        "sample_centered": (BYTES_PER_SAMPLE * k, "pm::k_sample<true,"),
+        # one pass: read key + value, write key + value (the last pass of the
+        # transpose sort writes the interleaved edge array instead of the keys)
+        "transpose_sort.scatter": (16 * slots, "pm::radix_scatter"),
+        "reverse_sort.scatter": (16 * slots, "pm::radix_scatter"),
     }
+    traffic = load_traffic()
+    timed = {n: v for n, v in kernels.items() if n in alg}
+    dom_name = max(timed, key=lambda n: timed[n]["ms_per_step"])
+    roofline = roofline_for(dom_name, kernels[dom_name], alg[dom_name], traffic)
+    roofline_sampler = roofline_for("sample_path", kernels["sample_path"], alg["sample_path"], traffic)
+    samp_ms = [kernels[n]["avg_ms"] for n in ("sample_path", "sample_centered") if n in kernels]
 
     out = {
         "metric": "3-path samples/s on R-MAT 120M edges",
@@ -166,7 +206,7 @@ def main():
             "parallelism": "single GPU",
         },
         "roofline": roofline,
-        "dominant_kernel": {"name": dom[0], **dom[1]},
+        "roofline_sampler": roofline_sampler,
         "kernels": kernels,
         "sampling_samples_per_s": 2 * k / (sum(samp_ms) * 1e-3),
         "estimates": res["est"][1:],

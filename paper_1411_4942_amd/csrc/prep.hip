@@ -568,7 +568,7 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
         PM_HIP(hipGetLastError());
     }
     uint32_t *sorted_deg, *order;
-    PM_TRY(radix_sort(vk0, vv0, vk1, vv1, n, bits_for((uint64_t)g->dmax), rscr, s, &sorted_deg, &order));
+    PM_TRY(radix_sort("vertex_sort", vk0, vv0, vk1, vv1, n, bits_for((uint64_t)g->dmax), rscr, s, &sorted_deg, &order));
 
     PM_TRY(dev_alloc((void **)&g->rank, sizeof(int32_t) * nn, s));
     PM_TRY(dev_alloc((void **)&g->deg, sizeof(uint32_t) * nn, s));
@@ -605,7 +605,7 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
     tmp.release(src_in);
     uint32_t *src_fin, *col_fin;
     PM_TRY(dev_alloc((void **)&g->edge, sizeof(uint64_t) * ss, s));
-    PM_TRY(radix_sort(ka, va, kb, vb, slots, vbits, rscr, s, &src_fin, &col_fin, g->edge));
+    PM_TRY(radix_sort("transpose_sort", ka, va, kb, vb, slots, vbits, rscr, s, &src_fin, &col_fin, g->edge));
     g->col = col_fin;
     tmp.keep(col_fin);
     g->bytes += (sizeof(uint32_t) + sizeof(uint64_t)) * ss;
@@ -620,7 +620,7 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
         PM_HIP(hipGetLastError());
     }
     uint32_t *key2, *rev;
-    PM_TRY(radix_sort(kb, v2a, ka, vfree, slots, vbits, rscr, s, &key2, &rev));
+    PM_TRY(radix_sort("reverse_sort", kb, v2a, ka, vfree, slots, vbits, rscr, s, &key2, &rev));
     if (slots > 0) {
         ProfScope prof("check_symmetry", s);
         hipLaunchKernelGGL(k_check_symmetry, dim3(grid_stream(slots)), dim3(kBlock), 0, s, key2, g->edge, slots,

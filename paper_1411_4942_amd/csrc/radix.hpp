@@ -8,6 +8,8 @@
 // LDS, then writes each digit run contiguously.
 #pragma once
 
+#include <string>
+
 #include "profile.hpp"
 #include "scan.hpp"
 
@@ -205,10 +207,12 @@ __global__ void radix_pair_copy(const uint32_t *__restrict__ k, const uint32_t *
         pair[i] = (uint64_t)k[i] | ((uint64_t)v[i] << 32);
 }
 
-inline pm_status radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t N, int bits,
-                            void *scratch, hipStream_t s, uint32_t **out_k, uint32_t **out_v,
+inline pm_status radix_sort(const char *name, uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t N,
+                            int bits, void *scratch, hipStream_t s, uint32_t **out_k, uint32_t **out_v,
                             uint64_t *pair_out = nullptr)
 {
+    const std::string n_hist = std::string(name) + ".histogram", n_scan = std::string(name) + ".count_scan",
+                      n_scat = std::string(name) + ".scatter";
     *out_k = k0;
     *out_v = v0;
     if (N <= 1 || bits <= 0) {
@@ -230,20 +234,20 @@ inline pm_status radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *
         int nb = bits - shift < 8 ? bits - shift : 8;
         uint32_t mask = (1u << nb) - 1u;
         {
-            ProfScope prof("radix_histogram", s);
+            ProfScope prof(n_hist.c_str(), s);
             hipLaunchKernelGGL(radix_histogram, dim3((unsigned)tiles), dim3(kBlock), 0, s, ki, N, shift, mask, counts,
                                tiles);
             PM_HIP(hipGetLastError());
         }
         {
-            ProfScope prof("radix_count_scan", s);
+            ProfScope prof(n_scan.c_str(), s);
             PM_TRY((scan_launch<uint32_t, 8>(CountIn{counts}, ExclusiveOut{offs}, cnt, SumOp<uint32_t>(), 0u,
                                              scan_scr, s)));
         }
         {
             const bool last = shift + 8 >= bits;
             uint64_t *po = (last && pair_out) ? pair_out : nullptr;
-            ProfScope prof("radix_scatter", s);
+            ProfScope prof(n_scat.c_str(), s);
             hipLaunchKernelGGL(radix_scatter, dim3((unsigned)tiles), dim3(kBlock), 0, s, ki, vi, N, shift, mask,
                                offs, tiles, po ? nullptr : ko, vo, po);
             PM_HIP(hipGetLastError());
