@@ -3,6 +3,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "ladder.hpp"
 
 // Relabelled graph: vertex ids are positions in the degree order of Section 4
 // (degree, then input id), so "u before v" is integer u < v and every row is
@@ -19,6 +20,9 @@ struct pm_graph {
     int32_t *rank = nullptr;      // [n] input id -> relabelled id
     uint64_t *p_tau = nullptr;    // [slots] inclusive prefix of tau
     uint64_t *p_lam = nullptr;    // [slots] inclusive prefix of lambda
+    uint32_t *ladder = nullptr;   // levels 1..ladder_top of the row search index
+    int ladder_top = 0;
+    uint64_t ladder_off[8] = {0};  // start of level l inside `ladder`
     uint32_t *guide_tau = nullptr;  // [nb_tau + 1]
     uint32_t *guide_lam = nullptr;  // [nb_lam + 1]
     uint32_t shift_tau = 0, shift_lam = 0;
@@ -37,6 +41,7 @@ namespace pm {
 struct SamplerView {
     const int64_t *off;
     const uint32_t *col;
+    Ladder ladder;
     const uint64_t *edge;    // row | col << 32 per slot
     const uint64_t *P;       // inclusive prefix of the sampler's weights
     const uint32_t *guide;   // guide[j] = first slot with P > j << shift
@@ -49,6 +54,9 @@ inline SamplerView view_of(const pm_graph *g, bool centered)
     SamplerView v;
     v.off = g->off;
     v.col = g->col;
+    v.ladder.top = g->ladder_top;
+    v.ladder.lvl[0] = g->col;
+    for (int l = 1; l < kLadderMax; ++l) v.ladder.lvl[l] = l <= g->ladder_top ? g->ladder + g->ladder_off[l] : nullptr;
     v.edge = g->edge;
     v.P = centered ? g->p_lam : g->p_tau;
     v.guide = centered ? g->guide_lam : g->guide_tau;

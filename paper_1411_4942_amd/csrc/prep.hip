@@ -28,6 +28,7 @@ enum : uint32_t {
     ERR_ASYM = 16u,
     ERR_OVF_TAU = 32u,
     ERR_OVF_LAM = 64u,
+    ERR_GUIDE = 128u,  // guide write out of range: only from inconsistent weights
 };
 
 struct PrepStats {
@@ -38,7 +39,26 @@ struct PrepStats {
     uint64_t n1_hi;
     uint32_t nlong_tau;
     uint32_t nlong_lam;
+    U64x2 totals;        // (2W, 2 Lambda) as summed by the weights scan
+    uint32_t shift_tau;  // guide bucket width 2^shift of each sampler
+    uint32_t shift_lam;
+    uint64_t nb_tau;     // guide buckets of each sampler
+    uint64_t nb_lam;
 };
+
+// Guide shape: the smallest bucket width 2^shift with at most `target`
+// buckets over [0, R) (target >= 2, so shift <= 63).  Same on host and device.
+__host__ __device__ inline uint32_t guide_shift(uint64_t R, uint64_t target)
+{
+    uint32_t sh = 0;
+    while (sh < 63 && ((R - 1) >> sh) + 1 > target) ++sh;
+    return sh;
+}
+
+__host__ __device__ inline uint64_t guide_target(int64_t slots)
+{
+    return slots / 4 > 2 ? (uint64_t)(slots / 4) : 2ull;
+}
 
 // ---------------------------------------------------------------------------
 // allocation
@@ -95,7 +115,7 @@ __global__ __launch_bounds__(kBlock) void k_degrees(const int64_t *__restrict__ 
         }
         uint32_t d = (uint32_t)(b - a);
         deg[v] = d;
-        if (d > 0) head[a] = (uint32_t)v;
+        if (d > 0) head[a] = (uint32_t)v + 1u;  // 0 marks "no row starts here"
         dmax = d > dmax ? d : dmax;
     }
     if (err) atomicOr(&st->err, err);
@@ -111,29 +131,28 @@ struct HeadIn {
     const uint32_t *h;
     __device__ __forceinline__ uint32_t operator()(int64_t i) const { return h[i]; }
 };
-struct StoreOut32 {
-    uint32_t *o;
-    __device__ __forceinline__ void operator()(int64_t i, uint32_t incl, uint32_t) const { o[i] = incl; }
-};
-
-// rows strictly ascending, columns in range, no self-loops (src = row of slot)
-__global__ __launch_bounds__(kBlock) void k_check_slots(const int32_t *__restrict__ col,
-                                                        const uint32_t *__restrict__ src, int64_t slots, int64_t n,
-                                                        PrepStats *st)
-{
-    uint32_t err = 0;
-    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < slots;
-         s += (int64_t)gridDim.x * blockDim.x) {
-        int32_t c = col[s];
-        uint32_t u = src[s];
+// The running maximum of the row-start marks is (row of slot i) + 1.  The
+// same pass checks the slot: column in range, no self-loop, and (unless a row
+// starts here) strictly above the previous column.
+struct RowOut {
+    uint32_t *src;
+    const int32_t *col;
+    int64_t n;
+    PrepStats *st;
+    __device__ __forceinline__ void operator()(int64_t i, uint32_t incl, uint32_t head) const
+    {
+        const uint32_t u = incl - 1u;
+        src[i] = u;
+        const int32_t c = col[i];
+        uint32_t err = 0;
         if (c < 0 || (int64_t)c >= n)
             err |= ERR_RANGE;
         else if ((uint32_t)c == u)
             err |= ERR_LOOP;
-        if (s > 0 && src[s - 1] == u && col[s - 1] >= c) err |= ERR_ORDER;
+        if (head == 0 && i > 0 && col[i - 1] >= c) err |= ERR_ORDER;
+        if (err) atomicOr(&st->err, err);
     }
-    if (err) atomicOr(&st->err, err);
-}
+};
 
 __global__ void k_iota(uint32_t *p, int64_t n)
 {
@@ -174,6 +193,13 @@ __global__ __launch_bounds__(kBlock) void k_place_rows(const int64_t *__restrict
     }
 }
 
+// ladder level l from level l-1: next[i] = prev[32 i]
+__global__ void k_ladder_level(const uint32_t *__restrict__ prev, int64_t count, uint32_t *__restrict__ next)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        next[i] = prev[i * 32];
+}
+
 __global__ void k_copy_u32(const uint32_t *__restrict__ a, uint32_t *__restrict__ b, int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -201,7 +227,7 @@ __global__ __launch_bounds__(kBlock) void k_check_symmetry(const uint32_t *__res
 // Both weights of a slot come out of one pass over (src, col, rev).
 struct WeightsIn {
     const uint64_t *edge;
-    const uint32_t *deg, *rev;
+    const uint32_t *rev;
     const int64_t *off;
     PrepStats *st;
     __device__ __forceinline__ U64x2 operator()(int64_t s) const
@@ -209,8 +235,8 @@ struct WeightsIn {
         const uint64_t e = edge[s];
         const uint32_t u = (uint32_t)e, v = (uint32_t)(e >> 32);
         const int64_t r = rev[s];
-        const int64_t du = deg[u], dv = deg[v];
-        const int64_t ou = off[u], ov = off[v];
+        const int64_t ou = off[u], ov = off[v];  // both bounds of a row share a line
+        const int64_t du = off[u + 1] - ou, dv = off[v + 1] - ov;
         if (r < ov || r >= ov + dv) atomicOr(&st->err, (uint32_t)ERR_ASYM);
         const uint64_t tau = (uint64_t)(du - 1) * (uint64_t)(dv - 1);
         const uint64_t luv = (uint64_t)(du - 1 - (s - ou));
@@ -235,8 +261,40 @@ struct WeightsLoad {
 
 // inclusive prefixes with wrap detection: incl < x happens iff the running
 // sum passed 2^64
+// Guide entries of slot i: the buckets whose start j << shift lies in
+// [P[i-1], P[i]) point at slot i.  Runs longer than 64 buckets go to a list
+// that k_guide_long fills with whole blocks.
+// These writes run before the validation verdicts reach the host, so they
+// are bounded by the guide and list sizes whatever the weights hold (with a
+// valid graph every bucket index is below nb and the long list fits).
+__device__ __forceinline__ void guide_fill(uint64_t prev, uint64_t cur, uint32_t shift, uint64_t nb, uint32_t slot,
+                                           uint32_t *__restrict__ guide, uint32_t *__restrict__ long_list,
+                                           uint32_t cap, uint32_t *nlong, uint32_t *err)
+{
+    if (cur <= prev) return;
+    const uint64_t mask = (shift == 0) ? 0ull : ((1ull << shift) - 1ull);
+    const uint64_t j0 = (prev >> shift) + ((prev & mask) != 0 ? 1u : 0u);
+    const uint64_t j1 = (cur - 1) >> shift;
+    if (j1 < j0) return;
+    if (j1 >= nb) {
+        atomicOr(err, (uint32_t)ERR_GUIDE);
+        return;
+    }
+    if (j1 - j0 < 64) {
+        for (uint64_t j = j0; j <= j1; ++j) guide[j] = slot;
+    } else {
+        const uint32_t idx = atomicAdd(nlong, 1u);
+        if (idx < cap)
+            long_list[idx] = slot;
+        else
+            atomicOr(err, (uint32_t)ERR_GUIDE);
+    }
+}
+
 struct WeightsOut {
     uint64_t *p_tau, *p_lam;
+    uint32_t *guide_tau, *guide_lam, *long_tau, *long_lam;
+    uint32_t long_cap;
     PrepStats *st;
     __device__ __forceinline__ void operator()(int64_t i, U64x2 incl, U64x2 x) const
     {
@@ -244,8 +302,27 @@ struct WeightsOut {
         p_lam[i] = incl.b;
         if (incl.a < x.a) atomicOr(&st->err, (uint32_t)ERR_OVF_TAU);
         if (incl.b < x.b) atomicOr(&st->err, (uint32_t)ERR_OVF_LAM);
+        guide_fill(incl.a - x.a, incl.a, st->shift_tau, st->nb_tau, (uint32_t)i, guide_tau, long_tau, long_cap,
+                   &st->nlong_tau, &st->err);
+        guide_fill(incl.b - x.b, incl.b, st->shift_lam, st->nb_lam, (uint32_t)i, guide_lam, long_lam, long_cap,
+                   &st->nlong_lam, &st->err);
     }
 };
+
+// guide shape from the totals, and the sentinel guide[nb] = last slot
+__global__ void k_guide_setup(PrepStats *st, int64_t slots, uint32_t *guide_tau, uint32_t *guide_lam)
+{
+    const uint64_t target = guide_target(slots);
+    const uint64_t Rt = st->totals.a, Rl = st->totals.b;
+    const uint32_t sht = Rt ? guide_shift(Rt, target) : 0u, shl = Rl ? guide_shift(Rl, target) : 0u;
+    const uint64_t nbt = Rt ? ((Rt - 1) >> sht) + 1 : 0, nbl = Rl ? ((Rl - 1) >> shl) + 1 : 0;
+    st->shift_tau = sht;
+    st->shift_lam = shl;
+    st->nb_tau = nbt;  // <= target, the allocated size less the sentinel
+    st->nb_lam = nbl;
+    if (Rt) guide_tau[nbt] = (uint32_t)(slots - 1);
+    if (Rl) guide_lam[nbl] = (uint32_t)(slots - 1);
+}
 
 // N_1 = sum_v C(d_v, 3) in 128 bits; isolated vertices.  One pair of
 // atomics per block.
@@ -298,36 +375,14 @@ __global__ __launch_bounds__(kBlock) void k_n1(const uint32_t *__restrict__ deg,
     }
 }
 
-// guide[j] = first slot whose prefix exceeds j << shift; slot s covers the
-// buckets whose start lies in [P[s-1], P[s]).  Long ranges go to a list.
-__global__ __launch_bounds__(kBlock) void k_guide(const uint64_t *__restrict__ P, int64_t slots, uint32_t shift,
-                                                  uint32_t *__restrict__ guide, uint32_t *__restrict__ long_list,
-                                                  uint32_t *nlong)
-{
-    const uint64_t mask = (shift == 0) ? 0ull : ((1ull << shift) - 1ull);
-    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < slots;
-         s += (int64_t)gridDim.x * blockDim.x) {
-        uint64_t prev = s > 0 ? P[s - 1] : 0ull, cur = P[s];
-        if (cur <= prev) continue;
-        uint64_t j0 = (prev >> shift) + ((prev & mask) != 0 ? 1u : 0u);
-        uint64_t j1 = (cur - 1) >> shift;
-        if (j1 < j0) continue;
-        if (j1 - j0 < 64) {
-            for (uint64_t j = j0; j <= j1; ++j) guide[j] = (uint32_t)s;
-        } else {
-            uint32_t idx = atomicAdd(nlong, 1u);
-            long_list[idx] = (uint32_t)s;
-        }
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void k_guide_long(const uint64_t *__restrict__ P, uint32_t shift,
+__global__ __launch_bounds__(kBlock) void k_guide_long(const uint64_t *__restrict__ P, const uint32_t *shift_p,
                                                        uint32_t *__restrict__ guide,
                                                        const uint32_t *__restrict__ long_list,
-                                                       const uint32_t *nlong)
+                                                       const uint32_t *nlong, uint32_t cap)
 {
+    const uint32_t shift = *shift_p;
     const uint64_t mask = (shift == 0) ? 0ull : ((1ull << shift) - 1ull);
-    const uint32_t cnt = *nlong;
+    const uint32_t cnt = *nlong < cap ? *nlong : cap;  // listed runs were checked against nb
     for (uint32_t e = blockIdx.x; e < cnt; e += gridDim.x) {
         uint32_t s = long_list[e];
         uint64_t prev = s > 0 ? P[s - 1] : 0ull, cur = P[s];
@@ -387,48 +442,6 @@ const char *err_text(uint32_t e)
     return "invalid graph";
 }
 
-// smallest shift with ((R-1) >> shift) + 1 <= target buckets
-void choose_guide(uint64_t R, int64_t slots, uint32_t *shift, uint64_t *nb)
-{
-    uint64_t target = (uint64_t)std::max<int64_t>(1, slots / 4);
-    uint32_t sh = 0;
-    while (sh < 63 && ((R - 1) >> sh) + 1 > target) ++sh;
-    *shift = sh;
-    *nb = ((R - 1) >> sh) + 1;
-}
-
-pm_status build_guide(const uint64_t *P, int64_t slots, uint64_t R, Temps &tmp, PrepStats *st_dev,
-                      uint32_t *nlong_dev, uint32_t **guide_out, uint32_t *shift_out, uint64_t *nb_out,
-                      uint64_t *bytes, hipStream_t s)
-{
-    *guide_out = nullptr;
-    *shift_out = 0;
-    *nb_out = 0;
-    if (R == 0) return PM_OK;
-    uint32_t shift;
-    uint64_t nb;
-    choose_guide(R, slots, &shift, &nb);
-    uint32_t *guide = nullptr;
-    PM_TRY(dev_alloc((void **)&guide, (nb + 1) * sizeof(uint32_t), s));
-    *guide_out = guide;
-    *bytes += (nb + 1) * sizeof(uint32_t);
-    uint32_t cap = (uint32_t)(nb / 64 + 2);
-    uint32_t *long_list = nullptr;
-    PM_TRY(tmp.get(&long_list, cap));
-    PM_TRY(fill_async<uint32_t>(guide + nb, (uint32_t)(slots - 1), 1, s));
-    ProfScope prof("guide", s);
-    hipLaunchKernelGGL(k_guide, dim3(grid_stream(slots)), dim3(kBlock), 0, s, P, slots, shift, guide, long_list,
-                       nlong_dev);
-    PM_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_guide_long, dim3(std::min<uint32_t>(cap, 2048)), dim3(kBlock), 0, s, P, shift, guide,
-                       long_list, nlong_dev);
-    PM_HIP(hipGetLastError());
-    *shift_out = shift;
-    *nb_out = nb;
-    (void)st_dev;
-    return PM_OK;
-}
-
 }  // namespace
 
 void graph_free(pm_graph *g, hipStream_t s)
@@ -437,6 +450,7 @@ void graph_free(pm_graph *g, hipStream_t s)
     dev_free(g->off, s);
     dev_free(g->col, s);
     dev_free(g->edge, s);
+    dev_free(g->ladder, s);
     dev_free(g->deg, s);
     dev_free(g->rank, s);
     dev_free(g->p_tau, s);
@@ -537,15 +551,10 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
         char *scr = nullptr;
         PM_TRY(tmp.get(&scr, ScanScratch<uint32_t>::bytes_for(slots, 16)));
         ProfScope prof("row_scan", s);
-        PM_TRY((scan_launch<uint32_t, 16>(HeadIn{head}, StoreOut32{src_in}, slots, MaxOp<uint32_t>(), 0u, scr, s)));
+        PM_TRY((scan_launch<uint32_t, 16>(HeadIn{head}, RowOut{src_in, col_in, n, st}, slots, MaxOp<uint32_t>(), 0u,
+                                          scr, s)));
     }
     tmp.release(head);
-    if (slots > 0) {
-        ProfScope prof("check_slots", s);
-        hipLaunchKernelGGL(k_check_slots, dim3(grid_stream(slots)), dim3(kBlock), 0, s, col_in, src_in, slots, n,
-                           st);
-        PM_HIP(hipGetLastError());
-    }
     PM_HIP(hipMemcpyAsync(&hst, st, sizeof(hst), hipMemcpyDeviceToHost, s));
     PM_HIP(hipStreamSynchronize(s));
     if (hst.err) {
@@ -591,11 +600,30 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
     tmp.release(vv1);
 
     const int vbits = bits_for(n > 0 ? (uint64_t)(n - 1) : 0);
+    // the column buffers are padded to whole 128-byte lines (ladder level 0)
+    const int64_t ssp = (ss + 31) / 32 * 32 + 32;
     uint32_t *ka, *va, *kb, *vb;
     PM_TRY(tmp.get(&ka, ss));
-    PM_TRY(tmp.get(&va, ss));
+    PM_TRY(tmp.get(&va, ssp));
     PM_TRY(tmp.get(&kb, ss));
-    PM_TRY(tmp.get(&vb, ss));
+    PM_TRY(tmp.get(&vb, ssp));
+
+    // ladder levels 1..top, count(l) = ceil(slots / 32^l); top is the smallest
+    // level whose single line covers every slot (32^(top+1) >= slots)
+    {
+        uint64_t total = 0;
+        const int top = ladder_top_for(slots);
+        g->ladder_top = top;
+        for (int l = 1; l <= top; ++l) {
+            const uint64_t cnt = ladder_count(slots, l);
+            g->ladder_off[l] = total;
+            total += (cnt + 31) / 32 * 32;
+        }
+        if (top > 0) {
+            PM_TRY(dev_alloc((void **)&g->ladder, sizeof(uint32_t) * (total + 32), s));
+            g->bytes += sizeof(uint32_t) * (total + 32);
+        }
+    }
     if (slots > 0) {
         ProfScope prof("place_rows", s);
         hipLaunchKernelGGL(k_place_rows, dim3(grid_stream(slots)), dim3(kBlock), 0, s, off_in, col_in, src_in,
@@ -605,9 +633,16 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
     tmp.release(src_in);
     uint32_t *src_fin, *col_fin;
     PM_TRY(dev_alloc((void **)&g->edge, sizeof(uint64_t) * ss, s));
-    PM_TRY(radix_sort("transpose_sort", ka, va, kb, vb, slots, vbits, rscr, s, &src_fin, &col_fin, g->edge));
+    PM_TRY(radix_sort("transpose_sort", ka, va, kb, vb, slots, vbits, rscr, s, &src_fin, &col_fin, g->edge,
+                      g->ladder_top > 0 ? g->ladder + g->ladder_off[1] : nullptr));
     g->col = col_fin;
     tmp.keep(col_fin);
+    for (int l = 2; l <= g->ladder_top; ++l) {
+        const int64_t cnt = (int64_t)ladder_count(slots, l);
+        hipLaunchKernelGGL(k_ladder_level, dim3(grid_for(cnt, kBlock, 1024)), dim3(kBlock), 0, s,
+                           g->ladder + g->ladder_off[l - 1], cnt, g->ladder + g->ladder_off[l]);
+        PM_HIP(hipGetLastError());
+    }
     g->bytes += (sizeof(uint32_t) + sizeof(uint64_t)) * ss;
     uint32_t *vfree = (col_fin == va) ? vb : va;  // keys went into edge: ka, kb are free too
 
@@ -628,19 +663,41 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
         PM_HIP(hipGetLastError());
     }
 
-    // weights and their prefixes (nothing below indexes memory through them
-    // until the checks are read back)
+    // weights, their prefixes and the guide tables of the edge draws (nothing
+    // below indexes memory through the weights until the checks are read back)
     PM_TRY(dev_alloc((void **)&g->p_tau, sizeof(uint64_t) * ss, s));
     PM_TRY(dev_alloc((void **)&g->p_lam, sizeof(uint64_t) * ss, s));
     g->bytes += 2 * sizeof(uint64_t) * ss;
+    const uint64_t gtarget = guide_target(slots);
+    const uint64_t long_cap = gtarget / 64 + 2;
+    PM_TRY(dev_alloc((void **)&g->guide_tau, sizeof(uint32_t) * (gtarget + 1), s));
+    PM_TRY(dev_alloc((void **)&g->guide_lam, sizeof(uint32_t) * (gtarget + 1), s));
+    g->bytes += 2 * sizeof(uint32_t) * (gtarget + 1);
+    uint32_t *long_tau = nullptr, *long_lam = nullptr;
+    PM_TRY(tmp.get(&long_tau, long_cap));
+    PM_TRY(tmp.get(&long_lam, long_cap));
     {
         char *scr = nullptr;
         PM_TRY(tmp.get(&scr, ScanScratch<U64x2>::bytes_for(slots, 16)));
         ProfScope prof("weights_scan", s);
-        PM_TRY((scan_launch_stored<U64x2, 16>(WeightsIn{g->edge, g->deg, rev, g->off, st},
-                                              WeightsStore{g->p_tau, g->p_lam}, WeightsLoad{g->p_tau, g->p_lam},
-                                              WeightsOut{g->p_tau, g->p_lam, st}, slots, PairSumOp(), U64x2{0, 0},
-                                              scr, s)));
+        auto mid = [&]() -> pm_status {
+            hipLaunchKernelGGL(k_guide_setup, dim3(1), dim3(1), 0, s, st, slots, g->guide_tau, g->guide_lam);
+            PM_HIP(hipGetLastError());
+            return PM_OK;
+        };
+        PM_TRY((scan_launch_stored<U64x2, 16>(
+            WeightsIn{g->edge, rev, g->off, st}, WeightsStore{g->p_tau, g->p_lam}, WeightsLoad{g->p_tau, g->p_lam},
+            WeightsOut{g->p_tau, g->p_lam, g->guide_tau, g->guide_lam, long_tau, long_lam, (uint32_t)long_cap, st},
+            slots, PairSumOp(),
+            U64x2{0, 0}, scr, s, &st->totals, mid)));
+        if (slots > 0) {
+            const unsigned gl = (unsigned)std::min<uint64_t>(long_cap, 2048);
+            hipLaunchKernelGGL(k_guide_long, dim3(gl), dim3(kBlock), 0, s, g->p_tau, &st->shift_tau, g->guide_tau,
+                               long_tau, &st->nlong_tau, (uint32_t)long_cap);
+            hipLaunchKernelGGL(k_guide_long, dim3(gl), dim3(kBlock), 0, s, g->p_lam, &st->shift_lam, g->guide_lam,
+                               long_lam, &st->nlong_lam, (uint32_t)long_cap);
+            PM_HIP(hipGetLastError());
+        }
     }
     if (n > 0) {
         hipLaunchKernelGGL(k_n1, dim3(grid_for(n, kBlock, 1024)), dim3(kBlock), 0, s, g->deg, n, st);
@@ -665,18 +722,23 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
         set_error("N1 does not fit in 64 bits");
         return PM_EOVERFLOW;
     }
+    if (hst.err & ERR_GUIDE) {
+        set_error("internal: guide table inconsistent with the weights");
+        return PM_EDEVICE;
+    }
     g->R_tau = R[0];
     g->R_lam = R[1];
     g->N1 = hst.n1_lo;
     g->isolated = (int64_t)hst.isolated;
+    if (g->R_tau) {
+        g->shift_tau = hst.shift_tau;
+        g->nb_tau = ((g->R_tau - 1) >> g->shift_tau) + 1;
+    }
+    if (g->R_lam) {
+        g->shift_lam = hst.shift_lam;
+        g->nb_lam = ((g->R_lam - 1) >> g->shift_lam) + 1;
+    }
 
-    // guide tables of the edge draws
-    uint32_t *nlong = &st->nlong_tau;
-    PM_TRY(build_guide(g->p_tau, slots, g->R_tau, tmp, st, nlong, &g->guide_tau, &g->shift_tau, &g->nb_tau,
-                       &g->bytes, s));
-    nlong = &st->nlong_lam;
-    PM_TRY(build_guide(g->p_lam, slots, g->R_lam, tmp, st, nlong, &g->guide_lam, &g->shift_lam, &g->nb_lam,
-                       &g->bytes, s));
     PM_HIP(hipStreamSynchronize(s));
     guard.g = nullptr;
     *out = g;

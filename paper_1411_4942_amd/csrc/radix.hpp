@@ -65,12 +65,14 @@ __global__ __launch_bounds__(kBlock) void radix_histogram(const uint32_t *__rest
 
 // keys_out may be null when pair_out is given: then pair_out[dst] =
 // key | val << 32 replaces the key array (vals_out is always written).
+// sample_out, when given, receives every 32nd value: sample_out[dst / 32].
 __global__ __launch_bounds__(kBlock) void radix_scatter(const uint32_t *__restrict__ keys_in,
                                                         const uint32_t *__restrict__ vals_in, int64_t N, int shift,
                                                         uint32_t mask, const uint32_t *__restrict__ offsets,
                                                         int64_t tiles, uint32_t *__restrict__ keys_out,
                                                         uint32_t *__restrict__ vals_out,
-                                                        uint64_t *__restrict__ pair_out)
+                                                        uint64_t *__restrict__ pair_out,
+                                                        uint32_t *__restrict__ sample_out)
 {
     __shared__ uint32_t s_key[kRadixTile];
     __shared__ uint32_t s_val[kRadixTile];
@@ -165,6 +167,7 @@ __global__ __launch_bounds__(kBlock) void radix_scatter(const uint32_t *__restri
             else
                 keys_out[dst] = k;
             vals_out[dst] = vv;
+            if (sample_out && (dst & 31u) == 0) sample_out[dst >> 5] = vv;
         }
     }
 }
@@ -201,15 +204,17 @@ inline size_t radix_scratch_bytes(int64_t N)
 // interleaved with the values into pair_out instead (*out_k is then null).
 // N < 2^32.
 __global__ void radix_pair_copy(const uint32_t *__restrict__ k, const uint32_t *__restrict__ v, int64_t N,
-                                uint64_t *__restrict__ pair)
+                                uint64_t *__restrict__ pair, uint32_t *__restrict__ sample)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
         pair[i] = (uint64_t)k[i] | ((uint64_t)v[i] << 32);
+        if (sample && (i & 31) == 0) sample[i >> 5] = v[i];
+    }
 }
 
 inline pm_status radix_sort(const char *name, uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t N,
                             int bits, void *scratch, hipStream_t s, uint32_t **out_k, uint32_t **out_v,
-                            uint64_t *pair_out = nullptr)
+                            uint64_t *pair_out = nullptr, uint32_t *sample_out = nullptr)
 {
     const std::string n_hist = std::string(name) + ".histogram", n_scan = std::string(name) + ".count_scan",
                       n_scat = std::string(name) + ".scatter";
@@ -218,7 +223,7 @@ inline pm_status radix_sort(const char *name, uint32_t *k0, uint32_t *v0, uint32
     if (N <= 1 || bits <= 0) {
         if (pair_out && N > 0) {
             hipLaunchKernelGGL(radix_pair_copy, dim3(grid_for(N, kBlock, 4096)), dim3(kBlock), 0, s, k0, v0, N,
-                               pair_out);
+                               pair_out, sample_out);
             PM_HIP(hipGetLastError());
             *out_k = nullptr;
         }
@@ -247,9 +252,10 @@ inline pm_status radix_sort(const char *name, uint32_t *k0, uint32_t *v0, uint32
         {
             const bool last = shift + 8 >= bits;
             uint64_t *po = (last && pair_out) ? pair_out : nullptr;
+            uint32_t *so = last ? sample_out : nullptr;
             ProfScope prof(n_scat.c_str(), s);
             hipLaunchKernelGGL(radix_scatter, dim3((unsigned)tiles), dim3(kBlock), 0, s, ki, vi, N, shift, mask,
-                               offs, tiles, po ? nullptr : ko, vo, po);
+                               offs, tiles, po ? nullptr : ko, vo, po, so);
             PM_HIP(hipGetLastError());
         }
         uint32_t *tk = ki, *tv = vi;

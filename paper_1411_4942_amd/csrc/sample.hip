@@ -24,64 +24,24 @@ struct Draw {
     uint32_t lo, hi;  // edge-draw search window, then lo = the slot
 };
 
-// Membership test "key in row": binary search with early exit.
-struct Member {
-    uint32_t lo, hi, key, found;
+// Bounds of the row to search for the pair (known, other): the row of the
+// smaller id (after the relabel the shorter one); the offsets are loaded only
+// when that row is not already in registers.
+struct RowSearch {
+    uint32_t lo, hi, key;
 };
 
-__device__ __forceinline__ void member_init(Member &m, const int64_t *__restrict__ off, uint32_t a, uint32_t b)
+__device__ __forceinline__ RowSearch row_search(const int64_t *__restrict__ off, uint32_t known, uint32_t klo,
+                                                uint32_t khi, uint32_t other)
 {
-    // search the row of the smaller id: after the relabel it is the shorter one
+    if (known < other) return RowSearch{klo, khi, other};
+    return RowSearch{(uint32_t)off[other], (uint32_t)off[other + 1], known};
+}
+
+__device__ __forceinline__ RowSearch row_search2(const int64_t *__restrict__ off, uint32_t a, uint32_t b)
+{
     const uint32_t x = a < b ? a : b;
-    m.key = a < b ? b : a;
-    m.lo = (uint32_t)off[x];
-    m.hi = (uint32_t)off[x + 1];
-    m.found = 0;
-}
-
-// Same, when one endpoint's row bounds are already in registers: the row of
-// the smaller id is searched, so the offsets load happens only when `other`
-// is the smaller one.
-__device__ __forceinline__ void member_init_known(Member &m, const int64_t *__restrict__ off, uint32_t known,
-                                                  uint32_t klo, uint32_t khi, uint32_t other)
-{
-    if (known < other) {
-        m.lo = klo;
-        m.hi = khi;
-        m.key = other;
-    } else {
-        m.lo = (uint32_t)off[other];
-        m.hi = (uint32_t)off[other + 1];
-        m.key = known;
-    }
-    m.found = 0;
-}
-
-// Advance every live search by one probe; the U probes are issued together.
-template <int N>
-__device__ __forceinline__ bool member_step(Member (&m)[N], const uint32_t *__restrict__ col)
-{
-    uint32_t mid[N], c[N];
-#pragma unroll
-    for (int t = 0; t < N; ++t) mid[t] = m[t].lo < m[t].hi ? (m[t].lo + m[t].hi) >> 1 : 0u;
-#pragma unroll
-    for (int t = 0; t < N; ++t) c[t] = col[mid[t]];
-    bool live = false;
-#pragma unroll
-    for (int t = 0; t < N; ++t) {
-        if (m[t].lo < m[t].hi) {
-            if (c[t] == m[t].key) {
-                m[t].found = 1;
-                m[t].lo = m[t].hi;
-            } else if (c[t] < m[t].key) {
-                m[t].lo = mid[t] + 1;
-            } else {
-                m[t].hi = mid[t];
-            }
-        }
-        live |= m[t].lo < m[t].hi;
-    }
-    return live;
+    return RowSearch{(uint32_t)off[x], (uint32_t)off[x + 1], a < b ? b : a};
 }
 
 // U independent samples per lane, advanced in lockstep so that each lane has
@@ -188,53 +148,36 @@ __global__ __launch_bounds__(kBlock) void k_sample(SamplerView g, uint64_t seed,
         }
 
         uint32_t cls[U];
-        if (!CENTERED) {
-            // x = [u'~v], y = [u~v'], z = [u'~v'], all 3U searches together
-            Member m[3 * U];
 #pragma unroll
-            for (int q = 0; q < U; ++q) {
-                member_init_known(m[3 * q + 0], g.off, v[q], ov[q], ov[q] + dv[q], up[q]);
-                member_init_known(m[3 * q + 1], g.off, u[q], ou[q], ou[q] + du[q], vp[q]);
-                member_init(m[3 * q + 2], g.off, up[q], vp[q]);
-                if (!act[q] || up[q] == vp[q]) m[3 * q].hi = m[3 * q].lo, m[3 * q + 1].hi = m[3 * q + 1].lo,
-                                                m[3 * q + 2].hi = m[3 * q + 2].lo;
+        for (int q = 0; q < U; ++q) {
+            if (!act[q] || up[q] == vp[q]) {
+                cls[q] = PM_TALLY_TRI;
+                continue;
             }
-            while (member_step(m, g.col)) {
-            }
-#pragma unroll
-            for (int q = 0; q < U; ++q) {
-                const uint32_t x = m[3 * q].found, y = m[3 * q + 1].found, z = m[3 * q + 2].found;
+            if (!CENTERED) {
+                // x = [u'~v], y = [u~v'], z = [u'~v']
+                const RowSearch sx = row_search(g.off, v[q], ov[q], ov[q] + dv[q], up[q]);
+                const RowSearch sy = row_search(g.off, u[q], ou[q], ou[q] + du[q], vp[q]);
+                const RowSearch sz = row_search2(g.off, up[q], vp[q]);
+                const uint32_t x = ladder_contains(g.ladder, sx.lo, sx.hi, sx.key);
+                const uint32_t y = ladder_contains(g.ladder, sy.lo, sy.hi, sy.key);
+                const uint32_t z = ladder_contains(g.ladder, sz.lo, sz.hi, sz.key);
                 const uint32_t e = x + y + z;
                 // 3 edges: 3-path; 4: 4-cycle with the closing edge, else
                 // tailed triangle; 5: chordal-4-cycle; 6: 4-clique
-                cls[q] = up[q] == vp[q] ? (uint32_t)PM_TALLY_TRI
-                                        : (e == 0 ? 2u : e == 1 ? (z ? 4u : 3u) : e == 2 ? 5u : 6u);
+                cls[q] = e == 0 ? 2u : e == 1 ? (z ? 4u : 3u) : e == 2 ? 5u : 6u;
+            } else {
+                // centered iff u'~v' (Definition 4.1); then the chords u'~v
+                // and u~v', searched in the rows of v and u (v < u', u < v')
+                const RowSearch sz = row_search2(g.off, up[q], vp[q]);
+                if (!ladder_contains(g.ladder, sz.lo, sz.hi, sz.key)) {
+                    cls[q] = PM_TALLY_OPEN;
+                    continue;
+                }
+                const uint32_t x = ladder_contains(g.ladder, ov[q], ov[q] + dv[q], up[q]);
+                const uint32_t y = ladder_contains(g.ladder, ou[q], ou[q] + du[q], vp[q]);
+                cls[q] = 4u + x + y;
             }
-        } else {
-            // centered iff u'~v' (Definition 4.1); then the chords x, y
-            Member mz[U];
-#pragma unroll
-            for (int q = 0; q < U; ++q) {
-                member_init(mz[q], g.off, up[q], vp[q]);
-                if (!act[q] || up[q] == vp[q]) mz[q].hi = mz[q].lo;
-            }
-            while (member_step(mz, g.col)) {
-            }
-            Member mc[2 * U];
-#pragma unroll
-            for (int q = 0; q < U; ++q) {
-                // v < u' and u < v' by construction: the rows of v and u
-                member_init_known(mc[2 * q + 0], g.off, v[q], ov[q], ov[q] + dv[q], up[q]);
-                member_init_known(mc[2 * q + 1], g.off, u[q], ou[q], ou[q] + du[q], vp[q]);
-                if (!act[q] || !mz[q].found) mc[2 * q].hi = mc[2 * q].lo, mc[2 * q + 1].hi = mc[2 * q + 1].lo;
-            }
-            while (member_step(mc, g.col)) {
-            }
-#pragma unroll
-            for (int q = 0; q < U; ++q)
-                cls[q] = up[q] == vp[q] ? (uint32_t)PM_TALLY_TRI
-                                        : (!mz[q].found ? (uint32_t)PM_TALLY_OPEN
-                                                        : 4u + mc[2 * q].found + mc[2 * q + 1].found);
         }
 #pragma unroll
         for (int q = 0; q < U; ++q)

@@ -111,7 +111,8 @@ __global__ __launch_bounds__(kBlock) void scan_reduce_kernel(In in, int64_t N, O
 
 // exclusive scan of tile sums by one block of 1024 threads, 8 per thread
 template <typename T, typename Op>
-__global__ __launch_bounds__(1024) void scan_tiles_kernel(T *sums, int64_t ntiles, Op op, T identity)
+__global__ __launch_bounds__(1024) void scan_tiles_kernel(T *sums, int64_t ntiles, Op op, T identity,
+                                                          T *total_out)
 {
     constexpr int kT = 1024, kPer = 8, kW = kT / kWave;
     __shared__ T s_wave[kW];
@@ -146,6 +147,7 @@ __global__ __launch_bounds__(1024) void scan_tiles_kernel(T *sums, int64_t ntile
         if (t == kT - 1) s_carry = run;
         __syncthreads();
     }
+    if (t == 0 && total_out) *total_out = s_carry;
 }
 
 template <typename T, int ITEMS, typename Op, typename In, typename Out>
@@ -209,9 +211,12 @@ __global__ __launch_bounds__(kBlock) void scan_reduce_store_kernel(In in, St st,
     }
 }
 
-template <typename T, int ITEMS, typename Op, typename In, typename St, typename Ld, typename Out>
+// total_out (device, may be null) receives the sum of all elements before
+// launch 3; mid() is called on the host between the tile scan and launch 3
+// (to enqueue work that depends on the total).
+template <typename T, int ITEMS, typename Op, typename In, typename St, typename Ld, typename Out, typename Mid>
 pm_status scan_launch_stored(In in, St st, Ld ld, Out out, int64_t N, Op op, T identity, void *scratch,
-                             hipStream_t s)
+                             hipStream_t s, T *total_out, Mid mid)
 {
     if (N <= 0) return PM_OK;
     const int64_t tiles = (N + (int64_t)kBlock * ITEMS - 1) / ((int64_t)kBlock * ITEMS);
@@ -219,8 +224,9 @@ pm_status scan_launch_stored(In in, St st, Ld ld, Out out, int64_t N, Op op, T i
     hipLaunchKernelGGL((scan_reduce_store_kernel<T, ITEMS, Op, In, St>), dim3((unsigned)tiles), dim3(kBlock), 0, s,
                        in, st, N, op, identity, sums);
     PM_HIP(hipGetLastError());
-    hipLaunchKernelGGL((scan_tiles_kernel<T, Op>), dim3(1), dim3(1024), 0, s, sums, tiles, op, identity);
+    hipLaunchKernelGGL((scan_tiles_kernel<T, Op>), dim3(1), dim3(1024), 0, s, sums, tiles, op, identity, total_out);
     PM_HIP(hipGetLastError());
+    PM_TRY(mid());
     hipLaunchKernelGGL((scan_apply_kernel<T, ITEMS, Op, Ld, Out>), dim3((unsigned)tiles), dim3(kBlock), 0, s, ld,
                        out, N, op, identity, (const T *)sums);
     PM_HIP(hipGetLastError());
@@ -248,7 +254,8 @@ pm_status scan_launch(In in, Out out, int64_t N, Op op, T identity, void *scratc
     hipLaunchKernelGGL((scan_reduce_kernel<T, ITEMS, Op, In>), dim3((unsigned)tiles), dim3(kBlock), 0, s, in, N, op,
                        identity, sums);
     PM_HIP(hipGetLastError());
-    hipLaunchKernelGGL((scan_tiles_kernel<T, Op>), dim3(1), dim3(1024), 0, s, sums, tiles, op, identity);
+    hipLaunchKernelGGL((scan_tiles_kernel<T, Op>), dim3(1), dim3(1024), 0, s, sums, tiles, op, identity,
+                       (T *)nullptr);
     PM_HIP(hipGetLastError());
     hipLaunchKernelGGL((scan_apply_kernel<T, ITEMS, Op, In, Out>), dim3((unsigned)tiles), dim3(kBlock), 0, s, in,
                        out, N, op, identity, (const T *)sums);
