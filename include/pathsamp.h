@@ -172,6 +172,12 @@ pm_status pm_samples_for_error(double rel_err, double delta, double alpha, uint6
  * depend on the shape.  Default 1 and 4 (the fastest measured on MI355X). */
 pm_status pm_set_sampler_shape(int32_t samples_per_lane, int32_t blocks_per_cu);
 
+/* Device memory: the library keeps freed blocks for reuse (each tagged with
+ * an event on the stream that released it).  This returns every cached block
+ * of the current device to the runtime (after those events complete).  Blocks
+ * are freed on the device that allocated them. */
+pm_status pm_release_cached_memory(void);
+
 /* ------------------------------------------------------------------------ */
 /* Diagnostics                                                               */
 /* ------------------------------------------------------------------------ */

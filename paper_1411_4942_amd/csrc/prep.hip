@@ -15,7 +15,6 @@
 #include "radix.hpp"
 
 #include <algorithm>
-#include <mutex>
 #include <vector>
 
 namespace pm {
@@ -58,43 +57,6 @@ __host__ __device__ inline uint32_t guide_shift(uint64_t R, uint64_t target)
 __host__ __device__ inline uint64_t guide_target(int64_t slots)
 {
     return slots / 4 > 2 ? (uint64_t)(slots / 4) : 2ull;
-}
-
-// ---------------------------------------------------------------------------
-// allocation
-// ---------------------------------------------------------------------------
-
-static std::mutex g_pool_mu;
-static bool g_pool_ready[64];
-
-pm_status dev_alloc(void **p, size_t bytes, hipStream_t s)
-{
-    int dev = 0;
-    PM_HIP(hipGetDevice(&dev));
-    {
-        std::lock_guard<std::mutex> lk(g_pool_mu);
-        if (dev >= 0 && dev < 64 && !g_pool_ready[dev]) {
-            hipMemPool_t pool;
-            if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-                uint64_t thr = UINT64_MAX;  // keep freed blocks for reuse
-                (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-            }
-            g_pool_ready[dev] = true;
-        }
-    }
-    if (bytes == 0) bytes = 256;
-    hipError_t e = hipMallocAsync(p, bytes, s);
-    if (e != hipSuccess) {
-        *p = nullptr;
-        set_error(std::string("hipMallocAsync(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
-        return e == hipErrorOutOfMemory ? PM_ENOMEM : PM_EDEVICE;
-    }
-    return PM_OK;
-}
-
-void dev_free(void *p, hipStream_t s)
-{
-    if (p) (void)hipFreeAsync(p, s);
 }
 
 // ---------------------------------------------------------------------------

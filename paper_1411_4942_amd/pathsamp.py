@@ -84,6 +84,7 @@ _SIGNATURES = {
                                               ctypes.POINTER(ctypes.c_uint64)]),
     "pm_philox_device": (ctypes.c_int32, [_P, _P, ctypes.c_int64]),
     "pm_set_sampler_shape": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32]),
+    "pm_release_cached_memory": (ctypes.c_int32, []),
     "pm_profile_enable": (ctypes.c_int32, [ctypes.c_int32]),
     "pm_profile_read": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "pm_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
@@ -244,6 +245,11 @@ def samples_for_error(rel_err: float, delta: float, alpha: float) -> int:
 def set_sampler_shape(samples_per_lane: int, blocks_per_cu: int):
     """Launch shape of the sampling kernels (tallies do not depend on it)."""
     _check(lib().pm_set_sampler_shape(samples_per_lane, blocks_per_cu), "pm_set_sampler_shape")
+
+
+def release_cached_memory():
+    """Return the library's cached device blocks of the current device."""
+    _check(lib().pm_release_cached_memory(), "pm_release_cached_memory")
 
 
 def philox_device(inputs) -> np.ndarray:

@@ -259,3 +259,30 @@ def test_sampler_launch_shape_does_not_change_tallies(shape):
     assert got["tally_cent"] == og.sample_centered(2024, 98_765, 5).tolist()
     with pytest.raises(ps.PathSampError):
         ps.set_sampler_shape(3, 8)
+
+
+def test_cached_device_memory_reuse_across_streams():
+    """Graphs created and destroyed repeatedly on two streams reuse cached
+    device blocks; every count stays equal to the oracle's."""
+    _say("allocator reuse")
+    off1, col1 = synth.chung_lu(6000, 50000, 2.3, 300.0, 21)
+    off2, col2 = synth.erdos_renyi(3000, 30000, 22)
+    o1, o2 = oracle.Graph(off1, col1), oracle.Graph(off2, col2)
+    want1 = (o1.sample_path(3, 50_000).tolist(), o1.sample_centered(3, 50_000).tolist())
+    want2 = (o2.sample_path(4, 50_000).tolist(), o2.sample_centered(4, 50_000).tolist())
+    d1, d2 = _dev(off1, col1), _dev(off2, col2)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    for it in range(4):
+        with torch.cuda.stream(s1):
+            g1 = ps.Graph(*d1, stream=s1)
+            r1 = g1.count(50_000, 50_000, seed=3, stream=s1)
+        with torch.cuda.stream(s2):
+            g2 = ps.Graph(*d2, stream=s2)
+            r2 = g2.count(50_000, 50_000, seed=4, stream=s2)
+        assert (r1["tally_path"], r1["tally_cent"]) == want1, it
+        assert (r2["tally_path"], r2["tally_cent"]) == want2, it
+        g1.destroy()
+        g2.destroy()
+        if it == 2:
+            torch.cuda.synchronize()
+            ps.release_cached_memory()
