@@ -533,13 +533,9 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
     PM_TRY(tmp.get(&vv0, nn));
     PM_TRY(tmp.get(&vk1, nn));
     PM_TRY(tmp.get(&vv1, nn));
-    if (n > 0) {
-        hipLaunchKernelGGL(k_copy_u32, dim3(grid_stream(n)), dim3(kBlock), 0, s, deg_in, vk0, n);
-        hipLaunchKernelGGL(k_iota, dim3(grid_stream(n)), dim3(kBlock), 0, s, vv0, n);
-        PM_HIP(hipGetLastError());
-    }
     uint32_t *sorted_deg, *order;
-    PM_TRY(radix_sort("vertex_sort", vk0, vv0, vk1, vv1, n, bits_for((uint64_t)g->dmax), rscr, s, &sorted_deg, &order));
+    PM_TRY(radix_sort("vertex_sort", deg_in, nullptr, vk0, vv0, vk1, vv1, n, bits_for((uint64_t)g->dmax), rscr, s,
+                      &sorted_deg, &order));
 
     PM_TRY(dev_alloc((void **)&g->rank, sizeof(int32_t) * nn, s));
     PM_TRY(dev_alloc((void **)&g->deg, sizeof(uint32_t) * nn, s));
@@ -589,13 +585,14 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
     if (slots > 0) {
         ProfScope prof("place_rows", s);
         hipLaunchKernelGGL(k_place_rows, dim3(grid_stream(slots)), dim3(kBlock), 0, s, off_in, col_in, src_in,
-                           g->rank, g->off, slots, ka, va);
+                           g->rank, g->off, slots, kb, vb);
         PM_HIP(hipGetLastError());
     }
     tmp.release(src_in);
     uint32_t *src_fin, *col_fin;
     PM_TRY(dev_alloc((void **)&g->edge, sizeof(uint64_t) * ss, s));
-    PM_TRY(radix_sort("transpose_sort", ka, va, kb, vb, slots, vbits, rscr, s, &src_fin, &col_fin, g->edge,
+    // G1 sits in (kb, vb); the sort alternates (ka, va) and (kb, vb)
+    PM_TRY(radix_sort("transpose_sort", kb, vb, ka, va, kb, vb, slots, vbits, rscr, s, &src_fin, &col_fin, g->edge,
                       g->ladder_top > 0 ? g->ladder + g->ladder_off[1] : nullptr));
     g->col = col_fin;
     tmp.keep(col_fin);
@@ -607,17 +604,13 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
     }
     g->bytes += (sizeof(uint32_t) + sizeof(uint64_t)) * ss;
     uint32_t *vfree = (col_fin == va) ? vb : va;  // keys went into edge: ka, kb are free too
-
-    // reverse slots and the symmetry check
     uint32_t *v2a;
     PM_TRY(tmp.get(&v2a, ss));
-    if (slots > 0) {
-        hipLaunchKernelGGL(k_copy_u32, dim3(grid_stream(slots)), dim3(kBlock), 0, s, g->col, kb, slots);
-        hipLaunchKernelGGL(k_iota, dim3(grid_stream(slots)), dim3(kBlock), 0, s, v2a, slots);
-        PM_HIP(hipGetLastError());
-    }
+
+    // reverse slots and the symmetry check: the slots' columns sorted stably,
+    // with each slot's own position as payload
     uint32_t *key2, *rev;
-    PM_TRY(radix_sort("reverse_sort", kb, v2a, ka, vfree, slots, vbits, rscr, s, &key2, &rev));
+    PM_TRY(radix_sort("reverse_sort", g->col, nullptr, kb, vfree, ka, v2a, slots, vbits, rscr, s, &key2, &rev));
     if (slots > 0) {
         ProfScope prof("check_symmetry", s);
         hipLaunchKernelGGL(k_check_symmetry, dim3(grid_stream(slots)), dim3(kBlock), 0, s, key2, g->edge, slots,

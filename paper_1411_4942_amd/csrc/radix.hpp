@@ -63,6 +63,7 @@ __global__ __launch_bounds__(kBlock) void radix_histogram(const uint32_t *__rest
     counts[(int64_t)t * tiles + blockIdx.x] = c;
 }
 
+// vals_in may be null: the payload is then the element's input position.
 // keys_out may be null when pair_out is given: then pair_out[dst] =
 // key | val << 32 replaces the key array (vals_out is always written).
 // sample_out, when given, receives every 32nd value: sample_out[dst / 32].
@@ -97,7 +98,7 @@ __global__ __launch_bounds__(kBlock) void radix_scatter(const uint32_t *__restri
         int64_t idx = radix_index(tile, w, i, lane);
         bool ok = idx < N;
         key[i] = ok ? keys_in[idx] : 0u;
-        val[i] = ok ? vals_in[idx] : 0u;
+        val[i] = ok ? (vals_in ? vals_in[idx] : (uint32_t)idx) : 0u;
         dig[i] = (key[i] >> shift) & mask;
     }
     __syncthreads();
@@ -198,35 +199,42 @@ inline size_t radix_scratch_bytes(int64_t N)
     return (size_t)cnt * 2 * sizeof(uint32_t) + ScanScratch<uint32_t>::bytes_for(cnt, 8) + 1024;
 }
 
-// Sort (keys, vals) by the low `bits` bits of the keys, stably.  Ping-pongs
-// between (k0, v0) and (k1, v1); on return *out_k / *out_v point at the
-// buffers holding the result.  With pair_out, the last pass writes the keys
-// interleaved with the values into pair_out instead (*out_k is then null).
-// N < 2^32.
+// Sort (keys, vals) by the low `bits` bits of the keys, stably.  The first
+// pass reads (in_k, in_v), which are never written (in_v null: the payload
+// is the input position); passes alternate between the buffer pairs
+// (k0, v0) and (k1, v1).  On return *out_k / *out_v point at the result.
+// With pair_out, the last pass writes key | val << 32 there instead of the
+// keys (*out_k is then null); with sample_out it also writes every 32nd
+// value.  N < 2^32.
 __global__ void radix_pair_copy(const uint32_t *__restrict__ k, const uint32_t *__restrict__ v, int64_t N,
-                                uint64_t *__restrict__ pair, uint32_t *__restrict__ sample)
+                                uint64_t *__restrict__ pair, uint32_t *__restrict__ sample, uint32_t *__restrict__ vcopy)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
-        pair[i] = (uint64_t)k[i] | ((uint64_t)v[i] << 32);
-        if (sample && (i & 31) == 0) sample[i >> 5] = v[i];
+        const uint32_t vv = v ? v[i] : (uint32_t)i;
+        if (pair) pair[i] = (uint64_t)k[i] | ((uint64_t)vv << 32);
+        if (sample && (i & 31) == 0) sample[i >> 5] = vv;
+        vcopy[i] = vv;
     }
 }
 
-inline pm_status radix_sort(const char *name, uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t N,
-                            int bits, void *scratch, hipStream_t s, uint32_t **out_k, uint32_t **out_v,
-                            uint64_t *pair_out = nullptr, uint32_t *sample_out = nullptr)
+inline pm_status radix_sort(const char *name, const uint32_t *in_k, const uint32_t *in_v, uint32_t *k0, uint32_t *v0,
+                            uint32_t *k1, uint32_t *v1, int64_t N, int bits, void *scratch, hipStream_t s,
+                            uint32_t **out_k, uint32_t **out_v, uint64_t *pair_out = nullptr,
+                            uint32_t *sample_out = nullptr)
 {
     const std::string n_hist = std::string(name) + ".histogram", n_scan = std::string(name) + ".count_scan",
                       n_scat = std::string(name) + ".scatter";
     *out_k = k0;
     *out_v = v0;
     if (N <= 1 || bits <= 0) {
-        if (pair_out && N > 0) {
-            hipLaunchKernelGGL(radix_pair_copy, dim3(grid_for(N, kBlock, 4096)), dim3(kBlock), 0, s, k0, v0, N,
-                               pair_out, sample_out);
+        // nothing to sort: copy the input through (values, pairs, samples)
+        if (N > 0) {
+            hipLaunchKernelGGL(radix_pair_copy, dim3(grid_for(N, kBlock, 4096)), dim3(kBlock), 0, s, in_k, in_v, N,
+                               pair_out, sample_out, v0);
             PM_HIP(hipGetLastError());
-            *out_k = nullptr;
+            if (!pair_out) PM_HIP(hipMemcpyAsync(k0, in_k, sizeof(uint32_t) * N, hipMemcpyDeviceToDevice, s));
         }
+        if (pair_out) *out_k = nullptr;
         return PM_OK;
     }
     const int64_t tiles = (N + kRadixTile - 1) / kRadixTile;
@@ -234,7 +242,8 @@ inline pm_status radix_sort(const char *name, uint32_t *k0, uint32_t *v0, uint32
     uint32_t *counts = (uint32_t *)scratch;
     uint32_t *offs = counts + cnt;
     void *scan_scr = (void *)(((uintptr_t)(offs + cnt) + 255) & ~(uintptr_t)255);
-    uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
+    const uint32_t *ki = in_k, *vi = in_v;
+    uint32_t *ko = k0, *vo = v0;
     for (int shift = 0; shift < bits; shift += 8) {
         int nb = bits - shift < 8 ? bits - shift : 8;
         uint32_t mask = (1u << nb) - 1u;
@@ -258,14 +267,14 @@ inline pm_status radix_sort(const char *name, uint32_t *k0, uint32_t *v0, uint32
                                offs, tiles, po ? nullptr : ko, vo, po, so);
             PM_HIP(hipGetLastError());
         }
-        uint32_t *tk = ki, *tv = vi;
+        *out_k = ko;
+        *out_v = vo;
         ki = ko;
         vi = vo;
-        ko = tk;
-        vo = tv;
+        ko = (ko == k0) ? k1 : k0;
+        vo = (vo == v0) ? v1 : v0;
     }
-    *out_k = pair_out ? nullptr : ki;
-    *out_v = vi;
+    if (pair_out) *out_k = nullptr;
     return PM_OK;
 }
 
