@@ -64,8 +64,7 @@ __host__ __device__ inline uint64_t guide_target(int64_t slots)
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(kBlock) void k_degrees(const int64_t *__restrict__ off, int64_t n, int64_t slots,
-                                                    uint32_t *__restrict__ deg, uint32_t *__restrict__ head,
-                                                    PrepStats *st)
+                                                    uint32_t *__restrict__ deg, PrepStats *st)
 {
     uint32_t err = 0, dmax = 0;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
@@ -77,7 +76,6 @@ __global__ __launch_bounds__(kBlock) void k_degrees(const int64_t *__restrict__ 
         }
         uint32_t d = (uint32_t)(b - a);
         deg[v] = d;
-        if (d > 0) head[a] = (uint32_t)v + 1u;  // 0 marks "no row starts here"
         dmax = d > dmax ? d : dmax;
     }
     if (err) atomicOr(&st->err, err);
@@ -88,33 +86,6 @@ __global__ __launch_bounds__(kBlock) void k_degrees(const int64_t *__restrict__ 
     }
     if (lane_id() == 0) atomicMax(&st->dmax, dmax);
 }
-
-struct HeadIn {
-    const uint32_t *h;
-    __device__ __forceinline__ uint32_t operator()(int64_t i) const { return h[i]; }
-};
-// The running maximum of the row-start marks is (row of slot i) + 1.  The
-// same pass checks the slot: column in range, no self-loop, and (unless a row
-// starts here) strictly above the previous column.
-struct RowOut {
-    uint32_t *src;
-    const int32_t *col;
-    int64_t n;
-    PrepStats *st;
-    __device__ __forceinline__ void operator()(int64_t i, uint32_t incl, uint32_t head) const
-    {
-        const uint32_t u = incl - 1u;
-        src[i] = u;
-        const int32_t c = col[i];
-        uint32_t err = 0;
-        if (c < 0 || (int64_t)c >= n)
-            err |= ERR_RANGE;
-        else if ((uint32_t)c == u)
-            err |= ERR_LOOP;
-        if (head == 0 && i > 0 && col[i - 1] >= c) err |= ERR_ORDER;
-        if (err) atomicOr(&st->err, err);
-    }
-};
 
 __global__ void k_iota(uint32_t *p, int64_t n)
 {
@@ -137,22 +108,40 @@ struct OffOut {
     __device__ __forceinline__ void operator()(int64_t i, uint64_t incl, uint64_t) const { off[i + 1] = (int64_t)incl; }
 };
 
-// G1: the input's slots moved into the rows of the new order (unsorted rows)
+// G1: every input row moved to its place in the new order, columns mapped
+// to new ids (rows not yet sorted).  One wave per input row at a time, which
+// also checks the row: columns in range, no self-loop, strictly ascending.
+// Offsets were checked before this runs; an out-of-range column is flagged
+// and its entry left unwritten (the caller stops on the flag).
 __global__ __launch_bounds__(kBlock) void k_place_rows(const int64_t *__restrict__ off_in,
-                                                       const int32_t *__restrict__ col_in,
-                                                       const uint32_t *__restrict__ src_in,
+                                                       const int32_t *__restrict__ col_in, int64_t n,
                                                        const int32_t *__restrict__ rank,
-                                                       const int64_t *__restrict__ off_new, int64_t slots,
-                                                       uint32_t *__restrict__ key, uint32_t *__restrict__ val)
+                                                       const int64_t *__restrict__ off_new,
+                                                       uint32_t *__restrict__ key, uint32_t *__restrict__ val,
+                                                       PrepStats *st)
 {
-    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < slots;
-         s += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t u = src_in[s];
-        int32_t ru = rank[u];
-        int64_t dst = off_new[ru] + (s - off_in[u]);
-        key[dst] = (uint32_t)rank[col_in[s]];
-        val[dst] = (uint32_t)ru;
+    const int lane = lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    uint32_t err = 0;
+    for (int64_t u = wave; u < n; u += nwaves) {
+        const int64_t a = off_in[u], b = off_in[u + 1];
+        if (a == b) continue;
+        const int32_t ru = rank[u];
+        const int64_t base = off_new[ru] - a;
+        for (int64_t p = a + lane; p < b; p += kWave) {
+            const int32_t c = col_in[p];
+            if (c < 0 || (int64_t)c >= n) {
+                err |= ERR_RANGE;
+                continue;
+            }
+            if (c == (int32_t)u) err |= ERR_LOOP;
+            if (p > a && col_in[p - 1] >= c) err |= ERR_ORDER;
+            key[base + p] = (uint32_t)rank[c];
+            val[base + p] = (uint32_t)ru;
+        }
     }
+    if (err) atomicOr(&st->err, err);
 }
 
 // ladder level l from level l-1: next[i] = prev[32 i]
@@ -494,29 +483,14 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
     PrepStats hst;
 
     const int64_t nn = std::max<int64_t>(n, 1), ss = std::max<int64_t>(slots, 1);
-    uint32_t *deg_in = nullptr, *head = nullptr;
+    uint32_t *deg_in = nullptr;
     PM_TRY(tmp.get(&deg_in, nn));
-    PM_TRY(tmp.get(&head, ss));
-    PM_TRY(fill_async<uint32_t>(head, 0u, slots, s));
     if (n > 0) {
         ProfScope prof("degrees", s);
-        hipLaunchKernelGGL(k_degrees, dim3(grid_stream(n)), dim3(kBlock), 0, s, off_in, n, slots, deg_in, head, st);
+        hipLaunchKernelGGL(k_degrees, dim3(grid_stream(n)), dim3(kBlock), 0, s, off_in, n, slots, deg_in, st);
         PM_HIP(hipGetLastError());
     }
-    // (bad offsets only skip head writes: the row scan and the slot checks
-    // below stay in bounds, and both verdicts are read back together)
-
-    // row of every input slot, then the slot checks
-    uint32_t *src_in = nullptr;
-    PM_TRY(tmp.get(&src_in, ss));
-    {
-        char *scr = nullptr;
-        PM_TRY(tmp.get(&scr, ScanScratch<uint32_t>::bytes_for(slots, 16)));
-        ProfScope prof("row_scan", s);
-        PM_TRY((scan_launch<uint32_t, 16>(HeadIn{head}, RowOut{src_in, col_in, n, st}, slots, MaxOp<uint32_t>(), 0u,
-                                          scr, s)));
-    }
-    tmp.release(head);
+    // the row walk below trusts the offsets: read the verdict first
     PM_HIP(hipMemcpyAsync(&hst, st, sizeof(hst), hipMemcpyDeviceToHost, s));
     PM_HIP(hipStreamSynchronize(s));
     if (hst.err) {
@@ -584,11 +558,17 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
     }
     if (slots > 0) {
         ProfScope prof("place_rows", s);
-        hipLaunchKernelGGL(k_place_rows, dim3(grid_stream(slots)), dim3(kBlock), 0, s, off_in, col_in, src_in,
-                           g->rank, g->off, slots, kb, vb);
+        hipLaunchKernelGGL(k_place_rows, dim3(grid_stream(n * kWave)), dim3(kBlock), 0, s, off_in, col_in, n,
+                           g->rank, g->off, kb, vb, st);
         PM_HIP(hipGetLastError());
     }
-    tmp.release(src_in);
+    // the sorts and the weights trust the columns: read the slot checks
+    PM_HIP(hipMemcpyAsync(&hst, st, sizeof(hst), hipMemcpyDeviceToHost, s));
+    PM_HIP(hipStreamSynchronize(s));
+    if (hst.err) {
+        set_error(err_text(hst.err));
+        return PM_EGRAPH;
+    }
     uint32_t *src_fin, *col_fin;
     PM_TRY(dev_alloc((void **)&g->edge, sizeof(uint64_t) * ss, s));
     // G1 sits in (kb, vb); the sort alternates (ka, va) and (kb, vb)
