@@ -108,13 +108,35 @@ struct OffOut {
     __device__ __forceinline__ void operator()(int64_t i, uint64_t incl, uint64_t) const { off[i + 1] = (int64_t)incl; }
 };
 
-// G1: every input row moved to its place in the new order, columns mapped
-// to new ids (rows not yet sorted).  One wave per input row at a time, which
-// also checks the row: columns in range, no self-loop, strictly ascending.
-// Offsets were checked before this runs; an out-of-range column is flagged
-// and its entry left unwritten (the caller stops on the flag).
+// Row holding slot p: upper_bound(off, p) - 1 over [lo, hi), all 64 lanes
+// probing together (64-ary search); p is the same in every lane.
+__device__ __forceinline__ int64_t wave_row_of(const int64_t *__restrict__ off, int64_t n, int64_t p)
+{
+    int64_t lo = 0, hi = n + 1;  // first x with off[x] > p lies in [lo, hi]
+    const int lane = lane_id();
+    while (hi - lo > 1) {
+        const int64_t step = (hi - lo + kWave - 1) / kWave;
+        const int64_t x = lo + (int64_t)(lane + 1) * step;
+        const bool le = x < hi && off[x] <= p;
+        const uint64_t m = __ballot(le);
+        const int cnt = __popcll(m);  // probes at or below p form a prefix
+        const int64_t nlo = lo + (int64_t)cnt * step;
+        const int64_t nhi = lo + (int64_t)(cnt + 1) * step;
+        lo = nlo;
+        hi = nhi < hi ? nhi : hi;
+    }
+    return lo;  // off[lo] <= p < off[lo + 1] (lo is the last x with off[x] <= p)
+}
+
+// G1: every input slot moved into the row of its vertex's new id, columns
+// mapped to new ids (rows not yet sorted).  Slot-parallel, 64 consecutive
+// slots per wave: a 64-ary search brackets their rows, then each lane finds
+// its own row inside the bracket.  The same pass checks every slot: column in
+// range, no self-loop, strictly above the previous column of its row.  An
+// out-of-range column is flagged and left unwritten (the caller stops on the
+// flag).  Offsets were checked before this runs.
 __global__ __launch_bounds__(kBlock) void k_place_rows(const int64_t *__restrict__ off_in,
-                                                       const int32_t *__restrict__ col_in, int64_t n,
+                                                       const int32_t *__restrict__ col_in, int64_t n, int64_t slots,
                                                        const int32_t *__restrict__ rank,
                                                        const int64_t *__restrict__ off_new,
                                                        uint32_t *__restrict__ key, uint32_t *__restrict__ val,
@@ -123,23 +145,36 @@ __global__ __launch_bounds__(kBlock) void k_place_rows(const int64_t *__restrict
     const int lane = lane_id();
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    const int64_t chunks = (slots + kWave - 1) / kWave;
     uint32_t err = 0;
-    for (int64_t u = wave; u < n; u += nwaves) {
-        const int64_t a = off_in[u], b = off_in[u + 1];
-        if (a == b) continue;
-        const int32_t ru = rank[u];
-        const int64_t base = off_new[ru] - a;
-        for (int64_t p = a + lane; p < b; p += kWave) {
-            const int32_t c = col_in[p];
-            if (c < 0 || (int64_t)c >= n) {
-                err |= ERR_RANGE;
-                continue;
-            }
-            if (c == (int32_t)u) err |= ERR_LOOP;
-            if (p > a && col_in[p - 1] >= c) err |= ERR_ORDER;
-            key[base + p] = (uint32_t)rank[c];
-            val[base + p] = (uint32_t)ru;
+    for (int64_t ch = wave; ch < chunks; ch += nwaves) {
+        const int64_t p0 = ch * kWave;
+        const int64_t plast = (p0 + kWave - 1 < slots) ? p0 + kWave - 1 : slots - 1;
+        const int64_t ufirst = wave_row_of(off_in, n, p0);
+        const int64_t ulast = wave_row_of(off_in, n, plast);
+        const int64_t p = p0 + lane;
+        if (p >= slots) continue;
+        // last u in [ufirst, ulast] with off_in[u] <= p
+        int64_t lo = ufirst, hi = ulast + 1;
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (off_in[mid] <= p)
+                lo = mid;
+            else
+                hi = mid;
         }
+        const int64_t u = lo, a = off_in[u];
+        const int32_t c = col_in[p];
+        if (c < 0 || (int64_t)c >= n) {
+            err |= ERR_RANGE;
+            continue;
+        }
+        if (c == (int32_t)u) err |= ERR_LOOP;
+        if (p > a && col_in[p - 1] >= c) err |= ERR_ORDER;
+        const int32_t ru = rank[u];
+        const int64_t dst = off_new[ru] + (p - a);
+        key[dst] = (uint32_t)rank[c];
+        val[dst] = (uint32_t)ru;
     }
     if (err) atomicOr(&st->err, err);
 }
@@ -558,7 +593,7 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
     }
     if (slots > 0) {
         ProfScope prof("place_rows", s);
-        hipLaunchKernelGGL(k_place_rows, dim3(grid_stream(n * kWave)), dim3(kBlock), 0, s, off_in, col_in, n,
+        hipLaunchKernelGGL(k_place_rows, dim3(grid_stream(slots)), dim3(kBlock), 0, s, off_in, col_in, n, slots,
                            g->rank, g->off, kb, vb, st);
         PM_HIP(hipGetLastError());
     }
