@@ -129,12 +129,15 @@ __device__ __forceinline__ int64_t wave_row_of(const int64_t *__restrict__ off, 
 }
 
 // G1: every input slot moved into the row of its vertex's new id, columns
-// mapped to new ids (rows not yet sorted).  Slot-parallel, 64 consecutive
-// slots per wave: a 64-ary search brackets their rows, then each lane finds
-// its own row inside the bracket.  The same pass checks every slot: column in
-// range, no self-loop, strictly above the previous column of its row.  An
-// out-of-range column is flagged and left unwritten (the caller stops on the
-// flag).  Offsets were checked before this runs.
+// mapped to new ids (rows not yet sorted).  Slot-parallel: each wave owns
+// 1024 consecutive slots (16 coalesced rows of 64); a 64-ary search brackets
+// the rows they fall in, then each lane locates its slots' rows inside the
+// bracket, its lower bound only moving forward.  The same pass checks every
+// slot: column in range, no self-loop, strictly above the previous column of
+// its row.  An out-of-range column is flagged and left unwritten (the caller
+// stops on the flag).  Offsets were checked before this runs.
+constexpr int kPlaceItems = 16;
+
 __global__ __launch_bounds__(kBlock) void k_place_rows(const int64_t *__restrict__ off_in,
                                                        const int32_t *__restrict__ col_in, int64_t n, int64_t slots,
                                                        const int32_t *__restrict__ rank,
@@ -145,36 +148,42 @@ __global__ __launch_bounds__(kBlock) void k_place_rows(const int64_t *__restrict
     const int lane = lane_id();
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
-    const int64_t chunks = (slots + kWave - 1) / kWave;
+    const int64_t span = (int64_t)kWave * kPlaceItems;
+    const int64_t ranges = (slots + span - 1) / span;
     uint32_t err = 0;
-    for (int64_t ch = wave; ch < chunks; ch += nwaves) {
-        const int64_t p0 = ch * kWave;
-        const int64_t plast = (p0 + kWave - 1 < slots) ? p0 + kWave - 1 : slots - 1;
+    for (int64_t rg = wave; rg < ranges; rg += nwaves) {
+        const int64_t p0 = rg * span;
+        const int64_t plast = (p0 + span - 1 < slots) ? p0 + span - 1 : slots - 1;
         const int64_t ufirst = wave_row_of(off_in, n, p0);
         const int64_t ulast = wave_row_of(off_in, n, plast);
-        const int64_t p = p0 + lane;
-        if (p >= slots) continue;
-        // last u in [ufirst, ulast] with off_in[u] <= p
-        int64_t lo = ufirst, hi = ulast + 1;
-        while (hi - lo > 1) {
-            const int64_t mid = (lo + hi) >> 1;
-            if (off_in[mid] <= p)
-                lo = mid;
-            else
-                hi = mid;
+        int64_t lo0 = ufirst;  // rows of this lane's slots never decrease
+#pragma unroll 4
+        for (int i = 0; i < kPlaceItems; ++i) {
+            const int64_t p = p0 + (int64_t)i * kWave + lane;
+            if (p >= slots) break;
+            // last u in [lo0, ulast] with off_in[u] <= p
+            int64_t lo = lo0, hi = ulast + 1;
+            while (hi - lo > 1) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (off_in[mid] <= p)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            lo0 = lo;
+            const int64_t u = lo, a = off_in[u];
+            const int32_t c = col_in[p];
+            if (c < 0 || (int64_t)c >= n) {
+                err |= ERR_RANGE;
+                continue;
+            }
+            if (c == (int32_t)u) err |= ERR_LOOP;
+            if (p > a && col_in[p - 1] >= c) err |= ERR_ORDER;
+            const int32_t ru = rank[u];
+            const int64_t dst = off_new[ru] + (p - a);
+            key[dst] = (uint32_t)rank[c];
+            val[dst] = (uint32_t)ru;
         }
-        const int64_t u = lo, a = off_in[u];
-        const int32_t c = col_in[p];
-        if (c < 0 || (int64_t)c >= n) {
-            err |= ERR_RANGE;
-            continue;
-        }
-        if (c == (int32_t)u) err |= ERR_LOOP;
-        if (p > a && col_in[p - 1] >= c) err |= ERR_ORDER;
-        const int32_t ru = rank[u];
-        const int64_t dst = off_new[ru] + (p - a);
-        key[dst] = (uint32_t)rank[c];
-        val[dst] = (uint32_t)ru;
     }
     if (err) atomicOr(&st->err, err);
 }
@@ -192,20 +201,11 @@ __global__ void k_copy_u32(const uint32_t *__restrict__ a, uint32_t *__restrict_
         b[i] = a[i];
 }
 
-// Symmetry, half 1: listing the slots by (col, row) must list the rows in
-// the order of the slots' own rows (in-degree = out-degree everywhere and
-// the reverse slot of q has column src[q]).  Half 2 (the reverse slot lies in
-// row col[q]) is checked inside WeightsIn, which loads that row's bounds.
-__global__ __launch_bounds__(kBlock) void k_check_symmetry(const uint32_t *__restrict__ key2,
-                                                           const uint64_t *__restrict__ edge, int64_t slots,
-                                                           PrepStats *st)
-{
-    bool bad = false;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < slots;
-         q += (int64_t)gridDim.x * blockDim.x)
-        bad |= key2[q] != (uint32_t)edge[q];
-    if (bad) atomicOr(&st->err, (uint32_t)ERR_ASYM);
-}
+// Symmetry: listing the slots by (col, row) must list the rows in the order
+// of the slots' own rows (half 1: in-degree = out-degree everywhere and the
+// reverse slot of q has column src[q]), and the reverse slot of q must lie in
+// row col[q] (half 2).  Both are checked inside WeightsIn, which reads those
+// arrays anyway.
 
 // Section 3: tau_s = (d_u - 1)(d_v - 1).
 // Section 4: lambda_s = L_{u,v} L_{v,u}; L_{u,v} = d_u - 1 - (position of v in
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(kBlock) void k_check_symmetry(const uint32_t *__res
 // Both weights of a slot come out of one pass over (src, col, rev).
 struct WeightsIn {
     const uint64_t *edge;
-    const uint32_t *rev;
+    const uint32_t *rev, *key2;
     const int64_t *off;
     PrepStats *st;
     __device__ __forceinline__ U64x2 operator()(int64_t s) const
@@ -221,6 +221,7 @@ struct WeightsIn {
         const uint64_t e = edge[s];
         const uint32_t u = (uint32_t)e, v = (uint32_t)(e >> 32);
         const int64_t r = rev[s];
+        if (key2[s] != u) atomicOr(&st->err, (uint32_t)ERR_ASYM);  // symmetry, half 1
         const int64_t ou = off[u], ov = off[v];  // both bounds of a row share a line
         const int64_t du = off[u + 1] - ou, dv = off[v + 1] - ov;
         if (r < ov || r >= ov + dv) atomicOr(&st->err, (uint32_t)ERR_ASYM);
@@ -593,8 +594,8 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
     }
     if (slots > 0) {
         ProfScope prof("place_rows", s);
-        hipLaunchKernelGGL(k_place_rows, dim3(grid_stream(slots)), dim3(kBlock), 0, s, off_in, col_in, n, slots,
-                           g->rank, g->off, kb, vb, st);
+        hipLaunchKernelGGL(k_place_rows, dim3(grid_for((slots + kPlaceItems - 1) / kPlaceItems, kBlock, 4096)),
+                           dim3(kBlock), 0, s, off_in, col_in, n, slots, g->rank, g->off, kb, vb, st);
         PM_HIP(hipGetLastError());
     }
     // the sorts and the weights trust the columns: read the slot checks
@@ -626,12 +627,6 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
     // with each slot's own position as payload
     uint32_t *key2, *rev;
     PM_TRY(radix_sort("reverse_sort", g->col, nullptr, kb, vfree, ka, v2a, slots, vbits, rscr, s, &key2, &rev));
-    if (slots > 0) {
-        ProfScope prof("check_symmetry", s);
-        hipLaunchKernelGGL(k_check_symmetry, dim3(grid_stream(slots)), dim3(kBlock), 0, s, key2, g->edge, slots,
-                           st);
-        PM_HIP(hipGetLastError());
-    }
 
     // weights, their prefixes and the guide tables of the edge draws (nothing
     // below indexes memory through the weights until the checks are read back)
@@ -656,7 +651,7 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
             return PM_OK;
         };
         PM_TRY((scan_launch_stored<U64x2, 16>(
-            WeightsIn{g->edge, rev, g->off, st}, WeightsStore{g->p_tau, g->p_lam}, WeightsLoad{g->p_tau, g->p_lam},
+            WeightsIn{g->edge, rev, key2, g->off, st}, WeightsStore{g->p_tau, g->p_lam}, WeightsLoad{g->p_tau, g->p_lam},
             WeightsOut{g->p_tau, g->p_lam, g->guide_tau, g->guide_lam, long_tau, long_lam, (uint32_t)long_cap, st},
             slots, PairSumOp(),
             U64x2{0, 0}, scr, s, &st->totals, mid)));
