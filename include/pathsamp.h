@@ -149,6 +149,51 @@ pm_status pm_count(const pm_graph *g, const pm_params *p, pm_result *out, void *
 pm_status pm_sample_async(const pm_graph *g, const pm_params *p, uint64_t *tallies_dev, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Batched sampling: many prepared graphs in one launch                      */
+/* ------------------------------------------------------------------------ */
+
+/* Launch shape of a batch: samples per work tile and resident blocks per
+ * compute unit.  samples_per_tile = 0 asks the autotuner, which times tile
+ * sizes {1024, 4096, 16384} x blocks {2, 4, 8} on the batch and keeps the
+ * fastest (cached per graph count and total-sample magnitude). */
+typedef struct {
+    int32_t samples_per_tile;
+    int32_t blocks_per_cu;
+} pm_tune;
+
+typedef struct pm_batch pm_batch;
+
+/* A batch over count prepared graphs (all on the current device), graph i
+ * sampled with params[i].  Every graph's result is bit-for-bit the result of
+ * pm_count(graphs[i], &params[i]): samples depend only on (seed, sampler,
+ * id).  The work is a table of tiles (graph, sampler, first id, count, seed)
+ * consumed by one persistent kernel; the whole run (table upload, tally
+ * reset, kernel, tally download) is captured once as a HIP graph on an
+ * internal stream and replayed by pm_batch_run.  The batch keeps pointers to
+ * the graphs: destroy the batch before them.  Errors: PM_EINVAL (null,
+ * count <= 0, a graph on another device, k_path = k_cent = 0, delta outside
+ * (0,1), bad tune), PM_ENOMEM, PM_EDEVICE. */
+pm_status pm_batch_create(const pm_graph *const *graphs, const pm_params *params, int32_t count, const pm_tune *tune,
+                          void *stream, pm_batch **out);
+
+/* New parameters for the same graphs (seeds, id ranges, budgets); no
+ * recapture.  PM_EINVAL when the new budgets need more tiles than the batch
+ * was created with (the capacity is that of the creation budgets cut into
+ * tiles of min(1024, the requested tile size) samples). */
+pm_status pm_batch_set_params(pm_batch *b, const pm_params *params);
+
+/* Replay the batch after the work already on `stream`; out[count] receives
+ * each graph's result.  Returns when the results are on the host. */
+pm_status pm_batch_run(pm_batch *b, pm_result *out, void *stream);
+
+pm_status pm_batch_get_tune(const pm_batch *b, pm_tune *out);
+pm_status pm_batch_destroy(pm_batch *b);
+
+/* One-shot: pm_batch_create, pm_batch_run, pm_batch_destroy. */
+pm_status pm_count_batch(const pm_graph *const *graphs, const pm_params *params, pm_result *out, int32_t count,
+                         const pm_tune *tune, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Host-side estimates and error bars                                        */
 /* ------------------------------------------------------------------------ */
 

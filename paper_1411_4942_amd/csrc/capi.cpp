@@ -31,6 +31,12 @@ pm_status dev_alloc(void **p, size_t bytes, hipStream_t s);
 void dev_free(void *p, hipStream_t s);
 pm_status count_on_graph(const pm_graph *g, const pm_params *p, pm_result *out, hipStream_t s);
 pm_status set_sampler_shape(int32_t samples_per_lane, int32_t blocks_per_cu);
+pm_status batch_create(const pm_graph *const *graphs, const pm_params *params, int32_t count, const pm_tune *tune,
+                       hipStream_t user_stream, pm_batch **out);
+pm_status batch_set_params(pm_batch *b, const pm_params *params);
+pm_status batch_run(pm_batch *b, pm_result *out, hipStream_t user_stream);
+pm_status batch_get_tune(const pm_batch *b, pm_tune *out);
+pm_status batch_destroy(pm_batch *b);
 
 }  // namespace pm
 
@@ -154,6 +160,45 @@ pm_status pm_samples_for_error(double rel_err, double delta, double alpha, uint6
 pm_status pm_set_sampler_shape(int32_t samples_per_lane, int32_t blocks_per_cu)
 {
     PM_GUARD(return pm::set_sampler_shape(samples_per_lane, blocks_per_cu);)
+}
+
+pm_status pm_batch_create(const pm_graph *const *graphs, const pm_params *params, int32_t count, const pm_tune *tune,
+                          void *stream, pm_batch **out)
+{
+    PM_GUARD(return pm::batch_create(graphs, params, count, tune, (hipStream_t)stream, out);)
+}
+
+pm_status pm_batch_set_params(pm_batch *b, const pm_params *params)
+{
+    PM_GUARD(return pm::batch_set_params(b, params);)
+}
+
+pm_status pm_batch_run(pm_batch *b, pm_result *out, void *stream)
+{
+    PM_GUARD(return pm::batch_run(b, out, (hipStream_t)stream);)
+}
+
+pm_status pm_batch_get_tune(const pm_batch *b, pm_tune *out)
+{
+    PM_GUARD(return pm::batch_get_tune(b, out);)
+}
+
+pm_status pm_batch_destroy(pm_batch *b)
+{
+    PM_GUARD(return pm::batch_destroy(b);)
+}
+
+pm_status pm_count_batch(const pm_graph *const *graphs, const pm_params *params, pm_result *out, int32_t count,
+                         const pm_tune *tune, void *stream)
+{
+    PM_GUARD({
+        pm_batch *b = nullptr;
+        pm_status st = pm::batch_create(graphs, params, count, tune, (hipStream_t)stream, &b);
+        if (st != PM_OK) return st;
+        st = pm::batch_run(b, out, (hipStream_t)stream);
+        pm::batch_destroy(b);
+        return st;
+    })
 }
 
 pm_status pm_philox_device(const uint32_t *in, uint32_t *out, int64_t count)

@@ -1,15 +1,10 @@
-// The sampling kernels: Algorithm 1 (sample) classified as in Algorithm 2,
-// and Algorithm 3 (sample-centered) classified as in Algorithm 4.
-//
-// One lane per sample, grid-stride over sample ids.  Per sample:
-//   r      exact uniform in [0, R) from Philox keyed by (seed, id)
-//   slot   first s with P[s] > r: guide table, then a short binary search
-//   picks  o = r - P[s-1] split in mixed radix into the two neighbour picks
-//   tests  the three adjacency tests by binary search in the shorter row
-//          (after the relabel, the smaller id has the shorter or equal row)
-//   tally  per-lane counters, one wave reduction and atomic per class
+// The single-graph sampling kernels: Algorithm 1 (sample) classified as in
+// Algorithm 2, and Algorithm 3 (sample-centered) classified as in Algorithm 4
+// (the per-sample body is in sampler.hpp).  One lane per sample, grid-stride
+// over sample ids; per-lane counters, one wave reduction and atomic per class.
 #include "graph.hpp"
 #include "profile.hpp"
+#include "sampler.hpp"
 
 #include <algorithm>
 #include <atomic>
@@ -17,35 +12,8 @@
 
 namespace pm {
 
-// One sample's state.  Positions are below 2^32 (the library's size limit),
-// so slots and row bounds are held as uint32.
-struct Draw {
-    uint64_t r;       // uniform in [0, R)
-    uint32_t lo, hi;  // edge-draw search window, then lo = the slot
-};
-
-// Bounds of the row to search for the pair (known, other): the row of the
-// smaller id (after the relabel the shorter one); the offsets are loaded only
-// when that row is not already in registers.
-struct RowSearch {
-    uint32_t lo, hi, key;
-};
-
-__device__ __forceinline__ RowSearch row_search(const int64_t *__restrict__ off, uint32_t known, uint32_t klo,
-                                                uint32_t khi, uint32_t other)
-{
-    if (known < other) return RowSearch{klo, khi, other};
-    return RowSearch{(uint32_t)off[other], (uint32_t)off[other + 1], known};
-}
-
-__device__ __forceinline__ RowSearch row_search2(const int64_t *__restrict__ off, uint32_t a, uint32_t b)
-{
-    const uint32_t x = a < b ? a : b;
-    return RowSearch{(uint32_t)off[x], (uint32_t)off[x + 1], a < b ? b : a};
-}
-
-// U independent samples per lane, advanced in lockstep so that each lane has
-// U (or 3U) loads in flight at every dependent step of the chain.
+// U samples per lane per round of the grid-stride loop (U > 1 only
+// unrolls the loop; each sample is independent).
 template <bool CENTERED, int U>
 __global__ __launch_bounds__(kBlock) void k_sample(SamplerView g, uint64_t seed, uint64_t first, uint64_t k,
                                                    unsigned long long *__restrict__ tally)
@@ -53,145 +21,16 @@ __global__ __launch_bounds__(kBlock) void k_sample(SamplerView g, uint64_t seed,
     uint32_t cnt[PM_NUM_TALLIES];
 #pragma unroll
     for (int c = 0; c < PM_NUM_TALLIES; ++c) cnt[c] = 0;
-
     const uint64_t nthreads = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t tag = CENTERED ? 1u : 0u;
-
     for (uint64_t base = 0; base < k; base += nthreads * U) {
-        bool act[U];
-        Draw d[U];
 #pragma unroll
         for (int q = 0; q < U; ++q) {
             const uint64_t i = base + (uint64_t)q * nthreads + tid;
-            act[q] = i < k;
-            d[q].r = act[q] ? draw_bounded(seed, tag, first + i, g.R) : 0ull;
+            if (i < k) tally_add(cnt, sample_class<CENTERED>(g, seed, first + i));
         }
-        // edge draw: s = min{s : P[s] > r}, window from the guide table
-#pragma unroll
-        for (int q = 0; q < U; ++q) {
-            const uint64_t j = d[q].r >> g.shift;
-            d[q].lo = act[q] ? g.guide[j] : 0u;
-            d[q].hi = act[q] ? g.guide[j + 1] : 0u;
-        }
-        for (bool live = true; live;) {
-            uint32_t mid[U];
-            uint64_t pv[U];
-#pragma unroll
-            for (int q = 0; q < U; ++q) mid[q] = (d[q].lo + d[q].hi) >> 1;
-#pragma unroll
-            for (int q = 0; q < U; ++q) pv[q] = g.P[mid[q]];
-            live = false;
-#pragma unroll
-            for (int q = 0; q < U; ++q) {
-                if (d[q].lo < d[q].hi) {
-                    if (pv[q] > d[q].r)
-                        d[q].hi = mid[q];
-                    else
-                        d[q].lo = mid[q] + 1;
-                }
-                live |= d[q].lo < d[q].hi;
-            }
-        }
-        uint32_t u[U], v[U];
-        uint64_t below[U], cur[U];
-#pragma unroll
-        for (int q = 0; q < U; ++q) {
-            const uint32_t s = d[q].lo;
-            const uint64_t e = g.edge[s];
-            u[q] = (uint32_t)e;
-            v[q] = (uint32_t)(e >> 32);
-            below[q] = s ? g.P[s - 1] : 0ull;
-            if (CENTERED) cur[q] = g.P[s];
-        }
-        uint32_t ou[U], du[U], ov[U], dv[U];
-#pragma unroll
-        for (int q = 0; q < U; ++q) {
-            ou[q] = (uint32_t)g.off[u[q]];
-            du[q] = (uint32_t)g.off[u[q] + 1] - ou[q];
-            ov[q] = (uint32_t)g.off[v[q]];
-            dv[q] = (uint32_t)g.off[v[q] + 1] - ov[q];
-        }
-        uint32_t up[U], vp[U];
-#pragma unroll
-        for (int q = 0; q < U; ++q) {
-            if (!act[q]) {  // an idle lane's slot may have zero weight: no divisions
-                up[q] = vp[q] = 0;
-                continue;
-            }
-            const uint64_t o = d[q].r - below[q];
-            const uint32_t s = d[q].lo;
-            const uint32_t j = s - ou[q];  // position of v in row u
-            if (!CENTERED) {
-                // o in [0, (d_u-1)(d_v-1)): u' is the a-th of N(u)\{v} (v's
-                // own position stands for the row's last entry), v' the b-th of
-                // N(v)\{u}
-                uint64_t a, b;
-                divmod_small(o, dv[q] - 1, a, b);
-                up[q] = g.col[ou[q] + ((uint32_t)a == j ? du[q] - 1 : (uint32_t)a)];
-                vp[q] = g.col[ov[q] + (uint32_t)b];
-            } else {
-                // o in [0, L_uv L_vu): u' among the L_uv neighbours of u after
-                // v, v' among the L_vu neighbours of v after u (row suffixes)
-                const uint32_t luv = du[q] - 1 - j;
-                uint64_t lvu, rem, a, b;
-                divmod_small(cur[q] - below[q], luv, lvu, rem);
-                divmod_small(o, (uint32_t)lvu, a, b);
-                up[q] = g.col[s + 1 + (uint32_t)a];
-                vp[q] = g.col[ov[q] + (dv[q] - (uint32_t)lvu) + (uint32_t)b];
-            }
-        }
-        if (!CENTERED) {
-#pragma unroll
-            for (int q = 0; q < U; ++q)
-                if (act[q] && vp[q] == u[q]) vp[q] = g.col[ov[q] + dv[q] - 1];
-        }
-
-        uint32_t cls[U];
-#pragma unroll
-        for (int q = 0; q < U; ++q) {
-            if (!act[q] || up[q] == vp[q]) {
-                cls[q] = PM_TALLY_TRI;
-                continue;
-            }
-            if (!CENTERED) {
-                // x = [u'~v], y = [u~v'], z = [u'~v']
-                const RowSearch sx = row_search(g.off, v[q], ov[q], ov[q] + dv[q], up[q]);
-                const RowSearch sy = row_search(g.off, u[q], ou[q], ou[q] + du[q], vp[q]);
-                const RowSearch sz = row_search2(g.off, up[q], vp[q]);
-                const uint32_t x = ladder_contains(g.ladder, sx.lo, sx.hi, sx.key);
-                const uint32_t y = ladder_contains(g.ladder, sy.lo, sy.hi, sy.key);
-                const uint32_t z = ladder_contains(g.ladder, sz.lo, sz.hi, sz.key);
-                const uint32_t e = x + y + z;
-                // 3 edges: 3-path; 4: 4-cycle with the closing edge, else
-                // tailed triangle; 5: chordal-4-cycle; 6: 4-clique
-                cls[q] = e == 0 ? 2u : e == 1 ? (z ? 4u : 3u) : e == 2 ? 5u : 6u;
-            } else {
-                // centered iff u'~v' (Definition 4.1); then the chords u'~v
-                // and u~v', searched in the rows of v and u (v < u', u < v')
-                const RowSearch sz = row_search2(g.off, up[q], vp[q]);
-                if (!ladder_contains(g.ladder, sz.lo, sz.hi, sz.key)) {
-                    cls[q] = PM_TALLY_OPEN;
-                    continue;
-                }
-                const uint32_t x = ladder_contains(g.ladder, ov[q], ov[q] + dv[q], up[q]);
-                const uint32_t y = ladder_contains(g.ladder, ou[q], ou[q] + du[q], vp[q]);
-                cls[q] = 4u + x + y;
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < U; ++q)
-            if (act[q]) {
-#pragma unroll
-                for (int c = 0; c < PM_NUM_TALLIES; ++c) cnt[c] += (cls[q] == (uint32_t)c);
-            }
     }
-
-#pragma unroll
-    for (int c = 0; c < PM_NUM_TALLIES; ++c) {
-        uint32_t t = wave_sum_u32(cnt[c]);
-        if (lane_id() == 0 && t) atomicAdd(&tally[c], (unsigned long long)t);
-    }
+    tally_flush(cnt, tally);
 }
 
 // launch shape of the samplers (pm_set_sampler_shape)
@@ -218,7 +57,7 @@ static void launch_k_sample(unsigned blocks, hipStream_t s, const SamplerView &v
                        (unsigned long long *)tally);
 }
 
-static int cu_count(int dev)
+int sampler_cu_count(int dev)
 {
     static std::mutex mu;
     static int cache[64] = {0};
@@ -239,7 +78,7 @@ static pm_status launch_sampler(const pm_graph *g, bool centered, uint64_t seed,
     if (v.R == 0 || k == 0) return PM_OK;
     const int U = g_samples_per_lane.load();
     const uint64_t want = (k + (uint64_t)kBlock * U - 1) / ((uint64_t)kBlock * U);
-    const uint64_t cap = (uint64_t)cu_count(g->device) * (uint64_t)g_blocks_per_cu.load();
+    const uint64_t cap = (uint64_t)sampler_cu_count(g->device) * (uint64_t)g_blocks_per_cu.load();
     const unsigned blocks = (unsigned)std::max<uint64_t>(1, std::min(want, cap));
     ProfScope prof(centered ? "sample_centered" : "sample_path", s);
     switch (U * 2 + (centered ? 1 : 0)) {

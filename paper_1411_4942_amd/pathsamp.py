@@ -57,6 +57,10 @@ class ProfileEntry(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double)]
 
 
+class Tune(ctypes.Structure):
+    _fields_ = [("samples_per_tile", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
+
+
 class GraphInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("dmax", ctypes.c_int64), ("isolated", ctypes.c_int64),
                 ("W", ctypes.c_uint64), ("Lambda", ctypes.c_uint64), ("N1", ctypes.c_uint64),
@@ -87,6 +91,12 @@ _SIGNATURES = {
     "pm_release_cached_memory": (ctypes.c_int32, []),
     "pm_profile_enable": (ctypes.c_int32, [ctypes.c_int32]),
     "pm_profile_read": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "pm_batch_create": (ctypes.c_int32, [_P, _P, ctypes.c_int32, _P, _P, ctypes.POINTER(_P)]),
+    "pm_batch_set_params": (ctypes.c_int32, [_P, _P]),
+    "pm_batch_run": (ctypes.c_int32, [_P, _P, _P]),
+    "pm_batch_get_tune": (ctypes.c_int32, [_P, ctypes.POINTER(Tune)]),
+    "pm_batch_destroy": (ctypes.c_int32, [_P]),
+    "pm_count_batch": (ctypes.c_int32, [_P, _P, _P, ctypes.c_int32, _P, _P]),
     "pm_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "pm_last_error": (ctypes.c_char_p, []),
 }
@@ -209,6 +219,71 @@ class Graph:
             self.destroy()
         except Exception:
             pass
+
+
+def make_params(k_path: int, k_cent: int | None = None, seed: int = 1, first_path: int = 0, first_cent: int = 0,
+                delta: float = 0.01) -> Params:
+    return Params(k_path, k_path if k_cent is None else k_cent, seed, first_path, first_cent, delta)
+
+
+def _params_array(params):
+    arr = (Params * len(params))()
+    for i, p in enumerate(params):
+        arr[i] = p if isinstance(p, Params) else make_params(**p)
+    return arr
+
+
+def _graph_array(graphs):
+    arr = (ctypes.c_void_p * len(graphs))()
+    for i, g in enumerate(graphs):
+        arr[i] = g.handle.value
+    return arr
+
+
+class Batch:
+    """pm_batch: many prepared graphs sampled by one captured persistent launch."""
+
+    def __init__(self, graphs, params, tune=None, stream=None):
+        self._graphs = list(graphs)  # keep the handles alive
+        self.count = len(self._graphs)
+        ga, pa = _graph_array(self._graphs), _params_array(params)
+        t = None if tune is None else ctypes.byref(Tune(*tune))
+        h = ctypes.c_void_p()
+        _check(lib().pm_batch_create(ga, pa, self.count, t, _stream_ptr(stream), ctypes.byref(h)), "pm_batch_create")
+        self._h = h
+
+    def set_params(self, params):
+        _check(lib().pm_batch_set_params(self._h, _params_array(params)), "pm_batch_set_params")
+
+    def run(self, stream=None) -> list:
+        out = (Result * self.count)()
+        _check(lib().pm_batch_run(self._h, out, _stream_ptr(stream)), "pm_batch_run")
+        return [r.to_dict() for r in out]
+
+    def tune(self):
+        t = Tune()
+        _check(lib().pm_batch_get_tune(self._h, ctypes.byref(t)), "pm_batch_get_tune")
+        return (t.samples_per_tile, t.blocks_per_cu)
+
+    def destroy(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _check(lib().pm_batch_destroy(self._h), "pm_batch_destroy")
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def count_batch(graphs, params, tune=None, stream=None) -> list:
+    """pm_count_batch: one-shot batched count."""
+    ga, pa = _graph_array(graphs), _params_array(params)
+    out = (Result * len(graphs))()
+    t = None if tune is None else ctypes.byref(Tune(*tune))
+    _check(lib().pm_count_batch(ga, pa, out, len(graphs), t, _stream_ptr(stream)), "pm_count_batch")
+    return [r.to_dict() for r in out]
 
 
 def count_motifs(off, col, k: int, seed: int = 1) -> dict:
