@@ -194,6 +194,117 @@ pm_status pm_count_batch(const pm_graph *const *graphs, const pm_params *params,
                          const pm_tune *tune, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Served mode: continuous batching of motif-count requests                  */
+/* ------------------------------------------------------------------------ */
+
+/* A server owns registered graphs, prepares them on the device when a
+ * request needs them (and keeps them resident within an HBM budget), and
+ * runs requests in steps: each step is one persistent launch over work tiles
+ * of every active request, so requests that arrive while others run are
+ * admitted between steps and share the device with them.  A request either
+ * gives its sample budgets or asks for a relative error: then its first
+ * k_pilot ids per sampler are a pilot from which k is sized with
+ * Corollary 5.3 (pm_samples_for_request) and the ids [k_pilot, k) follow.
+ * A finished request's result is bit-for-bit pm_count with its final
+ * (k_path, k_cent, seed, first ids 0, delta): tallies are sums over ids, so
+ * how the ids are cut into steps does not matter. */
+typedef struct pm_server pm_server;
+
+typedef struct {
+    uint64_t hbm_budget;     /* bytes for resident prepared graphs (0: 3/4 of free device memory) */
+    int32_t max_active;      /* requests on the device at once (0: 256) */
+    int32_t max_graphs;      /* registered graphs (0: 1024) */
+    uint64_t step_samples;   /* samples per step shared by the active requests (0: 2^25) */
+    uint64_t k_pilot;        /* pilot ids per sampler (0: 65536) */
+    uint64_t k_max;          /* cap on a sized budget, per sampler (0: 2e9) */
+    int32_t samples_per_tile;  /* work tile (0: 4096) */
+    int32_t blocks_per_cu;     /* resident blocks per compute unit (0: 4) */
+} pm_server_cfg;
+
+typedef struct {
+    uint32_t graph;       /* id from pm_server_add_graph */
+    uint32_t motif_mask;  /* bit i (i = 1..6): size k for motif i; 0 means all six */
+    double rel_err;       /* requested relative error, (0,1) (ignored with fixed budgets) */
+    double delta;         /* failure probability per motif, (0,1) */
+    uint64_t seed;        /* Philox key */
+    uint64_t k_path;      /* fixed budgets: if either is non-zero both are used as */
+    uint64_t k_cent;      /* given and no pilot is run */
+} pm_request;
+
+typedef struct {
+    double queued_ms;      /* submit to admission */
+    double latency_ms;     /* submit to result */
+    uint64_t k_path, k_cent; /* final budgets */
+    uint32_t steps;        /* device steps that carried its work */
+    uint32_t capped_mask;  /* bit i: motif i needed more than k_max (its bar is what k_max gives) */
+    uint32_t unseen_mask;  /* bit i: motif i had no pilot hit (sized from the pilot's upper bound) */
+    int32_t prepared;      /* 1: its admission prepared (or re-prepared) the graph */
+} pm_req_stats;
+
+typedef struct {
+    uint64_t steps, samples, requests_done;
+    uint64_t resident_bytes, resident_graphs, preparations, evictions;
+    double busy_ms;        /* sum of step durations (device events) */
+} pm_server_stats;
+
+/* Create a server on the current device; its worker thread starts at once.
+ * cfg may be NULL (all defaults).  Errors: PM_EINVAL, PM_ENOMEM, PM_EDEVICE. */
+pm_status pm_server_create(const pm_server_cfg *cfg, pm_server **out);
+
+/* Register a graph.  The CSR buffers (host or device) are read when the graph
+ * is prepared, which may happen again after an eviction: they must stay
+ * valid and unchanged until pm_server_destroy.  flags as for
+ * pm_graph_create.  Errors: PM_EINVAL (null, too many graphs). */
+pm_status pm_server_add_graph(pm_server *srv, const pm_csr_view *csr, uint32_t flags, uint32_t *graph_id);
+
+/* Prepare a registered graph now (blocking).  PM_EBUSY when it cannot fit
+ * beside the graphs pinned by active requests, PM_ENOMEM when it exceeds the
+ * budget alone, or the pm_graph_create error for an invalid graph. */
+pm_status pm_server_preload(pm_server *srv, uint32_t graph_id);
+
+/* Queue a request (non-blocking); admission is first come, first served,
+ * when a slot is free and the graph is resident or fits the budget after
+ * evicting idle graphs (least recently used first).  Errors: PM_EINVAL
+ * (unknown graph, rel_err or delta outside (0,1) when sizing), PM_ECANCELED
+ * (server shutting down). */
+pm_status pm_server_submit(pm_server *srv, const pm_request *req, uint64_t *ticket);
+
+/* Wait for a request and release its ticket.  timeout_ms < 0 waits for
+ * ever; on timeout PM_EBUSY is returned and the ticket stays valid.  The
+ * request's own status is returned otherwise (PM_OK, PM_ECANCELED, the error
+ * of preparing its graph, PM_ENOMEM if its graph exceeds the budget alone).
+ * out and st may be NULL. */
+pm_status pm_server_wait(pm_server *srv, uint64_t ticket, int64_t timeout_ms, pm_result *out, pm_req_stats *st);
+
+/* Cancel a queued or running request (its wait returns PM_ECANCELED unless
+ * it already finished). */
+pm_status pm_server_cancel(pm_server *srv, uint64_t ticket);
+
+pm_status pm_server_get_stats(pm_server *srv, pm_server_stats *out);
+
+/* Cancel what is left, stop the worker, free every prepared graph.  No
+ * other call on this server may be in progress or follow. */
+pm_status pm_server_destroy(pm_server *srv);
+
+/* The sizing rule of the served mode.  From pilot tallies over k0 ids per
+ * sampler: alpha_i = t_i / k0 for the motifs of mask (2, 3 from the 3-path
+ * sampler; 4, 5, 6 from the centered one); a motif with no hit uses the
+ * upper end p_u of its Definition 5.2 interval instead (bit i of *unseen);
+ * k_i = pm_samples_for_error(rel_err, delta, alpha_i).  Motif 1 is the
+ * difference N_1 - C_3 - 2 C_5 - 4 C_6 of Algorithm 2: its error budget
+ * rel_err * est_1 (pilot estimates) is split evenly over the h terms with a
+ * hit, term j sized at relative error rel_err * est_1 / (h c_j est_j),
+ * c = (1, 2, 4), when that is below 1; est_1 <= 0 sets bit 1 of *capped.
+ * alpha = 1 uses D(1, 1 - e) = ln(1 / (1 - e)).  A sampler's k is the
+ * largest k_i of its motifs and at least k0; a k_i above k_max becomes k_max
+ * (bit i of *capped).  A sampler of zero total weight gets k0.  Errors:
+ * PM_EINVAL (null, k0 = 0, k_max < k0, rel_err or delta outside (0,1)). */
+pm_status pm_samples_for_request(const uint64_t tally_path[PM_NUM_TALLIES], const uint64_t tally_cent[PM_NUM_TALLIES],
+                                 uint64_t k0, uint64_t W, uint64_t Lambda, uint64_t N1, uint32_t motif_mask,
+                                 double rel_err, double delta, uint64_t k_max, uint64_t *k_path, uint64_t *k_cent,
+                                 uint32_t *capped, uint32_t *unseen);
+
+/* ------------------------------------------------------------------------ */
 /* Host-side estimates and error bars                                        */
 /* ------------------------------------------------------------------------ */
 

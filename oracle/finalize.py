@@ -48,12 +48,17 @@ def chernoff_interval(count: int, k: int, delta: float):
         raise ValueError("k must be positive")
     if not (0.0 < delta < 1.0):
         raise ValueError("delta must lie in (0, 1)")
-    target = math.log(1.0 / delta) / k
     if count == 0:
         return 0.0, 1.0 - delta ** (1.0 / k)
     if count == k:
         return delta ** (1.0 / k), 1.0
-    alpha = count / k
+    return chernoff_interval_alpha(count / k, k, delta)
+
+
+def chernoff_interval_alpha(alpha: float, k: int, delta: float):
+    """The two roots of k D(alpha, p) = ln(1/delta) for a proportion
+    0 < alpha < 1 given as a real number (Definition 5.2)."""
+    target = math.log(1.0 / delta) / k
 
     def solve(lo, hi, increasing):
         # root of D(alpha, p) = target on [lo, hi]; D is monotone there
@@ -148,3 +153,76 @@ def finalize(tally_path, tally_cent, R_tau: int, R_lam: int, N1: int, k_path: in
         "hi": hi,
         "est_basic": est_basic,
     }
+
+
+def samples_for_error(rel_err: float, delta: float, alpha: float) -> int:
+    """Smallest k with k min(D(alpha, alpha(1-e)), D(alpha, alpha(1+e))) >=
+    ln(1/delta): the bar of Corollary 5.3 around alpha stays within relative
+    error e on both sides (the side above 1 does not bind)."""
+    d = kl_bernoulli(alpha, alpha * (1.0 - rel_err))
+    if alpha * (1.0 + rel_err) < 1.0:
+        d = min(d, kl_bernoulli(alpha, alpha * (1.0 + rel_err)))
+    return math.ceil(math.log(1.0 / delta) / d)
+
+
+def samples_for_request(tally_path, tally_cent, k0: int, W: int, Lambda: int, N1: int, mask: int,
+                        rel_err: float, delta: float, k_max: int):
+    """Budgets (k_path, k_cent, capped, unseen) of the served mode from pilot
+    tallies over k0 ids per sampler.
+
+    Motifs 2, 3 are sized on the 3-path sampler's proportions and 4, 5, 6 on
+    the centered sampler's, each at relative error rel_err; a motif without a
+    pilot hit takes the upper root p_u of its interval as its proportion.
+    Motif 1 is N_1 - C_3 - 2 C_5 - 4 C_6 (Algorithm 2): its allowed error
+    rel_err * C^_1 is shared equally by the h terms with a hit, term j sized at
+    relative error rel_err C^_1 / (h c_j C^_j) when that is below 1.  Each
+    sampler's k is its largest requirement, at least k0, at most k_max."""
+    if mask == 0:
+        mask = 0x7E
+    capped = unseen = 0
+    need = [0] * 7
+    p_unseen = 1.0 - delta ** (1.0 / k0)
+
+    def size(i, t, eps):
+        nonlocal unseen
+        if t == 0:
+            unseen |= 1 << i
+            alpha = p_unseen
+        else:
+            alpha = t / k0
+        if alpha >= 1.0:
+            return math.ceil(math.log(1.0 / delta) / kl_bernoulli(1.0, 1.0 - eps))
+        return samples_for_error(eps, delta, alpha)
+
+    tp = [int(x) for x in tally_path]
+    tc = [int(x) for x in tally_cent]
+    if W:
+        for i in (2, 3):
+            if mask >> i & 1:
+                need[i] = size(i, tp[i], rel_err)
+        if mask >> 1 & 1:
+            terms = ((3, 1.0), (5, 2.0), (6, 4.0))
+            est = {j: tp[j] * W / (k0 * A2[j]) for j, _ in terms}
+            hits = sum(1 for j, _ in terms if tp[j])
+            est1 = N1 - est[3] - 2.0 * est[5] - 4.0 * est[6]
+            if not est1 > 0.0:
+                capped |= 2
+            else:
+                for j, c in terms:
+                    if tp[j] == 0:
+                        continue
+                    eps = rel_err * est1 / (hits * c * est[j])
+                    if eps < 1.0:
+                        need[1] = max(need[1], size(1, tp[j], eps))
+    if Lambda:
+        for i in (4, 5, 6):
+            if mask >> i & 1:
+                need[i] = size(i, tc[i], rel_err)
+    k = [k0, k0]
+    for i in range(1, 7):
+        if need[i] > k_max:
+            capped |= 1 << i
+            need[i] = k_max
+        side = 0 if i <= 3 else 1
+        k[side] = max(k[side], need[i])
+    return k[0], k[1], capped, unseen

@@ -18,7 +18,7 @@
 #include <new>
 #include <vector>
 
-#include "graph.hpp"
+#include "batch.hpp"
 #include "profile.hpp"
 #include "sampler.hpp"
 
@@ -28,24 +28,6 @@ pm_status finalize(const uint64_t tp[PM_NUM_TALLIES], const uint64_t tc[PM_NUM_T
                    uint64_t Lambda, uint64_t N1, uint64_t k_path, uint64_t k_cent, double delta, pm_result *out);
 pm_status check_device(const pm_graph *g);
 int sampler_cu_count(int dev);
-
-struct BatchGraph {
-    SamplerView v[2];  // 3-path, centered
-};
-
-struct BatchTile {
-    uint32_t graph;
-    uint32_t tag;    // 0 3-path sampler, 1 centered sampler
-    uint32_t count;  // samples
-    uint32_t pad;
-    uint64_t first;  // first sample id
-    uint64_t seed;
-};
-
-struct BatchCtl {
-    uint32_t ntiles;
-    uint32_t cursor;
-};
 
 __global__ __launch_bounds__(kBlock) void k_sample_batch(const BatchGraph *__restrict__ graphs,
                                                          const BatchTile *__restrict__ tiles, BatchCtl *ctl,
@@ -72,8 +54,17 @@ __global__ __launch_bounds__(kBlock) void k_sample_batch(const BatchGraph *__res
             for (uint32_t i = threadIdx.x; i < T.count; i += blockDim.x)
                 tally_add(cnt, sample_class<true>(g, T.seed, T.first + i));
         }
-        tally_flush(cnt, tallies + ((uint64_t)T.graph * 2 + T.tag) * PM_NUM_TALLIES);
+        tally_flush(cnt, tallies + ((uint64_t)T.slot * 2 + T.tag) * PM_NUM_TALLIES);
     }
+}
+
+pm_status launch_tiles(const BatchGraph *graphs, const BatchTile *tiles, BatchCtl *ctl, uint64_t *tallies,
+                       unsigned blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sample_batch, dim3(blocks), dim3(kBlock), 0, s, graphs, tiles, ctl,
+                       (unsigned long long *)tallies);
+    PM_HIP(hipGetLastError());
+    return PM_OK;
 }
 
 }  // namespace pm
@@ -131,7 +122,7 @@ uint32_t fill_tiles(pm_batch *b, uint32_t per)
                 t.graph = (uint32_t)i;
                 t.tag = (uint32_t)tag;
                 t.count = (uint32_t)std::min<uint64_t>(per, k - done);
-                t.pad = 0;
+                t.slot = (uint32_t)i;
                 t.first = first + done;
                 t.seed = b->params[i].seed;
             }
@@ -180,9 +171,7 @@ pm_status enqueue_run(pm_batch *b)
     PM_HIP(hipMemcpyAsync(b->d_tiles, b->h_tiles, sizeof(BatchTile) * b->tile_cap, hipMemcpyHostToDevice, b->stream));
     PM_HIP(hipMemcpyAsync(b->d_ctl, b->h_ctl, sizeof(BatchCtl), hipMemcpyHostToDevice, b->stream));
     PM_TRY(fill_async<uint64_t>(b->d_tallies, 0ull, (int64_t)b->count * 2 * PM_NUM_TALLIES, b->stream));
-    hipLaunchKernelGGL(k_sample_batch, dim3(b->blocks), dim3(kBlock), 0, b->stream, b->d_graphs, b->d_tiles,
-                       b->d_ctl, (unsigned long long *)b->d_tallies);
-    PM_HIP(hipGetLastError());
+    PM_TRY(launch_tiles(b->d_graphs, b->d_tiles, b->d_ctl, b->d_tallies, b->blocks, b->stream));
     PM_HIP(hipMemcpyAsync(b->h_tallies, b->d_tallies, sizeof(uint64_t) * b->count * 2 * PM_NUM_TALLIES,
                           hipMemcpyDeviceToHost, b->stream));
     return PM_OK;

@@ -15,6 +15,7 @@ namespace pm {
 static thread_local std::string t_last_error;
 
 void set_error(const std::string &msg) { t_last_error = msg; }
+std::string last_error_text() { return t_last_error; }
 
 pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm_graph **out);
 void graph_free(pm_graph *g, hipStream_t s);
@@ -37,6 +38,17 @@ pm_status batch_set_params(pm_batch *b, const pm_params *params);
 pm_status batch_run(pm_batch *b, pm_result *out, hipStream_t user_stream);
 pm_status batch_get_tune(const pm_batch *b, pm_tune *out);
 pm_status batch_destroy(pm_batch *b);
+pm_status samples_for_request(const uint64_t tp[PM_NUM_TALLIES], const uint64_t tc[PM_NUM_TALLIES], uint64_t k0,
+                              uint64_t W, uint64_t Lambda, uint64_t N1, uint32_t mask, double rel_err, double delta,
+                              uint64_t k_max, uint64_t *k_path, uint64_t *k_cent, uint32_t *capped, uint32_t *unseen);
+pm_status server_create(const pm_server_cfg *cfg, pm_server **out);
+pm_status server_add_graph(pm_server *S, const pm_csr_view *csr, uint32_t flags, uint32_t *gid);
+pm_status server_preload(pm_server *S, uint32_t gid);
+pm_status server_submit(pm_server *S, const pm_request *q, uint64_t *ticket);
+pm_status server_wait(pm_server *S, uint64_t ticket, int64_t timeout_ms, pm_result *out, pm_req_stats *st);
+pm_status server_cancel(pm_server *S, uint64_t ticket);
+pm_status server_get_stats(pm_server *S, pm_server_stats *out);
+pm_status server_destroy(pm_server *S);
 
 }  // namespace pm
 
@@ -155,6 +167,55 @@ pm_status pm_chernoff_interval(uint64_t count, uint64_t k, double delta, double 
 pm_status pm_samples_for_error(double rel_err, double delta, double alpha, uint64_t *k_out)
 {
     PM_GUARD(return pm::samples_for_error(rel_err, delta, alpha, k_out);)
+}
+
+pm_status pm_samples_for_request(const uint64_t tally_path[PM_NUM_TALLIES], const uint64_t tally_cent[PM_NUM_TALLIES],
+                                 uint64_t k0, uint64_t W, uint64_t Lambda, uint64_t N1, uint32_t motif_mask,
+                                 double rel_err, double delta, uint64_t k_max, uint64_t *k_path, uint64_t *k_cent,
+                                 uint32_t *capped, uint32_t *unseen)
+{
+    PM_GUARD(return pm::samples_for_request(tally_path, tally_cent, k0, W, Lambda, N1, motif_mask, rel_err, delta,
+                                            k_max, k_path, k_cent, capped, unseen);)
+}
+
+pm_status pm_server_create(const pm_server_cfg *cfg, pm_server **out)
+{
+    PM_GUARD(return pm::server_create(cfg, out);)
+}
+
+pm_status pm_server_add_graph(pm_server *srv, const pm_csr_view *csr, uint32_t flags, uint32_t *graph_id)
+{
+    PM_GUARD(return pm::server_add_graph(srv, csr, flags, graph_id);)
+}
+
+pm_status pm_server_preload(pm_server *srv, uint32_t graph_id)
+{
+    PM_GUARD(return pm::server_preload(srv, graph_id);)
+}
+
+pm_status pm_server_submit(pm_server *srv, const pm_request *req, uint64_t *ticket)
+{
+    PM_GUARD(return pm::server_submit(srv, req, ticket);)
+}
+
+pm_status pm_server_wait(pm_server *srv, uint64_t ticket, int64_t timeout_ms, pm_result *out, pm_req_stats *st)
+{
+    PM_GUARD(return pm::server_wait(srv, ticket, timeout_ms, out, st);)
+}
+
+pm_status pm_server_cancel(pm_server *srv, uint64_t ticket)
+{
+    PM_GUARD(return pm::server_cancel(srv, ticket);)
+}
+
+pm_status pm_server_get_stats(pm_server *srv, pm_server_stats *out)
+{
+    PM_GUARD(return pm::server_get_stats(srv, out);)
+}
+
+pm_status pm_server_destroy(pm_server *srv)
+{
+    PM_GUARD(return pm::server_destroy(srv);)
 }
 
 pm_status pm_set_sampler_shape(int32_t samples_per_lane, int32_t blocks_per_cu)

@@ -12,6 +12,8 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <algorithm>
+#include <string>
 
 #include "../../include/pathsamp.h"
 
@@ -154,6 +156,89 @@ pm_status samples_for_error(double rel_err, double delta, double alpha, uint64_t
     if (up < 1.0) d = std::fmin(d, kl(alpha, up));
     const double k = std::ceil(std::log(1.0 / delta) / d);
     *k_out = (k >= 1.8e19) ? UINT64_MAX : (uint64_t)k;
+    return PM_OK;
+}
+
+namespace {
+
+// k of pm_samples_for_error, extended to alpha = 1 (only the lower side
+// binds: D(1, 1 - e) = ln(1 / (1 - e))) and saturating instead of failing
+uint64_t k_for(double rel_err, double delta, double alpha)
+{
+    if (alpha >= 1.0) {
+        const double k = std::ceil(std::log(1.0 / delta) / -std::log1p(-rel_err));
+        return k >= 1.8e19 ? UINT64_MAX : (uint64_t)k;
+    }
+    uint64_t k = UINT64_MAX;
+    (void)samples_for_error(rel_err, delta, alpha, &k);
+    return k;
+}
+
+}  // namespace
+
+pm_status samples_for_request(const uint64_t tp[PM_NUM_TALLIES], const uint64_t tc[PM_NUM_TALLIES], uint64_t k0,
+                              uint64_t W, uint64_t Lambda, uint64_t N1, uint32_t mask, double rel_err, double delta,
+                              uint64_t k_max, uint64_t *k_path, uint64_t *k_cent, uint32_t *capped, uint32_t *unseen)
+{
+    if (!tp || !tc || !k_path || !k_cent || !capped || !unseen || k0 == 0 || k_max < k0 ||
+        !(rel_err > 0.0 && rel_err < 1.0) || !(delta > 0.0 && delta < 1.0)) {
+        set_error("samples_for_request: need k0 > 0, k_max >= k0, rel_err and delta in (0,1)");
+        return PM_EINVAL;
+    }
+    if (mask == 0) mask = 0x7e;
+    *capped = 0;
+    *unseen = 0;
+    uint64_t need[7] = {0};
+    // p_u of Definition 5.2 for a proportion observed as 0 in k0 samples
+    const double p_unseen = 1.0 - std::pow(delta, 1.0 / (double)k0);
+    auto size_one = [&](int i, uint64_t t, double eps) -> uint64_t {
+        double alpha = (double)t / (double)k0;
+        if (t == 0) {
+            alpha = p_unseen;
+            *unseen |= 1u << i;
+        }
+        return k_for(eps, delta, alpha);
+    };
+    if (W != 0) {
+        for (int i = 2; i <= 3; ++i)
+            if (mask & (1u << i)) need[i] = size_one(i, tp[i], rel_err);
+        if (mask & 2u) {
+            // C_1 = N_1 - C_3 - 2 C_5 - 4 C_6 (Algorithm 2's estimates): split
+            // the error budget over the terms that had a hit
+            const int terms[3] = {3, 5, 6};
+            const double coef[3] = {1.0, 2.0, 4.0};
+            double est[3];
+            int hits = 0;
+            for (int j = 0; j < 3; ++j) {
+                est[j] = (double)tp[terms[j]] * (double)W / ((double)k0 * kA2[terms[j]]);
+                if (tp[terms[j]] != 0) ++hits;
+            }
+            const double est1 = (double)N1 - est[0] - 2.0 * est[1] - 4.0 * est[2];
+            if (!(est1 > 0.0)) {
+                *capped |= 2u;  // no relative error can be promised
+            } else {
+                for (int j = 0; j < 3; ++j) {
+                    if (tp[terms[j]] == 0) continue;
+                    const double eps = rel_err * est1 / (hits * coef[j] * est[j]);
+                    if (eps < 1.0) need[1] = std::max(need[1], size_one(1, tp[terms[j]], eps));
+                }
+            }
+        }
+    }
+    if (Lambda != 0)
+        for (int i = 4; i <= 6; ++i)
+            if (mask & (1u << i)) need[i] = size_one(i, tc[i], rel_err);
+    uint64_t kp = k0, kc = k0;
+    for (int i = 1; i <= 6; ++i) {
+        uint64_t &k = i <= 3 ? kp : kc;
+        if (need[i] > k_max) {
+            *capped |= 1u << i;
+            need[i] = k_max;
+        }
+        k = std::max(k, need[i]);
+    }
+    *k_path = kp;
+    *k_cent = kc;
     return PM_OK;
 }
 

@@ -447,6 +447,21 @@ void graph_free(pm_graph *g, hipStream_t s)
     delete g;
 }
 
+// Device bytes a prepared graph of n vertices and `slots` directed slots
+// holds (what graph_create adds up in pm_graph::bytes).
+uint64_t graph_bytes_for(int64_t n, int64_t slots)
+{
+    const uint64_t nn = (uint64_t)std::max<int64_t>(n, 1), ss = (uint64_t)std::max<int64_t>(slots, 1);
+    uint64_t b = 4 * nn + 4 * nn + 8 * ((uint64_t)n + 1);
+    const int top = ladder_top_for(slots);
+    uint64_t total = 0;
+    for (int l = 1; l <= top; ++l) total += (ladder_count(slots, l) + 31) / 32 * 32;
+    if (top > 0) b += 4 * (total + 32);
+    b += 12 * ss + 16 * ss;
+    b += 2 * 4 * (guide_target(slots) + 1);
+    return b;
+}
+
 pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm_graph **out)
 {
     (void)flags;  // every check always runs: later kernels rely on them

@@ -61,6 +61,36 @@ class Tune(ctypes.Structure):
     _fields_ = [("samples_per_tile", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
 
 
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("max_active", ctypes.c_int32), ("max_graphs", ctypes.c_int32),
+                ("step_samples", ctypes.c_uint64), ("k_pilot", ctypes.c_uint64), ("k_max", ctypes.c_uint64),
+                ("samples_per_tile", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("graph", ctypes.c_uint32), ("motif_mask", ctypes.c_uint32), ("rel_err", ctypes.c_double),
+                ("delta", ctypes.c_double), ("seed", ctypes.c_uint64), ("k_path", ctypes.c_uint64),
+                ("k_cent", ctypes.c_uint64)]
+
+
+class ReqStats(ctypes.Structure):
+    _fields_ = [("queued_ms", ctypes.c_double), ("latency_ms", ctypes.c_double), ("k_path", ctypes.c_uint64),
+                ("k_cent", ctypes.c_uint64), ("steps", ctypes.c_uint32), ("capped_mask", ctypes.c_uint32),
+                ("unseen_mask", ctypes.c_uint32), ("prepared", ctypes.c_int32)]
+
+    def to_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_uint64), ("samples", ctypes.c_uint64), ("requests_done", ctypes.c_uint64),
+                ("resident_bytes", ctypes.c_uint64), ("resident_graphs", ctypes.c_uint64),
+                ("preparations", ctypes.c_uint64), ("evictions", ctypes.c_uint64), ("busy_ms", ctypes.c_double)]
+
+    def to_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class GraphInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("dmax", ctypes.c_int64), ("isolated", ctypes.c_int64),
                 ("W", ctypes.c_uint64), ("Lambda", ctypes.c_uint64), ("N1", ctypes.c_uint64),
@@ -97,6 +127,21 @@ _SIGNATURES = {
     "pm_batch_get_tune": (ctypes.c_int32, [_P, ctypes.POINTER(Tune)]),
     "pm_batch_destroy": (ctypes.c_int32, [_P]),
     "pm_count_batch": (ctypes.c_int32, [_P, _P, _P, ctypes.c_int32, _P, _P]),
+    "pm_samples_for_request": (ctypes.c_int32, [_P, _P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                                ctypes.c_uint64, ctypes.c_uint32, ctypes.c_double, ctypes.c_double,
+                                                ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64),
+                                                ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint32),
+                                                ctypes.POINTER(ctypes.c_uint32)]),
+    "pm_server_create": (ctypes.c_int32, [ctypes.POINTER(ServerCfg), ctypes.POINTER(_P)]),
+    "pm_server_add_graph": (ctypes.c_int32, [_P, ctypes.POINTER(CsrView), ctypes.c_uint32,
+                                             ctypes.POINTER(ctypes.c_uint32)]),
+    "pm_server_preload": (ctypes.c_int32, [_P, ctypes.c_uint32]),
+    "pm_server_submit": (ctypes.c_int32, [_P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
+    "pm_server_wait": (ctypes.c_int32, [_P, ctypes.c_uint64, ctypes.c_int64, ctypes.POINTER(Result),
+                                        ctypes.POINTER(ReqStats)]),
+    "pm_server_cancel": (ctypes.c_int32, [_P, ctypes.c_uint64]),
+    "pm_server_get_stats": (ctypes.c_int32, [_P, ctypes.POINTER(ServerStats)]),
+    "pm_server_destroy": (ctypes.c_int32, [_P]),
     "pm_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "pm_last_error": (ctypes.c_char_p, []),
 }
@@ -284,6 +329,80 @@ def count_batch(graphs, params, tune=None, stream=None) -> list:
     t = None if tune is None else ctypes.byref(Tune(*tune))
     _check(lib().pm_count_batch(ga, pa, out, len(graphs), t, _stream_ptr(stream)), "pm_count_batch")
     return [r.to_dict() for r in out]
+
+
+def samples_for_request(tally_path, tally_cent, k0: int, W: int, Lambda: int, N1: int, motif_mask: int,
+                        rel_err: float, delta: float, k_max: int):
+    """pm_samples_for_request: (k_path, k_cent, capped_mask, unseen_mask)."""
+    tp = (ctypes.c_uint64 * NUM_TALLIES)(*[int(x) for x in tally_path])
+    tc = (ctypes.c_uint64 * NUM_TALLIES)(*[int(x) for x in tally_cent])
+    kp, kc = ctypes.c_uint64(), ctypes.c_uint64()
+    cap, uns = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(lib().pm_samples_for_request(tp, tc, k0, W, Lambda, N1, motif_mask, rel_err, delta, k_max,
+                                        ctypes.byref(kp), ctypes.byref(kc), ctypes.byref(cap), ctypes.byref(uns)),
+           "pm_samples_for_request")
+    return kp.value, kc.value, cap.value, uns.value
+
+
+class Server:
+    """pm_server: continuous batching of motif-count requests over registered graphs.
+
+    Registered CSR buffers (torch tensors or numpy arrays) are kept referenced
+    here, since the server may read them again after an eviction."""
+
+    def __init__(self, hbm_budget: int = 0, max_active: int = 0, max_graphs: int = 0, step_samples: int = 0,
+                 k_pilot: int = 0, k_max: int = 0, samples_per_tile: int = 0, blocks_per_cu: int = 0):
+        cfg = ServerCfg(hbm_budget, max_active, max_graphs, step_samples, k_pilot, k_max, samples_per_tile,
+                        blocks_per_cu)
+        h = ctypes.c_void_p()
+        _check(lib().pm_server_create(ctypes.byref(cfg), ctypes.byref(h)), "pm_server_create")
+        self._h = h
+        self._keep = []
+
+    def add_graph(self, off, col, flags: int = PM_VALIDATE | PM_CHECK_SYMMETRY) -> int:
+        view, keep = _csr_view(off, col)
+        gid = ctypes.c_uint32()
+        _check(lib().pm_server_add_graph(self._h, ctypes.byref(view), flags, ctypes.byref(gid)),
+               "pm_server_add_graph")
+        self._keep.append(keep)
+        return gid.value
+
+    def preload(self, gid: int):
+        _check(lib().pm_server_preload(self._h, gid), "pm_server_preload")
+
+    def submit(self, graph: int, rel_err: float = 0.01, delta: float = 0.01, seed: int = 1, motif_mask: int = 0,
+               k_path: int = 0, k_cent: int = 0) -> int:
+        rq = Request(graph, motif_mask, rel_err, delta, seed, k_path, k_cent)
+        t = ctypes.c_uint64()
+        _check(lib().pm_server_submit(self._h, ctypes.byref(rq), ctypes.byref(t)), "pm_server_submit")
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        """(result dict, stats dict); raises PathSampError with the request's status."""
+        r, st = Result(), ReqStats()
+        _check(lib().pm_server_wait(self._h, ticket, timeout_ms, ctypes.byref(r), ctypes.byref(st)),
+               "pm_server_wait")
+        return r.to_dict(), st.to_dict()
+
+    def cancel(self, ticket: int):
+        _check(lib().pm_server_cancel(self._h, ticket), "pm_server_cancel")
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().pm_server_get_stats(self._h, ctypes.byref(st)), "pm_server_get_stats")
+        return st.to_dict()
+
+    def destroy(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _check(lib().pm_server_destroy(self._h), "pm_server_destroy")
+            self._h = ctypes.c_void_p()
+            self._keep = []
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
 
 
 def count_motifs(off, col, k: int, seed: int = 1) -> dict:
