@@ -111,6 +111,187 @@ def cpu_baseline(scale: int, edge_factor: float, k: int, seed: int) -> dict:
     }
 
 
+def _graph_seconds(fn):
+    import torch
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
+
+
+def batched_leg(count: int, k: int, replays: int) -> dict:
+    """Many Chung-Lu graphs in one captured persistent launch, against the
+    same work as sequential pm_count calls and as one plain launch."""
+    import torch
+
+    from paper_1411_4942_amd import pathsamp as ps
+    from paper_1411_4942_amd import workloads
+
+    specs = workloads.batched_specs(count)
+    t0 = time.perf_counter()
+    csrs = []
+    for i, sp in enumerate(specs):
+        csrs.append(workloads.build(sp))
+        if (i + 1) % 64 == 0:
+            log(f"[bench] batched: generated {i + 1}/{count} graphs ({time.perf_counter() - t0:.1f}s)")
+    graphs, prep_s = _graph_seconds(lambda: [ps.Graph(o, c) for o, c in csrs])
+    infos = [g.info() for g in graphs]
+    params = [dict(k_path=k, k_cent=k, seed=sp["philox_seed"]) for sp in specs]
+    drawn = sum((k if i["W"] else 0) + (k if i["Lambda"] else 0) for i in infos)
+
+    batch, create_s = _graph_seconds(lambda: ps.Batch(graphs, params))
+    res = batch.run()  # warm replay
+    times = []
+    for _ in range(replays):
+        r2, dt = _graph_seconds(batch.run)
+        times.append(dt)
+        assert r2 == res
+    t_batch = min(times)
+    log(f"[bench] batched: tune {batch.tune()}, replay {1e3 * t_batch:.2f} ms")
+
+    def sequential():
+        return [g.count(p["k_path"], p["k_cent"], seed=p["seed"]) for g, p in zip(graphs, params)]
+
+    seq = sequential()
+    seq, t_seq = _graph_seconds(sequential)
+    big = max(range(count), key=lambda i: infos[i]["m"])
+    half = drawn // 2
+    graphs[big].count(half, half, seed=1)
+    _, t_plain = _graph_seconds(lambda: graphs[big].count(half, half, seed=1))
+    out = {
+        "workload": f"{count} Chung-Lu graphs, n log-uniform [1e3,2e5], m log-uniform [5e3,2e6], "
+                    f"gamma U[2.1,2.8], k={k} per sampler each, Philox seed 1+g",
+        "graphs": count,
+        "sum_m": int(sum(i["m"] for i in infos)),
+        "zero_W": int(sum(1 for i in infos if i["W"] == 0)),
+        "zero_Lambda": int(sum(1 for i in infos if i["Lambda"] == 0)),
+        "samples_drawn": int(drawn),
+        "tune": list(batch.tune()),
+        "autotune_and_capture_s": create_s,
+        "prep_s": prep_s,
+        "batched_ms": 1e3 * t_batch,
+        "batched_samples_per_s": drawn / t_batch,
+        "sequential_ms": 1e3 * t_seq,
+        "sequential_samples_per_s": drawn / t_seq,
+        "plain_one_graph_ms": 1e3 * t_plain,
+        "plain_one_graph_samples_per_s": 2 * half / t_plain,
+        "plain_graph_m": int(infos[big]["m"]),
+        "bit_exact_vs_sequential": res == seq,
+    }
+    batch.destroy()
+    for g in graphs:
+        g.destroy()
+    del csrs
+    torch.cuda.empty_cache()
+    ps.release_cached_memory()
+    return out
+
+
+def served_leg(count: int, n_sat: int, n_open: int, loads, rel_err: float, delta: float, k_max: int,
+               plain_check: int) -> dict:
+    """A pool of resident graphs behind the request server: closed-loop
+    saturation, then Poisson arrivals at fractions of it."""
+    import numpy as np
+    import torch
+
+    from paper_1411_4942_amd import pathsamp as ps
+    from paper_1411_4942_amd import workloads
+
+    specs = workloads.served_specs(count)
+    t0 = time.perf_counter()
+    csrs = []
+    for i, sp in enumerate(specs):
+        csrs.append(workloads.build(sp))
+        if (i + 1) % 16 == 0:
+            log(f"[bench] served: generated {i + 1}/{count} graphs ({time.perf_counter() - t0:.1f}s)")
+    srv = ps.Server(k_max=k_max)
+    gids = [srv.add_graph(o, c) for o, c in csrs]
+    _, prep_s = _graph_seconds(lambda: [srv.preload(g) for g in gids])
+    st0 = srv.stats()
+    log(f"[bench] served: {count} graphs resident, {st0['resident_bytes'] / 2 ** 30:.1f} GiB, prep {prep_s:.1f}s")
+    rng = np.random.Generator(np.random.PCG64(1))
+    seed_ctr = [10_000]
+
+    def one_request():
+        seed_ctr[0] += 1
+        return dict(graph=int(gids[int(rng.integers(0, count))]), rel_err=rel_err, delta=delta, seed=seed_ctr[0])
+
+    def run(reqs, arrivals):
+        """Submit at the given offsets (s), wait for all; (records, wall s, samples)."""
+        s_before = srv.stats()["samples"]
+        start = time.perf_counter()
+        tickets = []
+        for rq, at in zip(reqs, arrivals):
+            now = time.perf_counter() - start
+            if at > now:
+                time.sleep(at - now)
+            tickets.append(srv.submit(**rq))
+        recs = []
+        for rq, t in zip(reqs, tickets):
+            res, st = srv.wait(t)
+            recs.append((rq, res, st))
+        wall = time.perf_counter() - start
+        return recs, wall, srv.stats()["samples"] - s_before
+
+    sat_reqs = [one_request() for _ in range(n_sat)]
+    recs, wall, samples = run(sat_reqs, [0.0] * n_sat)
+    sat_rps = n_sat / wall
+    log(f"[bench] served: saturation {sat_rps:.2f} req/s, {samples / wall:.3e} samples/s")
+    out = {
+        "workload": f"{count} resident graphs (R-MAT + Chung-Lu, m log-uniform [1e4,5e7]), requests for all six "
+                    f"motifs at rel_err {rel_err}, delta {delta}, k from Corollary 5.3 on a 65536-id pilot, "
+                    f"k_max {k_max:.0e}",
+        "graphs": count,
+        "resident_gib": st0["resident_bytes"] / 2 ** 30,
+        "sum_m": int(sum(int(c.numel()) // 2 for _, c in csrs)),
+        "prep_s": prep_s,
+        "saturation": {"requests": n_sat, "req_per_s": sat_rps, "samples_per_s": samples / wall,
+                       "p50_ms": float(np.percentile([r[2]["latency_ms"] for r in recs], 50)),
+                       "p99_ms": float(np.percentile([r[2]["latency_ms"] for r in recs], 99))},
+        "capped_requests": int(sum(1 for r in recs if r[2]["capped_mask"])),
+        "mean_k_per_sampler": float(np.mean([(r[2]["k_path"] + r[2]["k_cent"]) / 2 for r in recs])),
+        "open_loop": [],
+    }
+    # the same requests one at a time through pm_count on a freshly prepared graph
+    if plain_check > 0:
+        t_plain = 0.0
+        drawn = 0
+        same = True
+        for rq, res, st in recs[:plain_check]:
+            o, c = csrs[gids.index(rq["graph"])]
+            g = ps.Graph(o, c)
+            r2, dt = _graph_seconds(lambda: g.count(st["k_path"], st["k_cent"], seed=rq["seed"], delta=rq["delta"]))
+            t_plain += dt
+            drawn += (st["k_path"] if r2["W"] else 0) + (st["k_cent"] if r2["Lambda"] else 0)
+            same &= r2 == res
+            g.destroy()
+        out["plain_sequential"] = {"requests": plain_check, "samples_per_s": drawn / t_plain,
+                                   "bit_exact_vs_served": same}
+    for frac in loads:
+        qps = frac * sat_rps
+        gaps = rng.exponential(1.0 / qps, size=n_open)
+        arrivals = np.cumsum(gaps) - gaps[0]
+        reqs = [one_request() for _ in range(n_open)]
+        recs, wall, samples = run(reqs, arrivals.tolist())
+        lat = [r[2]["latency_ms"] for r in recs]
+        out["open_loop"].append({"load": frac, "qps": qps, "requests": n_open, "req_per_s": n_open / wall,
+                                 "samples_per_s": samples / wall, "p50_ms": float(np.percentile(lat, 50)),
+                                 "p99_ms": float(np.percentile(lat, 99)),
+                                 "mean_queued_ms": float(np.mean([r[2]["queued_ms"] for r in recs]))})
+        log(f"[bench] served: load {frac:.2f}: p50 {out['open_loop'][-1]['p50_ms']:.0f} ms, "
+            f"p99 {out['open_loop'][-1]['p99_ms']:.0f} ms")
+    st = srv.stats()
+    out["server_steps"] = st["steps"]
+    out["server_busy_ms"] = st["busy_ms"]
+    srv.destroy()
+    del csrs
+    torch.cuda.empty_cache()
+    ps.release_cached_memory()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +303,15 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-scale", type=int, default=18)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--batch-graphs", type=int, default=256)
+    ap.add_argument("--batch-k", type=int, default=200_000)
+    ap.add_argument("--served-graphs", type=int, default=64)
+    ap.add_argument("--served-sat", type=int, default=4000)
+    ap.add_argument("--served-open", type=int, default=3000)
+    ap.add_argument("--served-loads", type=str, default="0.25,0.5,0.75,0.9")
+    ap.add_argument("--served-kmax", type=float, default=2e9)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -212,6 +402,14 @@ def main():
         "estimates": res["est"][1:],
         "rel_bar_halfwidth": [((h - l) / 2 / e if e else None) for e, l, h in zip(res["est"][1:], res["lo"][1:], res["hi"][1:])],
     }
+    if not args.no_batched:
+        log("[bench] batched leg ...")
+        out["batched"] = batched_leg(args.batch_graphs, args.batch_k, replays=5)
+    if not args.no_served:
+        log("[bench] served leg ...")
+        out["served"] = served_leg(args.served_graphs, args.served_sat, args.served_open,
+                                   [float(x) for x in args.served_loads.split(",")], 0.01, 0.01,
+                                   int(args.served_kmax), plain_check=min(8, args.served_sat))
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         kc = max(1, int(k * (2 ** args.cpu_scale) / (2 ** args.scale)))
