@@ -201,46 +201,90 @@ __global__ void k_copy_u32(const uint32_t *__restrict__ a, uint32_t *__restrict_
         b[i] = a[i];
 }
 
-// Symmetry: listing the slots by (col, row) must list the rows in the order
-// of the slots' own rows (half 1: in-degree = out-degree everywhere and the
-// reverse slot of q has column src[q]), and the reverse slot of q must lie in
-// row col[q] (half 2).  Both are checked inside WeightsIn, which reads those
-// arrays anyway.
+// Weights of a slot s = (u, v) with reverse slot r (Sections 3 and 4):
+//   tau_s    = (d_u - 1)(d_v - 1)
+//   lambda_s = L_{u,v} L_{v,u},  L_{u,v} = d_u - 1 - (position of v in row u)
+// counts the neighbours of u after v; r's position in row v gives L_{v,u}.
+// Symmetry is checked on the way: listing the slots by (col, row) must list
+// the rows in the order of the slots' own rows (half 1: the reverse slot of s
+// has column u, so in-degree = out-degree everywhere), and r must lie in row
+// v (half 2).
+//
+// Launch 1 of the weights scan, written out for memory-level parallelism:
+// both weights of every slot, parked in the prefix arrays, and one pair of
+// sums per tile of kBlock * kWItems slots (the tiling of the apply launch).
+// Each thread issues the loads of kWBatch items before any store, so their
+// gathers overlap.
+constexpr int kWItems = 16;
+constexpr int kWBatch = 8;
 
-// Section 3: tau_s = (d_u - 1)(d_v - 1).
-// Section 4: lambda_s = L_{u,v} L_{v,u}; L_{u,v} = d_u - 1 - (position of v in
-// row u) counts the neighbours of u after v; the reverse slot r gives L_{v,u}.
-// Both weights of a slot come out of one pass over (src, col, rev).
-struct WeightsIn {
-    const uint64_t *edge;
-    const uint32_t *rev, *key2;
-    const int64_t *off;
-    PrepStats *st;
-    __device__ __forceinline__ U64x2 operator()(int64_t s) const
-    {
-        const uint64_t e = edge[s];
-        const uint32_t u = (uint32_t)e, v = (uint32_t)(e >> 32);
-        const int64_t r = rev[s];
-        if (key2[s] != u) atomicOr(&st->err, (uint32_t)ERR_ASYM);  // symmetry, half 1
-        const int64_t ou = off[u], ov = off[v];  // both bounds of a row share a line
-        const int64_t du = off[u + 1] - ou, dv = off[v + 1] - ov;
-        if (r < ov || r >= ov + dv) atomicOr(&st->err, (uint32_t)ERR_ASYM);
-        const uint64_t tau = (uint64_t)(du - 1) * (uint64_t)(dv - 1);
-        const uint64_t luv = (uint64_t)(du - 1 - (s - ou));
-        const uint64_t lvu = (uint64_t)(dv - 1 - (r - ov));
-        return U64x2{tau, luv * lvu};
+__global__ __launch_bounds__(kBlock) void k_weights_reduce(const uint64_t *__restrict__ edge,
+                                                           const uint32_t *__restrict__ rev,
+                                                           const uint32_t *__restrict__ key2,
+                                                           const int64_t *__restrict__ off, int64_t N,
+                                                           uint64_t *__restrict__ p_tau,
+                                                           uint64_t *__restrict__ p_lam, U64x2 *__restrict__ tile_sums,
+                                                           PrepStats *st)
+{
+    __shared__ U64x2 s_wave[kBlock / kWave];
+    const int w = threadIdx.x / kWave;
+    const int lane = lane_id();
+    const int64_t wave_base = (int64_t)blockIdx.x * (kBlock * kWItems) + (int64_t)w * kWave * kWItems;
+    uint32_t err = 0;
+    uint64_t acc_t = 0, acc_l = 0;
+#pragma unroll
+    for (int h = 0; h < kWItems; h += kWBatch) {
+        uint64_t e[kWBatch];
+        uint32_t r[kWBatch], k2[kWBatch];
+#pragma unroll
+        for (int i = 0; i < kWBatch; ++i) {
+            const int64_t idx = wave_base + (int64_t)(h + i) * kWave + lane;
+            const bool ok = idx < N;
+            e[i] = ok ? edge[idx] : 0ull;
+            r[i] = ok ? rev[idx] : 0u;
+            k2[i] = ok ? key2[idx] : 0u;
+        }
+        int64_t ou[kWBatch], ou1[kWBatch], ov[kWBatch], ov1[kWBatch];
+#pragma unroll
+        for (int i = 0; i < kWBatch; ++i) {
+            const uint32_t u = (uint32_t)e[i], v = (uint32_t)(e[i] >> 32);
+            ou[i] = off[u];
+            ou1[i] = off[u + 1];
+            ov[i] = off[v];
+            ov1[i] = off[v + 1];
+        }
+#pragma unroll
+        for (int i = 0; i < kWBatch; ++i) {
+            const int64_t idx = wave_base + (int64_t)(h + i) * kWave + lane;
+            if (idx >= N) continue;
+            const uint32_t u = (uint32_t)e[i];
+            const int64_t rr = r[i];
+            if (k2[i] != u) err |= ERR_ASYM;  // symmetry, half 1
+            if (rr < ov[i] || rr >= ov1[i]) err |= ERR_ASYM;  // half 2
+            const int64_t du = ou1[i] - ou[i], dv = ov1[i] - ov[i];
+            const uint64_t tau = (uint64_t)(du - 1) * (uint64_t)(dv - 1);
+            const uint64_t luv = (uint64_t)(du - 1 - (idx - ou[i]));
+            const uint64_t lvu = (uint64_t)(dv - 1 - (rr - ov[i]));
+            const uint64_t lam = luv * lvu;
+            p_tau[idx] = tau;
+            p_lam[idx] = lam;
+            acc_t += tau;
+            acc_l += lam;
+        }
     }
-};
+    if (err) atomicOr(&st->err, err);
+    const U64x2 acc = wave_reduce(U64x2{acc_t, acc_l}, PairSumOp());
+    if (lane == 0) s_wave[w] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        U64x2 t{0, 0};
+#pragma unroll
+        for (int i = 0; i < kBlock / kWave; ++i) t = PairSumOp()(t, s_wave[i]);
+        tile_sums[blockIdx.x] = t;
+    }
+}
 
-// the weights are parked in the prefix arrays between the two passes
-struct WeightsStore {
-    uint64_t *p_tau, *p_lam;
-    __device__ __forceinline__ void operator()(int64_t i, U64x2 x) const
-    {
-        p_tau[i] = x.a;
-        p_lam[i] = x.b;
-    }
-};
+// launch 3 reads the parked weights back
 struct WeightsLoad {
     const uint64_t *p_tau, *p_lam;
     __device__ __forceinline__ U64x2 operator()(int64_t i) const { return U64x2{p_tau[i], p_lam[i]}; }
@@ -665,11 +709,26 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
             PM_HIP(hipGetLastError());
             return PM_OK;
         };
-        PM_TRY((scan_launch_stored<U64x2, 16>(
-            WeightsIn{g->edge, rev, key2, g->off, st}, WeightsStore{g->p_tau, g->p_lam}, WeightsLoad{g->p_tau, g->p_lam},
-            WeightsOut{g->p_tau, g->p_lam, g->guide_tau, g->guide_lam, long_tau, long_lam, (uint32_t)long_cap, st},
-            slots, PairSumOp(),
-            U64x2{0, 0}, scr, s, &st->totals, mid)));
+        if (slots > 0) {
+            const int64_t tiles = (slots + (int64_t)kBlock * kWItems - 1) / ((int64_t)kBlock * kWItems);
+            U64x2 *sums = (U64x2 *)scr;
+            {
+                ProfScope pr("weights.reduce", s);
+                hipLaunchKernelGGL(k_weights_reduce, dim3((unsigned)tiles), dim3(kBlock), 0, s, g->edge, rev, key2,
+                                   g->off, slots, g->p_tau, g->p_lam, sums, st);
+            }
+            hipLaunchKernelGGL((scan_tiles_kernel<U64x2, PairSumOp>), dim3(1), dim3(1024), 0, s, sums, tiles,
+                               PairSumOp(), U64x2{0, 0}, &st->totals);
+            PM_HIP(hipGetLastError());
+            PM_TRY(mid());
+            ProfScope pa("weights.apply", s);
+            hipLaunchKernelGGL((scan_apply_kernel<U64x2, kWItems, PairSumOp, WeightsLoad, WeightsOut>),
+                               dim3((unsigned)tiles), dim3(kBlock), 0, s, WeightsLoad{g->p_tau, g->p_lam},
+                               WeightsOut{g->p_tau, g->p_lam, g->guide_tau, g->guide_lam, long_tau, long_lam,
+                                          (uint32_t)long_cap, st},
+                               slots, PairSumOp(), U64x2{0, 0}, (const U64x2 *)sums);
+            PM_HIP(hipGetLastError());
+        }
         if (slots > 0) {
             const unsigned gl = (unsigned)std::min<uint64_t>(long_cap, 2048);
             hipLaunchKernelGGL(k_guide_long, dim3(gl), dim3(kBlock), 0, s, g->p_tau, &st->shift_tau, g->guide_tau,
