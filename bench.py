@@ -54,7 +54,7 @@ def load_traffic():
     return t if t.get("source_hash") == source_hash() else None
 
 
-def roofline_for(name, kern, alg_entry, traffic):
+def roofline_for(name, kern, alg_entry, traffic, copy_gbs=None):
     alg_bytes, symbol = alg_entry
     achieved = alg_bytes / (kern["avg_ms"] * 1e-3) / 1e9
     tr = None
@@ -65,8 +65,32 @@ def roofline_for(name, kern, alg_entry, traffic):
             tr = best["fetch_bytes"] + best["write_bytes"]
     return {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": tr, "algorithmic_bytes": alg_bytes,
+            "measured_copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs if copy_gbs else None,
             "avg_launch_ms": kern["avg_ms"],
             "traffic_over_algorithmic": (tr / alg_bytes) if tr else None}
+
+
+COPY_BYTES = 1 << 30
+
+
+def measure_copy(stream, reps: int = 5) -> float:
+    """Measured streaming ceiling: the library's copy kernel over 1 GiB
+    (read + write bytes / average launch time, HIP events on its stream)."""
+    import torch
+
+    from paper_1411_4942_amd import pathsamp as ps
+
+    a = torch.empty(COPY_BYTES // 4, dtype=torch.int32, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    ps.device_copy(b, a, stream=stream)
+    ps.profile_enable(True)
+    for _ in range(reps):
+        ps.device_copy(b, a, stream=stream)
+    torch.cuda.synchronize()
+    n, ms = ps.profile_read()["stream_copy"]
+    ps.profile_enable(False)
+    del a, b
+    return 2 * COPY_BYTES / (ms / n * 1e-3) / 1e9
 
 
 def log(*a):
@@ -353,6 +377,7 @@ def main():
     ms_per_step = 1e3 * (t1 - t0) / args.steps
     value = 2 * k / ((t1 - t0) / args.steps)
     log(f"[bench] {args.steps} steps: {ms_per_step:.2f} ms/step")
+    copy_gbs = measure_copy(stream)
 
     # per-kernel averages (HIP events on the launch stream)
     kernels = {name: {"launches": n, "avg_ms": ms / n, "ms_per_step": ms / args.steps}
@@ -370,8 +395,8 @@ def main():
     traffic = load_traffic()
     timed = {n: v for n, v in kernels.items() if n in alg}
     dom_name = max(timed, key=lambda n: timed[n]["ms_per_step"])
-    roofline = roofline_for(dom_name, kernels[dom_name], alg[dom_name], traffic)
-    roofline_sampler = roofline_for("sample_path", kernels["sample_path"], alg["sample_path"], traffic)
+    roofline = roofline_for(dom_name, kernels[dom_name], alg[dom_name], traffic, copy_gbs)
+    roofline_sampler = roofline_for("sample_path", kernels["sample_path"], alg["sample_path"], traffic, copy_gbs)
     samp_ms = [kernels[n]["avg_ms"] for n in ("sample_path", "sample_centered") if n in kernels]
 
     out = {

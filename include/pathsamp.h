@@ -343,6 +343,13 @@ pm_status pm_release_cached_memory(void);
  * input). */
 pm_status pm_philox_device(const uint32_t *in, uint32_t *out, int64_t count);
 
+/* Streaming copy of `bytes` bytes between two device buffers on `stream`
+ * (16-byte vector loads and stores, asynchronous): the reference kernel of
+ * known traffic for calibrating hardware counters and for the measured
+ * streaming ceiling.  Pointers aligned to 16 bytes, bytes a multiple of 16,
+ * else PM_EINVAL. */
+pm_status pm_device_copy(void *dst, const void *src, uint64_t bytes, void *stream);
+
 /* Per-kernel timing with HIP events recorded on each launch's stream.
  * pm_profile_enable clears the totals and switches recording on (1) or off
  * (0); pm_profile_read waits for the recorded events and returns one entry

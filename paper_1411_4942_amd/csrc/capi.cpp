@@ -28,6 +28,7 @@ pm_status finalize(const uint64_t tp[PM_NUM_TALLIES], const uint64_t tc[PM_NUM_T
 pm_status chernoff_interval(uint64_t count, uint64_t k, double delta, double *p_lo, double *p_hi);
 pm_status samples_for_error(double rel_err, double delta, double alpha, uint64_t *k_out);
 pm_status philox_device(const uint32_t *in, uint32_t *out, int64_t count);
+pm_status device_copy(void *dst, const void *src, uint64_t bytes, hipStream_t s);
 pm_status dev_alloc(void **p, size_t bytes, hipStream_t s);
 void dev_free(void *p, hipStream_t s);
 pm_status count_on_graph(const pm_graph *g, const pm_params *p, pm_result *out, hipStream_t s);
@@ -260,6 +261,11 @@ pm_status pm_count_batch(const pm_graph *const *graphs, const pm_params *params,
         pm::batch_destroy(b);
         return st;
     })
+}
+
+pm_status pm_device_copy(void *dst, const void *src, uint64_t bytes, void *stream)
+{
+    PM_GUARD(return pm::device_copy(dst, src, bytes, (hipStream_t)stream);)
 }
 
 pm_status pm_philox_device(const uint32_t *in, uint32_t *out, int64_t count)

@@ -120,6 +120,31 @@ __global__ void k_philox(const uint32_t *in, uint32_t *out, int64_t count)
     out[4 * i + 3] = r.w;
 }
 
+// Streaming copy, 16 bytes per lane per step: the reference kernel whose
+// bytes are known exactly (calibrates hardware traffic counters, measures the
+// streaming ceiling of the device).
+__global__ __launch_bounds__(kBlock) void k_stream_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                       int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+pm_status device_copy(void *dst, const void *src, uint64_t bytes, hipStream_t s)
+{
+    if ((bytes > 0 && (!dst || !src)) || bytes % 16 != 0 || ((uintptr_t)dst | (uintptr_t)src) % 16 != 0) {
+        set_error("device_copy: device pointers aligned to 16 bytes, size a multiple of 16");
+        return PM_EINVAL;
+    }
+    const int64_t n = (int64_t)(bytes / 16);
+    if (n == 0) return PM_OK;
+    ProfScope prof("stream_copy", s);
+    hipLaunchKernelGGL(k_stream_copy, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, s, (const uint4 *)src,
+                       (uint4 *)dst, n);
+    PM_HIP(hipGetLastError());
+    return PM_OK;
+}
+
 pm_status philox_device(const uint32_t *in, uint32_t *out, int64_t count)
 {
     if (count < 0 || (count > 0 && (!in || !out))) {

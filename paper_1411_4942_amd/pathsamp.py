@@ -117,6 +117,7 @@ _SIGNATURES = {
     "pm_samples_for_error": (ctypes.c_int32, [ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                               ctypes.POINTER(ctypes.c_uint64)]),
     "pm_philox_device": (ctypes.c_int32, [_P, _P, ctypes.c_int64]),
+    "pm_device_copy": (ctypes.c_int32, [_P, _P, ctypes.c_uint64, _P]),
     "pm_set_sampler_shape": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32]),
     "pm_release_cached_memory": (ctypes.c_int32, []),
     "pm_profile_enable": (ctypes.c_int32, [ctypes.c_int32]),
@@ -452,6 +453,14 @@ def philox_device(inputs) -> np.ndarray:
     out = np.zeros((a.shape[0], 4), np.uint32)
     _check(lib().pm_philox_device(a.ctypes.data, out.ctypes.data, a.shape[0]), "pm_philox_device")
     return out
+
+
+def device_copy(dst, src, stream=None):
+    """pm_device_copy between two same-sized CUDA tensors (asynchronous)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("tensors differ in size")
+    _check(lib().pm_device_copy(dst.data_ptr(), src.data_ptr(), nbytes, _stream_ptr(stream)), "pm_device_copy")
 
 
 def profile_enable(on: bool = True):
