@@ -139,6 +139,10 @@ __global__ void fill_kernel(T *p, T value, int64_t n)
     for (; i < n; i += stride) p[i] = value;
 }
 
+// Blocks for n items at `threads` per block, capped.  Streaming kernels pass
+// a cap that is never reached (a flat grid, one item per thread): on MI355X a
+// flat copy measured 6.2 TB/s against 4.6 TB/s for 8192 blocks striding
+// over the same array.
 inline int grid_for(int64_t n, int threads, int max_blocks = 65536)
 {
     int64_t b = (n + threads - 1) / threads;
@@ -151,7 +155,7 @@ template <typename T>
 inline pm_status fill_async(T *p, T value, int64_t n, hipStream_t s)
 {
     if (n <= 0) return PM_OK;
-    hipLaunchKernelGGL(fill_kernel<T>, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, s, p, value, n);
+    hipLaunchKernelGGL(fill_kernel<T>, dim3(grid_for(n, kBlock, 1 << 22)), dim3(kBlock), 0, s, p, value, n);
     PM_HIP(hipGetLastError());
     return PM_OK;
 }

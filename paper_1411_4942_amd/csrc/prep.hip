@@ -84,7 +84,16 @@ __global__ __launch_bounds__(kBlock) void k_degrees(const int64_t *__restrict__ 
         uint32_t x = __shfl_xor(dmax, o, kWave);
         dmax = x > dmax ? x : dmax;
     }
-    if (lane_id() == 0) atomicMax(&st->dmax, dmax);
+    // one atomic per block: contention on st->dmax, not bandwidth, bounds this kernel
+    __shared__ uint32_t s_max[kBlock / kWave];
+    if (lane_id() == 0) s_max[threadIdx.x / kWave] = dmax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t m = 0;
+#pragma unroll
+        for (int i = 0; i < kBlock / kWave; ++i) m = s_max[i] > m ? s_max[i] : m;
+        if (m) atomicMax(&st->dmax, m);
+    }
 }
 
 __global__ void k_iota(uint32_t *p, int64_t n)
@@ -461,7 +470,7 @@ struct Temps {
     }
 };
 
-int grid_stream(int64_t n) { return grid_for(n, kBlock, 4096); }
+int grid_stream(int64_t n) { return grid_for(n, kBlock, 1 << 22); }
 
 const char *err_text(uint32_t e)
 {
@@ -582,7 +591,7 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
     PM_TRY(tmp.get(&deg_in, nn));
     if (n > 0) {
         ProfScope prof("degrees", s);
-        hipLaunchKernelGGL(k_degrees, dim3(grid_stream(n)), dim3(kBlock), 0, s, off_in, n, slots, deg_in, st);
+        hipLaunchKernelGGL(k_degrees, dim3(grid_for(n, kBlock, 1024)), dim3(kBlock), 0, s, off_in, n, slots, deg_in, st);
         PM_HIP(hipGetLastError());
     }
     // the row walk below trusts the offsets: read the verdict first
@@ -653,7 +662,7 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
     }
     if (slots > 0) {
         ProfScope prof("place_rows", s);
-        hipLaunchKernelGGL(k_place_rows, dim3(grid_for((slots + kPlaceItems - 1) / kPlaceItems, kBlock, 4096)),
+        hipLaunchKernelGGL(k_place_rows, dim3(grid_for((slots + kPlaceItems - 1) / kPlaceItems, kBlock, 1 << 22)),
                            dim3(kBlock), 0, s, off_in, col_in, n, slots, g->rank, g->off, kb, vb, st);
         PM_HIP(hipGetLastError());
     }

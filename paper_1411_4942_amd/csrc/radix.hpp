@@ -1,7 +1,9 @@
 // Stable LSD radix sort of (uint32 key, uint32 value) pairs, 8-bit digits.
 //
-// One pass = three launches: per-tile digit histograms (digit-major layout),
-// an exclusive scan of those counts, and a stable scatter.  The scatter ranks
+// One pass: per-tile digit histograms (tile-major layout: each tile's 256
+// counts are one contiguous kilobyte, written and read whole), their
+// exclusive scan in digit-major order (per-chunk sums, one scan block, and a
+// rewrite of the chunks into offsets), and a stable scatter.  The scatter ranks
 // each wave's 1024 elements in input order with ballots (8 ballots give every
 // lane the mask of lanes holding the same digit) and per-wave digit counters
 // in LDS, combines the four waves per digit, stages the tile digit-sorted in
@@ -60,7 +62,7 @@ __global__ __launch_bounds__(kBlock) void radix_histogram(const uint32_t *__rest
     uint32_t c = 0;
 #pragma unroll
     for (int i = 0; i < kBlock / kWave; ++i) c += hist[i][t];
-    counts[(int64_t)t * tiles + blockIdx.x] = c;
+    counts[(int64_t)blockIdx.x * kRadixBins + t] = c;
 }
 
 // vals_in may be null: the payload is then the element's input position.
@@ -90,7 +92,7 @@ __global__ __launch_bounds__(kBlock) void radix_scatter(const uint32_t *__restri
 
 #pragma unroll
     for (int i = 0; i < kBlock / kWave; ++i) s_cnt[i][t] = 0;
-    s_goff[t] = offsets[(int64_t)t * tiles + tile];
+    s_goff[t] = offsets[tile * kRadixBins + t];
 
     uint32_t key[kRadixItems], val[kRadixItems], dig[kRadixItems], rank[kRadixItems];
 #pragma unroll
@@ -173,15 +175,115 @@ __global__ __launch_bounds__(kBlock) void radix_scatter(const uint32_t *__restri
     }
 }
 
-struct CountIn {
-    const uint32_t *c;
-    __device__ __forceinline__ uint32_t operator()(int64_t i) const { return c[i]; }
-};
+// Exclusive scan of the tile-major counts in (digit, tile) order: the output
+// position of digit d of tile t is the number of keys with a smaller digit
+// plus those with digit d in earlier tiles.  Tiles are grouped in chunks of
+// kRadixChunk; thread d of a block handles digit d, reading one contiguous
+// row of 256 counts per tile.
+constexpr int kRadixChunk = 64;
+constexpr int kRadixBatch = 8;  // loads in flight per thread
+constexpr int kRadixParts = 4;  // threads per digit in the chunk scan
 
-struct ExclusiveOut {
-    uint32_t *o;
-    __device__ __forceinline__ void operator()(int64_t i, uint32_t incl, uint32_t x) const { o[i] = incl - x; }
-};
+__global__ __launch_bounds__(kBlock) void radix_chunk_sums(const uint32_t *__restrict__ counts, int64_t tiles,
+                                                           uint32_t *__restrict__ chunk)
+{
+    const int d = threadIdx.x;
+    const int64_t t0 = (int64_t)blockIdx.x * kRadixChunk;
+    const int64_t t1 = (t0 + kRadixChunk < tiles) ? t0 + kRadixChunk : tiles;
+    uint32_t acc = 0;
+    for (int64_t t = t0; t < t1; t += kRadixBatch) {
+        uint32_t v[kRadixBatch];
+#pragma unroll
+        for (int i = 0; i < kRadixBatch; ++i) v[i] = (t + i < t1) ? counts[(t + i) * kRadixBins + d] : 0u;
+#pragma unroll
+        for (int i = 0; i < kRadixBatch; ++i) acc += v[i];
+    }
+    chunk[(int64_t)blockIdx.x * kRadixBins + d] = acc;
+}
+
+// One block of kRadixParts * 256 threads: thread (p, d) owns a contiguous
+// range of chunks of digit d.  chunk[c][d] becomes the output position of
+// digit d's first key in chunk c.
+__global__ __launch_bounds__(kRadixParts *kBlock) void radix_chunk_scan(uint32_t *__restrict__ chunk,
+                                                                        int64_t nchunks)
+{
+    __shared__ uint32_t s_part[kRadixParts][kRadixBins];
+    __shared__ uint32_t s_wave[kBlock / kWave];
+    const int d = threadIdx.x % kRadixBins, p = threadIdx.x / kRadixBins;
+    const int64_t per = (nchunks + kRadixParts - 1) / kRadixParts;
+    const int64_t c0 = p * per, c1 = (c0 + per < nchunks) ? c0 + per : nchunks;
+    uint32_t acc = 0;
+    for (int64_t c = c0; c < c1; c += kRadixBatch) {
+        uint32_t v[kRadixBatch];
+#pragma unroll
+        for (int i = 0; i < kRadixBatch; ++i) v[i] = (c + i < c1) ? chunk[(c + i) * kRadixBins + d] : 0u;
+#pragma unroll
+        for (int i = 0; i < kRadixBatch; ++i) acc += v[i];
+    }
+    s_part[p][d] = acc;
+    __syncthreads();
+    // digit totals, exclusive over digits (the threads of part 0, whole waves)
+    const int lane = lane_id(), w = d / kWave;
+    uint32_t tot = 0, incl = 0;
+    if (p == 0) {
+#pragma unroll
+        for (int q = 0; q < kRadixParts; ++q) tot += s_part[q][d];
+        incl = tot;
+#pragma unroll
+        for (int k = 1; k < kWave; k <<= 1) {
+            const uint32_t o = __shfl_up(incl, k, kWave);
+            if (lane >= k) incl += o;
+        }
+        if (lane == kWave - 1) s_wave[w] = incl;
+    }
+    __syncthreads();
+    if (p == 0) {
+        uint32_t pre = 0;
+        for (int ww = 0; ww < w; ++ww) pre += s_wave[ww];
+        // the digit's base, then each part's start within the digit
+        uint32_t run = pre + incl - tot;
+#pragma unroll
+        for (int q = 0; q < kRadixParts; ++q) {
+            const uint32_t x = s_part[q][d];
+            s_part[q][d] = run;
+            run += x;
+        }
+    }
+    __syncthreads();
+    uint32_t run = s_part[p][d];
+    for (int64_t c = c0; c < c1; c += kRadixBatch) {
+        uint32_t v[kRadixBatch];
+#pragma unroll
+        for (int i = 0; i < kRadixBatch; ++i) v[i] = (c + i < c1) ? chunk[(c + i) * kRadixBins + d] : 0u;
+#pragma unroll
+        for (int i = 0; i < kRadixBatch; ++i)
+            if (c + i < c1) {
+                chunk[(c + i) * kRadixBins + d] = run;
+                run += v[i];
+            }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void radix_chunk_apply(const uint32_t *__restrict__ counts,
+                                                            const uint32_t *__restrict__ chunk, int64_t tiles,
+                                                            uint32_t *__restrict__ offs)
+{
+    const int d = threadIdx.x;
+    const int64_t t0 = (int64_t)blockIdx.x * kRadixChunk;
+    const int64_t t1 = (t0 + kRadixChunk < tiles) ? t0 + kRadixChunk : tiles;
+    uint32_t run = chunk[(int64_t)blockIdx.x * kRadixBins + d];
+    for (int64_t t = t0; t < t1; t += kRadixBatch) {
+        uint32_t v[kRadixBatch];
+#pragma unroll
+        for (int i = 0; i < kRadixBatch; ++i) v[i] = (t + i < t1) ? counts[(t + i) * kRadixBins + d] : 0u;
+#pragma unroll
+        for (int i = 0; i < kRadixBatch; ++i)
+            if (t + i < t1) {
+                offs[(t + i) * kRadixBins + d] = run;
+                run += v[i];
+            }
+    }
+}
 
 inline int bits_for(uint64_t max_key)
 {
@@ -195,8 +297,9 @@ inline size_t radix_scratch_bytes(int64_t N)
 {
     int64_t tiles = (N + kRadixTile - 1) / kRadixTile;
     if (tiles < 1) tiles = 1;
-    int64_t cnt = tiles * kRadixBins;
-    return (size_t)cnt * 2 * sizeof(uint32_t) + ScanScratch<uint32_t>::bytes_for(cnt, 8) + 1024;
+    const int64_t cnt = tiles * kRadixBins;
+    const int64_t chunks = (tiles + kRadixChunk - 1) / kRadixChunk;
+    return (size_t)(2 * cnt + chunks * kRadixBins) * sizeof(uint32_t) + 1024;
 }
 
 // Sort (keys, vals) by the low `bits` bits of the keys, stably.  The first
@@ -229,7 +332,7 @@ inline pm_status radix_sort(const char *name, const uint32_t *in_k, const uint32
     if (N <= 1 || bits <= 0) {
         // nothing to sort: copy the input through (values, pairs, samples)
         if (N > 0) {
-            hipLaunchKernelGGL(radix_pair_copy, dim3(grid_for(N, kBlock, 4096)), dim3(kBlock), 0, s, in_k, in_v, N,
+            hipLaunchKernelGGL(radix_pair_copy, dim3(grid_for(N, kBlock, 1 << 22)), dim3(kBlock), 0, s, in_k, in_v, N,
                                pair_out, sample_out, v0);
             PM_HIP(hipGetLastError());
             if (!pair_out) PM_HIP(hipMemcpyAsync(k0, in_k, sizeof(uint32_t) * N, hipMemcpyDeviceToDevice, s));
@@ -239,9 +342,10 @@ inline pm_status radix_sort(const char *name, const uint32_t *in_k, const uint32
     }
     const int64_t tiles = (N + kRadixTile - 1) / kRadixTile;
     const int64_t cnt = tiles * kRadixBins;
+    const int64_t chunks = (tiles + kRadixChunk - 1) / kRadixChunk;
     uint32_t *counts = (uint32_t *)scratch;
     uint32_t *offs = counts + cnt;
-    void *scan_scr = (void *)(((uintptr_t)(offs + cnt) + 255) & ~(uintptr_t)255);
+    uint32_t *chunk = offs + cnt;
     const uint32_t *ki = in_k, *vi = in_v;
     uint32_t *ko = k0, *vo = v0;
     for (int shift = 0; shift < bits; shift += 8) {
@@ -255,8 +359,11 @@ inline pm_status radix_sort(const char *name, const uint32_t *in_k, const uint32
         }
         {
             ProfScope prof(n_scan.c_str(), s);
-            PM_TRY((scan_launch<uint32_t, 8>(CountIn{counts}, ExclusiveOut{offs}, cnt, SumOp<uint32_t>(), 0u,
-                                             scan_scr, s)));
+            hipLaunchKernelGGL(radix_chunk_sums, dim3((unsigned)chunks), dim3(kBlock), 0, s, counts, tiles, chunk);
+            hipLaunchKernelGGL(radix_chunk_scan, dim3(1), dim3(kRadixParts * kBlock), 0, s, chunk, chunks);
+            hipLaunchKernelGGL(radix_chunk_apply, dim3((unsigned)chunks), dim3(kBlock), 0, s, counts, chunk, tiles,
+                               offs);
+            PM_HIP(hipGetLastError());
         }
         {
             const bool last = shift + 8 >= bits;

@@ -139,7 +139,7 @@ pm_status device_copy(void *dst, const void *src, uint64_t bytes, hipStream_t s)
     const int64_t n = (int64_t)(bytes / 16);
     if (n == 0) return PM_OK;
     ProfScope prof("stream_copy", s);
-    hipLaunchKernelGGL(k_stream_copy, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, s, (const uint4 *)src,
+    hipLaunchKernelGGL(k_stream_copy, dim3(grid_for(n, kBlock, 1 << 22)), dim3(kBlock), 0, s, (const uint4 *)src,
                        (uint4 *)dst, n);
     PM_HIP(hipGetLastError());
     return PM_OK;
