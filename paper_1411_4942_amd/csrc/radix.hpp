@@ -17,13 +17,20 @@
 
 namespace pm {
 
+#ifndef PM_RADIX_THREADS
+#define PM_RADIX_THREADS 512
+#endif
+constexpr int kRadixThreads = PM_RADIX_THREADS;  // threads per histogram / scatter block (512 measured fastest of 256, 512, 1024)
+constexpr int kRadixWaves = kRadixThreads / kWave;
 constexpr int kRadixItems = 16;
-constexpr int kRadixTile = kBlock * kRadixItems;  // 4096
+constexpr int kRadixTile = kRadixThreads * kRadixItems;
 constexpr int kRadixBins = 256;
+static_assert(kRadixThreads >= kRadixBins && kRadixThreads % kRadixBins == 0, "one thread per digit, whole waves");
 
 // Tile layout shared by both kernels: wave w owns elements
 // [w * 1024, (w + 1) * 1024) of the tile, as 16 coalesced rows of 64, so the
-// element order inside a tile is (wave, row, lane).
+// element order inside a tile is (wave, row, lane).  Threads t < 256 also
+// stand for digit t in the per-digit phases.
 constexpr int kRadixWaveSpan = kWave * kRadixItems;  // 1024
 
 __device__ __forceinline__ int64_t radix_index(int64_t tile, int w, int i, int lane)
@@ -44,14 +51,13 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb)
     return x * per + (x < extra ? x : extra) + i;
 }
 
-__global__ __launch_bounds__(kBlock) void radix_histogram(const uint32_t *__restrict__ keys, int64_t N, int shift,
-                                                          uint32_t mask, uint32_t *__restrict__ counts,
-                                                          int64_t tiles)
+__global__ __launch_bounds__(kRadixThreads) void radix_histogram(const uint32_t *__restrict__ keys, int64_t N,
+                                                                  int shift, uint32_t mask,
+                                                                  uint32_t *__restrict__ counts, int64_t tiles)
 {
-    __shared__ uint32_t hist[kBlock / kWave][kRadixBins];
+    __shared__ uint32_t hist[kRadixWaves][kRadixBins];
     const int t = threadIdx.x, w = t / kWave, lane = lane_id();
-#pragma unroll
-    for (int i = 0; i < kBlock / kWave; ++i) hist[i][t] = 0;
+    for (int j = t; j < kRadixWaves * kRadixBins; j += kRadixThreads) (&hist[0][0])[j] = 0;
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kRadixItems; ++i) {
@@ -59,17 +65,19 @@ __global__ __launch_bounds__(kBlock) void radix_histogram(const uint32_t *__rest
         if (idx < N) atomicAdd(&hist[w][(keys[idx] >> shift) & mask], 1u);
     }
     __syncthreads();
-    uint32_t c = 0;
+    if (t < kRadixBins) {
+        uint32_t c = 0;
 #pragma unroll
-    for (int i = 0; i < kBlock / kWave; ++i) c += hist[i][t];
-    counts[(int64_t)blockIdx.x * kRadixBins + t] = c;
+        for (int i = 0; i < kRadixWaves; ++i) c += hist[i][t];
+        counts[(int64_t)blockIdx.x * kRadixBins + t] = c;
+    }
 }
 
 // vals_in may be null: the payload is then the element's input position.
 // keys_out may be null when pair_out is given: then pair_out[dst] =
 // key | val << 32 replaces the key array (vals_out is always written).
 // sample_out, when given, receives every 32nd value: sample_out[dst / 32].
-__global__ __launch_bounds__(kBlock) void radix_scatter(const uint32_t *__restrict__ keys_in,
+__global__ __launch_bounds__(kRadixThreads) void radix_scatter(const uint32_t *__restrict__ keys_in,
                                                         const uint32_t *__restrict__ vals_in, int64_t N, int shift,
                                                         uint32_t mask, const uint32_t *__restrict__ offsets,
                                                         int64_t tiles, uint32_t *__restrict__ keys_out,
@@ -79,10 +87,10 @@ __global__ __launch_bounds__(kBlock) void radix_scatter(const uint32_t *__restri
 {
     __shared__ uint32_t s_key[kRadixTile];
     __shared__ uint32_t s_val[kRadixTile];
-    __shared__ uint32_t s_cnt[kBlock / kWave][kRadixBins];  // per-wave digit counts, then wave offsets
-    __shared__ uint32_t s_start[kRadixBins];                // first LDS slot of each digit in the tile
-    __shared__ uint32_t s_goff[kRadixBins];                 // first output position of each digit
-    __shared__ uint32_t s_wsum[kBlock / kWave];
+    __shared__ uint32_t s_cnt[kRadixWaves][kRadixBins];  // per-wave digit counts, then wave offsets
+    __shared__ uint32_t s_start[kRadixBins];             // first LDS slot of each digit in the tile
+    __shared__ uint32_t s_goff[kRadixBins];              // first output position of each digit
+    __shared__ uint32_t s_wsum[kRadixBins / kWave];
 
     const int t = threadIdx.x;
     const int w = t / kWave;
@@ -90,9 +98,8 @@ __global__ __launch_bounds__(kBlock) void radix_scatter(const uint32_t *__restri
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
     const int64_t tile = xcd_tile(blockIdx.x, tiles);
 
-#pragma unroll
-    for (int i = 0; i < kBlock / kWave; ++i) s_cnt[i][t] = 0;
-    s_goff[t] = offsets[tile * kRadixBins + t];
+    for (int j = t; j < kRadixWaves * kRadixBins; j += kRadixThreads) (&s_cnt[0][0])[j] = 0;
+    if (t < kRadixBins) s_goff[t] = offsets[tile * kRadixBins + t];
 
     uint32_t key[kRadixItems], val[kRadixItems], dig[kRadixItems], rank[kRadixItems];
 #pragma unroll
@@ -125,24 +132,33 @@ __global__ __launch_bounds__(kBlock) void radix_scatter(const uint32_t *__restri
     }
     __syncthreads();
 
-    // per digit (thread t): offsets of the four waves, tile total
-    uint32_t c0 = s_cnt[0][t], c1 = s_cnt[1][t], c2 = s_cnt[2][t], c3 = s_cnt[3][t];
-    const uint32_t total = c0 + c1 + c2 + c3;
-    uint32_t incl = total;
+    // per digit (threads t < 256, whole waves): the tile's digit totals,
+    // scanned over digits, and each wave's start inside its digit's run
+    uint32_t total = 0, incl = 0;
+    if (t < kRadixBins) {
 #pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        uint32_t o = __shfl_up(incl, d, kWave);
-        if (lane >= d) incl += o;
+        for (int i = 0; i < kRadixWaves; ++i) total += s_cnt[i][t];
+        incl = total;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            uint32_t o = __shfl_up(incl, d, kWave);
+            if (lane >= d) incl += o;
+        }
+        if (lane == kWave - 1) s_wsum[w] = incl;
     }
-    if (lane == kWave - 1) s_wsum[w] = incl;
     __syncthreads();
-    uint32_t pre = 0;
-    for (int ww = 0; ww < w; ++ww) pre += s_wsum[ww];
-    s_start[t] = pre + incl - total;
-    s_cnt[0][t] = 0;
-    s_cnt[1][t] = c0;
-    s_cnt[2][t] = c0 + c1;
-    s_cnt[3][t] = c0 + c1 + c2;
+    if (t < kRadixBins) {
+        uint32_t pre = 0;
+        for (int ww = 0; ww < w; ++ww) pre += s_wsum[ww];
+        s_start[t] = pre + incl - total;
+        uint32_t run = 0;
+#pragma unroll
+        for (int i = 0; i < kRadixWaves; ++i) {
+            const uint32_t c = s_cnt[i][t];
+            s_cnt[i][t] = run;
+            run += c;
+        }
+    }
     __syncthreads();
 
 #pragma unroll
@@ -159,7 +175,7 @@ __global__ __launch_bounds__(kBlock) void radix_scatter(const uint32_t *__restri
     const int64_t tile_n = (N - tile * kRadixTile) < kRadixTile ? (N - tile * kRadixTile) : kRadixTile;
 #pragma unroll
     for (int i = 0; i < kRadixItems; ++i) {
-        int p = i * kBlock + t;
+        int p = i * kRadixThreads + t;
         if (p < tile_n) {
             uint32_t k = s_key[p];
             uint32_t d = (k >> shift) & mask;
@@ -353,8 +369,8 @@ inline pm_status radix_sort(const char *name, const uint32_t *in_k, const uint32
         uint32_t mask = (1u << nb) - 1u;
         {
             ProfScope prof(n_hist.c_str(), s);
-            hipLaunchKernelGGL(radix_histogram, dim3((unsigned)tiles), dim3(kBlock), 0, s, ki, N, shift, mask, counts,
-                               tiles);
+            hipLaunchKernelGGL(radix_histogram, dim3((unsigned)tiles), dim3(kRadixThreads), 0, s, ki, N, shift, mask,
+                               counts, tiles);
             PM_HIP(hipGetLastError());
         }
         {
@@ -370,7 +386,7 @@ inline pm_status radix_sort(const char *name, const uint32_t *in_k, const uint32
             uint64_t *po = (last && pair_out) ? pair_out : nullptr;
             uint32_t *so = last ? sample_out : nullptr;
             ProfScope prof(n_scat.c_str(), s);
-            hipLaunchKernelGGL(radix_scatter, dim3((unsigned)tiles), dim3(kBlock), 0, s, ki, vi, N, shift, mask,
+            hipLaunchKernelGGL(radix_scatter, dim3((unsigned)tiles), dim3(kRadixThreads), 0, s, ki, vi, N, shift, mask,
                                offs, tiles, po ? nullptr : ko, vo, po, so);
             PM_HIP(hipGetLastError());
         }
