@@ -293,14 +293,6 @@ __global__ __launch_bounds__(kBlock) void k_weights_reduce(const uint64_t *__res
     }
 }
 
-// launch 3 reads the parked weights back
-struct WeightsLoad {
-    const uint64_t *p_tau, *p_lam;
-    __device__ __forceinline__ U64x2 operator()(int64_t i) const { return U64x2{p_tau[i], p_lam[i]}; }
-};
-
-// inclusive prefixes with wrap detection: incl < x happens iff the running
-// sum passed 2^64
 // Guide entries of slot i: the buckets whose start j << shift lies in
 // [P[i-1], P[i]) point at slot i.  Runs longer than 64 buckets go to a list
 // that k_guide_long fills with whole blocks.
@@ -331,23 +323,6 @@ __device__ __forceinline__ void guide_fill(uint64_t prev, uint64_t cur, uint32_t
     }
 }
 
-struct WeightsOut {
-    uint64_t *p_tau, *p_lam;
-    uint32_t *guide_tau, *guide_lam, *long_tau, *long_lam;
-    uint32_t long_cap;
-    PrepStats *st;
-    __device__ __forceinline__ void operator()(int64_t i, U64x2 incl, U64x2 x) const
-    {
-        p_tau[i] = incl.a;
-        p_lam[i] = incl.b;
-        if (incl.a < x.a) atomicOr(&st->err, (uint32_t)ERR_OVF_TAU);
-        if (incl.b < x.b) atomicOr(&st->err, (uint32_t)ERR_OVF_LAM);
-        guide_fill(incl.a - x.a, incl.a, st->shift_tau, st->nb_tau, (uint32_t)i, guide_tau, long_tau, long_cap,
-                   &st->nlong_tau, &st->err);
-        guide_fill(incl.b - x.b, incl.b, st->shift_lam, st->nb_lam, (uint32_t)i, guide_lam, long_lam, long_cap,
-                   &st->nlong_lam, &st->err);
-    }
-};
 
 // guide shape from the totals, and the sentinel guide[nb] = last slot
 __global__ void k_guide_setup(PrepStats *st, int64_t slots, uint32_t *guide_tau, uint32_t *guide_lam)
@@ -362,6 +337,98 @@ __global__ void k_guide_setup(PrepStats *st, int64_t slots, uint32_t *guide_tau,
     st->nb_lam = nbl;
     if (Rt) guide_tau[nbt] = (uint32_t)(slots - 1);
     if (Rl) guide_lam[nbl] = (uint32_t)(slots - 1);
+}
+
+// Launch 3 of the weights scan: the prefixes from the parked weights, the
+// wrap checks and the guide entries.  Blocked arrangement: thread t of a tile
+// owns kWItems consecutive slots, scans them sequentially, and only the
+// thread totals go through a wave scan (one 64-lane scan per thread instead
+// of one per item).  The tiles are those of k_weights_reduce.
+__global__ __launch_bounds__(kBlock) void k_weights_apply(uint64_t *__restrict__ p_tau, uint64_t *__restrict__ p_lam,
+                                                          int64_t N, const U64x2 *__restrict__ tile_prefix,
+                                                          uint32_t *__restrict__ guide_tau,
+                                                          uint32_t *__restrict__ guide_lam,
+                                                          uint32_t *__restrict__ long_tau,
+                                                          uint32_t *__restrict__ long_lam, uint32_t long_cap,
+                                                          PrepStats *st)
+{
+    __shared__ U64x2 s_wave[kBlock / kWave];
+    const int w = threadIdx.x / kWave;
+    const int lane = lane_id();
+    const int64_t base = (int64_t)blockIdx.x * (kBlock * kWItems) + (int64_t)threadIdx.x * kWItems;
+    const uint32_t sh_t = st->shift_tau, sh_l = st->shift_lam;
+    const uint64_t nb_t = st->nb_tau, nb_l = st->nb_lam;
+    uint64_t a[kWItems], b[kWItems];
+    if (base + kWItems <= N) {
+        // 128 contiguous bytes per array and thread, as 16-byte loads
+        const uint4 *pa = reinterpret_cast<const uint4 *>(p_tau + base);
+        const uint4 *pb = reinterpret_cast<const uint4 *>(p_lam + base);
+#pragma unroll
+        for (int i = 0; i < kWItems / 2; ++i) {
+            const uint4 x = pa[i], y = pb[i];
+            a[2 * i] = (uint64_t)x.x | ((uint64_t)x.y << 32);
+            a[2 * i + 1] = (uint64_t)x.z | ((uint64_t)x.w << 32);
+            b[2 * i] = (uint64_t)y.x | ((uint64_t)y.y << 32);
+            b[2 * i + 1] = (uint64_t)y.z | ((uint64_t)y.w << 32);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kWItems; ++i) {
+            a[i] = base + i < N ? p_tau[base + i] : 0ull;
+            b[i] = base + i < N ? p_lam[base + i] : 0ull;
+        }
+    }
+    // thread-local inclusive sums
+#pragma unroll
+    for (int i = 1; i < kWItems; ++i) {
+        a[i] += a[i - 1];
+        b[i] += b[i - 1];
+    }
+    // exclusive prefix of the thread inside the tile
+    const U64x2 tot{a[kWItems - 1], b[kWItems - 1]};
+    const U64x2 incl = wave_inclusive(tot, PairSumOp(), U64x2{0, 0});
+    if (lane == kWave - 1) s_wave[w] = incl;
+    __syncthreads();
+    U64x2 run = tile_prefix[blockIdx.x];
+    for (int i = 0; i < w; ++i) run = PairSumOp()(run, s_wave[i]);
+    run.a += incl.a - tot.a;
+    run.b += incl.b - tot.b;
+    uint32_t err = 0;
+    uint64_t prev_a = run.a, prev_b = run.b;
+#pragma unroll
+    for (int i = 0; i < kWItems; ++i) {
+        const int64_t idx = base + i;
+        if (idx >= N) break;
+        const uint64_t ia = run.a + a[i], ib = run.b + b[i];
+        // the running sum passed 2^64 exactly where it decreases
+        if (ia < prev_a) err |= ERR_OVF_TAU;
+        if (ib < prev_b) err |= ERR_OVF_LAM;
+        guide_fill(prev_a, ia, sh_t, nb_t, (uint32_t)idx, guide_tau, long_tau, long_cap, &st->nlong_tau, &st->err);
+        guide_fill(prev_b, ib, sh_l, nb_l, (uint32_t)idx, guide_lam, long_lam, long_cap, &st->nlong_lam, &st->err);
+        a[i] = ia;
+        b[i] = ib;
+        prev_a = ia;
+        prev_b = ib;
+    }
+    if (base + kWItems <= N) {
+        uint4 *pa = reinterpret_cast<uint4 *>(p_tau + base);
+        uint4 *pb = reinterpret_cast<uint4 *>(p_lam + base);
+#pragma unroll
+        for (int i = 0; i < kWItems / 2; ++i) {
+            pa[i] = make_uint4((uint32_t)a[2 * i], (uint32_t)(a[2 * i] >> 32), (uint32_t)a[2 * i + 1],
+                               (uint32_t)(a[2 * i + 1] >> 32));
+            pb[i] = make_uint4((uint32_t)b[2 * i], (uint32_t)(b[2 * i] >> 32), (uint32_t)b[2 * i + 1],
+                               (uint32_t)(b[2 * i + 1] >> 32));
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kWItems; ++i)
+            if (base + i < N) {
+                p_tau[base + i] = a[i];
+                p_lam[base + i] = b[i];
+            }
+    }
+    if (err) atomicOr(&st->err, err);
 }
 
 // N_1 = sum_v C(d_v, 3) in 128 bits; isolated vertices.  One pair of
@@ -731,11 +798,9 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
             PM_HIP(hipGetLastError());
             PM_TRY(mid());
             ProfScope pa("weights.apply", s);
-            hipLaunchKernelGGL((scan_apply_kernel<U64x2, kWItems, PairSumOp, WeightsLoad, WeightsOut>),
-                               dim3((unsigned)tiles), dim3(kBlock), 0, s, WeightsLoad{g->p_tau, g->p_lam},
-                               WeightsOut{g->p_tau, g->p_lam, g->guide_tau, g->guide_lam, long_tau, long_lam,
-                                          (uint32_t)long_cap, st},
-                               slots, PairSumOp(), U64x2{0, 0}, (const U64x2 *)sums);
+            hipLaunchKernelGGL(k_weights_apply, dim3((unsigned)tiles), dim3(kBlock), 0, s, g->p_tau, g->p_lam, slots,
+                               (const U64x2 *)sums, g->guide_tau, g->guide_lam, long_tau, long_lam,
+                               (uint32_t)long_cap, st);
             PM_HIP(hipGetLastError());
         }
         if (slots > 0) {

@@ -59,10 +59,26 @@ __global__ __launch_bounds__(kRadixThreads) void radix_histogram(const uint32_t 
     const int t = threadIdx.x, w = t / kWave, lane = lane_id();
     for (int j = t; j < kRadixWaves * kRadixBins; j += kRadixThreads) (&hist[0][0])[j] = 0;
     __syncthreads();
+    const int64_t tile0 = (int64_t)blockIdx.x * kRadixTile;
+    if (tile0 + kRadixTile <= N && ((uintptr_t)keys & 15u) == 0) {
+        // whole tile: counting ignores order, so each lane takes 16-byte loads
+        const uint4 *k4 = reinterpret_cast<const uint4 *>(keys + tile0 + (int64_t)w * kRadixWaveSpan);
+        uint4 v[kRadixItems / 4];
 #pragma unroll
-    for (int i = 0; i < kRadixItems; ++i) {
-        int64_t idx = radix_index(blockIdx.x, w, i, lane);
-        if (idx < N) atomicAdd(&hist[w][(keys[idx] >> shift) & mask], 1u);
+        for (int q = 0; q < kRadixItems / 4; ++q) v[q] = k4[q * kWave + lane];
+#pragma unroll
+        for (int q = 0; q < kRadixItems / 4; ++q) {
+            atomicAdd(&hist[w][(v[q].x >> shift) & mask], 1u);
+            atomicAdd(&hist[w][(v[q].y >> shift) & mask], 1u);
+            atomicAdd(&hist[w][(v[q].z >> shift) & mask], 1u);
+            atomicAdd(&hist[w][(v[q].w >> shift) & mask], 1u);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kRadixItems; ++i) {
+            int64_t idx = radix_index(blockIdx.x, w, i, lane);
+            if (idx < N) atomicAdd(&hist[w][(keys[idx] >> shift) & mask], 1u);
+        }
     }
     __syncthreads();
     if (t < kRadixBins) {
