@@ -93,6 +93,25 @@ def measure_copy(stream, reps: int = 5) -> float:
     return 2 * COPY_BYTES / (ms / n * 1e-3) / 1e9
 
 
+def measure_gather(stream, count: int = 1 << 28, reps: int = 3) -> float:
+    """Measured random-access ceiling: independent 4-byte loads at random
+    positions of a 2 GiB table (loads per second; each touches its own line)."""
+    import torch
+
+    from paper_1411_4942_amd import pathsamp as ps
+
+    t = torch.empty(COPY_BYTES * 2 // 4, dtype=torch.int32, device="cuda").fill_(3)
+    ps.device_gather(t, count, seed=7, stream=stream)
+    ps.profile_enable(True)
+    for r in range(reps):
+        ps.device_gather(t, count, seed=11 + r, stream=stream)
+    torch.cuda.synchronize()
+    n, ms = ps.profile_read()["random_gather"]
+    ps.profile_enable(False)
+    del t
+    return count / (ms / n * 1e-3)
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -217,6 +236,51 @@ def batched_leg(count: int, k: int, replays: int) -> dict:
     return out
 
 
+def ingest_leg(scale: int, edge_factor: float, seed: int, k: int, want: dict, reps: int = 3) -> dict:
+    """End to end from the raw pair list: the R-MAT draws (loops and repeats
+    included) through pm_graph_from_edges and pm_count."""
+    import torch
+
+    from paper_1411_4942_amd import pathsamp as ps
+    from paper_1411_4942_amd import synth
+
+    u, v = synth.rmat_edges_torch(scale, edge_factor, seed=seed, device="cuda")
+    src, dst = u.to(torch.int32), v.to(torch.int32)
+    del u, v
+    n = 1 << scale
+    stream = torch.cuda.current_stream()
+
+    def once():
+        g = ps.Graph.from_edges(n, src, dst, stream=stream)
+        r = g.count(k, k, seed=1, stream=stream)
+        g.destroy()
+        return r
+
+    res = once()
+    ps.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        res = once()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ps.profile_read()
+    ps.profile_enable(False)
+    ms = 1e3 * (t1 - t0) / reps
+    out = {
+        "workload": f"raw R-MAT scale {scale} draws ({src.numel()} pairs, loops and repeats included) -> "
+                    f"CSR on the device -> prepare -> k={k} per sampler",
+        "pairs": int(src.numel()),
+        "ingest_ms": prof["ingest_total"][1] / prof["ingest_total"][0],
+        "end_to_end_ms": ms,
+        "end_to_end_samples_per_s": 2 * k / (ms * 1e-3),
+        "same_tallies_as_csr_input": res["tally_path"] == want["tally_path"] and res["tally_cent"] == want["tally_cent"],
+    }
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
 def served_leg(count: int, n_sat: int, n_open: int, loads, rel_err: float, delta: float, k_max: int,
                plain_check: int) -> dict:
     """A pool of resident graphs behind the request server: closed-loop
@@ -332,6 +396,7 @@ def main():
     ap.add_argument("--cpu-scale", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-ingest", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--batch-graphs", type=int, default=256)
     ap.add_argument("--batch-k", type=int, default=200_000)
@@ -382,6 +447,7 @@ def main():
     value = 2 * k / ((t1 - t0) / args.steps)
     log(f"[bench] {args.steps} steps: {ms_per_step:.2f} ms/step")
     copy_gbs = measure_copy(stream)
+    gather_per_s = measure_gather(stream)
 
     # per-kernel averages (HIP events on the launch stream)
     kernels = {name: {"launches": n, "avg_ms": ms / n, "ms_per_step": ms / args.steps}
@@ -409,6 +475,13 @@ def main():
     dom_name = max(timed, key=lambda n: timed[n]["ms_per_step"])
     roofline = roofline_for(dom_name, kernels[dom_name], alg[dom_name], traffic, copy_gbs)
     roofline_sampler = roofline_for("sample_path", kernels["sample_path"], alg["sample_path"], traffic, copy_gbs)
+    # line-granular view: fetched lines per sample against the random-load ceiling
+    roofline_sampler["random_loads_per_s_ceiling"] = gather_per_s
+    if roofline_sampler["traffic"]:
+        lines = roofline_sampler["traffic"] / 128.0 / k
+        roofline_sampler["lines_per_sample"] = lines
+        roofline_sampler["lines_per_s"] = lines * k / (kernels["sample_path"]["avg_ms"] * 1e-3)
+        roofline_sampler["frac_of_random_ceiling"] = roofline_sampler["lines_per_s"] / gather_per_s
     samp_ms = [kernels[n]["avg_ms"] for n in ("sample_path", "sample_centered") if n in kernels]
 
     out = {
@@ -439,6 +512,10 @@ def main():
         "estimates": res["est"][1:],
         "rel_bar_halfwidth": [((h - l) / 2 / e if e else None) for e, l, h in zip(res["est"][1:], res["lo"][1:], res["hi"][1:])],
     }
+    if not args.no_ingest:
+        log("[bench] ingest leg ...")
+        out["ingest"] = ingest_leg(args.scale, args.edge_factor, args.seed, k, res)
+        log(f"[bench] ingest: {out['ingest']['ingest_ms']:.2f} ms, end to end {out['ingest']['end_to_end_ms']:.2f} ms")
     if not args.no_batched:
         log("[bench] batched leg ...")
         out["batched"] = batched_leg(args.batch_graphs, args.batch_k, replays=5)

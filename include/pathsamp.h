@@ -149,6 +149,36 @@ pm_status pm_count(const pm_graph *g, const pm_params *p, pm_result *out, void *
 pm_status pm_sample_async(const pm_graph *g, const pm_params *p, uint64_t *tallies_dev, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Edge-list ingest                                                          */
+/* ------------------------------------------------------------------------ */
+
+/* A list of vertex pairs (src[e], dst[e]), e < num_edges, over vertices
+ * 0..n-1.  Buffers on the device (on_device = 1) or the host (0, copied). */
+typedef struct {
+    int64_t n;
+    int64_t num_edges;
+    const int32_t *src;
+    const int32_t *dst;
+    int32_t on_device;
+} pm_edge_view;
+
+/* The undirected simple graph of an edge list, as CSR (the clean-up of the
+ * paper's inputs, Section 6): every pair is an undirected edge, so both
+ * directions become slots; self-loops are dropped; repeated pairs (in either
+ * direction) are merged.  Rows come out strictly ascending.  off[n+1] and
+ * col[capacity] are caller-owned device buffers; capacity = 2 * num_edges
+ * always suffices; *slots_out = 2m.  Returns after the CSR is written (the
+ * stream is synchronised).  Errors: PM_EINVAL (null, sizes, capacity too
+ * small -- the message names the size needed), PM_EGRAPH (an endpoint
+ * outside [0, n)), PM_ENOMEM, PM_EDEVICE. */
+pm_status pm_csr_from_edges(const pm_edge_view *edges, int64_t *off, int32_t *col, int64_t capacity,
+                            int64_t *slots_out, void *stream);
+
+/* pm_csr_from_edges into library memory, then pm_graph_create on it (the
+ * intermediate CSR is freed).  The end-to-end path from a raw edge list. */
+pm_status pm_graph_from_edges(const pm_edge_view *edges, uint32_t flags, void *stream, pm_graph **out);
+
+/* ------------------------------------------------------------------------ */
 /* Batched sampling: many prepared graphs in one launch                      */
 /* ------------------------------------------------------------------------ */
 
@@ -349,6 +379,13 @@ pm_status pm_philox_device(const uint32_t *in, uint32_t *out, int64_t count);
  * streaming ceiling.  Pointers aligned to 16 bytes, bytes a multiple of 16,
  * else PM_EINVAL. */
 pm_status pm_device_copy(void *dst, const void *src, uint64_t bytes, void *stream);
+
+/* count independent 4-byte loads at pseudo-random positions (a splitmix64
+ * stream from seed) of a device table of `bytes` bytes, asynchronous on
+ * `stream`: the measured ceiling for line-granular random access, against
+ * which the samplers' line traffic is read.  Table 4-byte aligned, at least
+ * 4 bytes, count >= 0, else PM_EINVAL. */
+pm_status pm_device_gather(const void *table, uint64_t bytes, int64_t count, uint64_t seed, void *stream);
 
 /* Per-kernel timing with HIP events recorded on each launch's stream.
  * pm_profile_enable clears the totals and switches recording on (1) or off

@@ -29,6 +29,7 @@ pm_status chernoff_interval(uint64_t count, uint64_t k, double delta, double *p_
 pm_status samples_for_error(double rel_err, double delta, double alpha, uint64_t *k_out);
 pm_status philox_device(const uint32_t *in, uint32_t *out, int64_t count);
 pm_status device_copy(void *dst, const void *src, uint64_t bytes, hipStream_t s);
+pm_status device_gather(const void *table, uint64_t bytes, int64_t count, uint64_t seed, hipStream_t s);
 pm_status dev_alloc(void **p, size_t bytes, hipStream_t s);
 void dev_free(void *p, hipStream_t s);
 pm_status count_on_graph(const pm_graph *g, const pm_params *p, pm_result *out, hipStream_t s);
@@ -39,6 +40,9 @@ pm_status batch_set_params(pm_batch *b, const pm_params *params);
 pm_status batch_run(pm_batch *b, pm_result *out, hipStream_t user_stream);
 pm_status batch_get_tune(const pm_batch *b, pm_tune *out);
 pm_status batch_destroy(pm_batch *b);
+pm_status csr_from_edges(const pm_edge_view *ev, int64_t *off, int32_t *col, int64_t capacity, int64_t *slots_out,
+                         hipStream_t s);
+pm_status graph_from_edges(const pm_edge_view *ev, uint32_t flags, hipStream_t s, pm_graph **out);
 pm_status samples_for_request(const uint64_t tp[PM_NUM_TALLIES], const uint64_t tc[PM_NUM_TALLIES], uint64_t k0,
                               uint64_t W, uint64_t Lambda, uint64_t N1, uint32_t mask, double rel_err, double delta,
                               uint64_t k_max, uint64_t *k_path, uint64_t *k_cent, uint32_t *capped, uint32_t *unseen);
@@ -165,6 +169,17 @@ pm_status pm_chernoff_interval(uint64_t count, uint64_t k, double delta, double 
     PM_GUARD(return pm::chernoff_interval(count, k, delta, p_lo, p_hi);)
 }
 
+pm_status pm_csr_from_edges(const pm_edge_view *edges, int64_t *off, int32_t *col, int64_t capacity,
+                            int64_t *slots_out, void *stream)
+{
+    PM_GUARD(return pm::csr_from_edges(edges, off, col, capacity, slots_out, (hipStream_t)stream);)
+}
+
+pm_status pm_graph_from_edges(const pm_edge_view *edges, uint32_t flags, void *stream, pm_graph **out)
+{
+    PM_GUARD(return pm::graph_from_edges(edges, flags, (hipStream_t)stream, out);)
+}
+
 pm_status pm_samples_for_error(double rel_err, double delta, double alpha, uint64_t *k_out)
 {
     PM_GUARD(return pm::samples_for_error(rel_err, delta, alpha, k_out);)
@@ -266,6 +281,11 @@ pm_status pm_count_batch(const pm_graph *const *graphs, const pm_params *params,
 pm_status pm_device_copy(void *dst, const void *src, uint64_t bytes, void *stream)
 {
     PM_GUARD(return pm::device_copy(dst, src, bytes, (hipStream_t)stream);)
+}
+
+pm_status pm_device_gather(const void *table, uint64_t bytes, int64_t count, uint64_t seed, void *stream)
+{
+    PM_GUARD(return pm::device_gather(table, bytes, count, seed, (hipStream_t)stream);)
 }
 
 pm_status pm_philox_device(const uint32_t *in, uint32_t *out, int64_t count)

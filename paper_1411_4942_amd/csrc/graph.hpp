@@ -2,6 +2,8 @@
 // sampling kernels take.
 #pragma once
 
+#include <vector>
+
 #include "common.hpp"
 #include "ladder.hpp"
 
@@ -68,5 +70,39 @@ inline SamplerView view_of(const pm_graph *g, bool centered)
 // device memory through the stream-ordered allocator
 pm_status dev_alloc(void **p, size_t bytes, hipStream_t s);
 void dev_free(void *p, hipStream_t s);
+
+// Scoped temporaries: every block still held is freed (stream-ordered) when
+// the owner goes out of scope; keep() hands a block over to its new owner.
+struct Temps {
+    hipStream_t s;
+    std::vector<void *> ptrs;
+    explicit Temps(hipStream_t st) : s(st) {}
+    ~Temps()
+    {
+        for (void *p : ptrs) dev_free(p, s);
+    }
+    template <typename T>
+    pm_status get(T **p, size_t count)
+    {
+        void *q = nullptr;
+        PM_TRY(dev_alloc(&q, count * sizeof(T), s));
+        ptrs.push_back(q);
+        *p = (T *)q;
+        return PM_OK;
+    }
+    void release(void *p)
+    {
+        for (auto &q : ptrs)
+            if (q == p) {
+                dev_free(q, s);
+                q = nullptr;
+            }
+    }
+    void keep(void *p)
+    {
+        for (auto &q : ptrs)
+            if (q == p) q = nullptr;
+    }
+};
 
 }  // namespace pm

@@ -505,37 +505,6 @@ __global__ __launch_bounds__(kBlock) void k_guide_long(const uint64_t *__restric
 
 namespace {
 
-struct Temps {
-    hipStream_t s;
-    std::vector<void *> ptrs;
-    explicit Temps(hipStream_t st) : s(st) {}
-    ~Temps()
-    {
-        for (void *p : ptrs) dev_free(p, s);
-    }
-    template <typename T>
-    pm_status get(T **p, size_t count)
-    {
-        void *q = nullptr;
-        PM_TRY(dev_alloc(&q, count * sizeof(T), s));
-        ptrs.push_back(q);
-        *p = (T *)q;
-        return PM_OK;
-    }
-    void release(void *p)
-    {
-        for (auto &q : ptrs)
-            if (q == p) {
-                dev_free(q, s);
-                q = nullptr;
-            }
-    }
-    void keep(void *p)
-    {
-        for (auto &q : ptrs)
-            if (q == p) q = nullptr;
-    }
-};
 
 int grid_stream(int64_t n) { return grid_for(n, kBlock, 1 << 22); }
 

@@ -17,6 +17,9 @@
 
 namespace pm {
 
+// Kernels and helpers are local to each translation unit that sorts.
+namespace {
+
 #ifndef PM_RADIX_THREADS
 #define PM_RADIX_THREADS 512
 #endif
@@ -416,5 +419,7 @@ inline pm_status radix_sort(const char *name, const uint32_t *in_k, const uint32
     if (pair_out) *out_k = nullptr;
     return PM_OK;
 }
+
+}  // namespace
 
 }  // namespace pm

@@ -145,6 +145,48 @@ pm_status device_copy(void *dst, const void *src, uint64_t bytes, hipStream_t s)
     return PM_OK;
 }
 
+// Independent random 4-byte loads from a table: the ceiling for line-granular
+// random access (each load touches its own line).  Indices come from a
+// splitmix64 stream; the XOR of the loaded words keeps the loads live.
+__global__ __launch_bounds__(kBlock) void k_random_gather(const uint32_t *__restrict__ table, uint64_t words,
+                                                         int64_t count, uint64_t seed,
+                                                         unsigned long long *__restrict__ sink)
+{
+    uint32_t acc = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(i + 1);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        acc ^= table[z % words];
+    }
+    const uint32_t r = wave_sum_u32(acc);  // keeps every load; the value itself is not used
+    if (lane_id() == 0 && r == 0xFFFFFFFFu) atomicAdd(sink, 1ull);
+}
+
+pm_status device_gather(const void *table, uint64_t bytes, int64_t count, uint64_t seed, hipStream_t s)
+{
+    if (!table || bytes < 4 || count < 0 || ((uintptr_t)table & 3u) != 0) {
+        set_error("device_gather: device table of at least 4 bytes, 4-byte aligned, count >= 0");
+        return PM_EINVAL;
+    }
+    if (count == 0) return PM_OK;
+    unsigned long long *sink = nullptr;
+    PM_TRY(dev_alloc((void **)&sink, sizeof(unsigned long long), s));
+    {
+        ProfScope prof("random_gather", s);
+        hipLaunchKernelGGL(k_random_gather, dim3(grid_for(count, kBlock, 1 << 22)), dim3(kBlock), 0, s,
+                           (const uint32_t *)table, bytes / 4, count, seed, sink);
+    }
+    hipError_t e = hipGetLastError();
+    dev_free(sink, s);
+    if (e != hipSuccess) {
+        set_error(std::string("device_gather: ") + hipGetErrorString(e));
+        return PM_EDEVICE;
+    }
+    return PM_OK;
+}
+
 pm_status philox_device(const uint32_t *in, uint32_t *out, int64_t count)
 {
     if (count < 0 || (count > 0 && (!in || !out))) {

@@ -57,6 +57,11 @@ class ProfileEntry(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double)]
 
 
+class EdgeView(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("num_edges", ctypes.c_int64), ("src", ctypes.c_void_p),
+                ("dst", ctypes.c_void_p), ("on_device", ctypes.c_int32)]
+
+
 class Tune(ctypes.Structure):
     _fields_ = [("samples_per_tile", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
 
@@ -118,6 +123,7 @@ _SIGNATURES = {
                                               ctypes.POINTER(ctypes.c_uint64)]),
     "pm_philox_device": (ctypes.c_int32, [_P, _P, ctypes.c_int64]),
     "pm_device_copy": (ctypes.c_int32, [_P, _P, ctypes.c_uint64, _P]),
+    "pm_device_gather": (ctypes.c_int32, [_P, ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint64, _P]),
     "pm_set_sampler_shape": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32]),
     "pm_release_cached_memory": (ctypes.c_int32, []),
     "pm_profile_enable": (ctypes.c_int32, [ctypes.c_int32]),
@@ -143,6 +149,9 @@ _SIGNATURES = {
     "pm_server_cancel": (ctypes.c_int32, [_P, ctypes.c_uint64]),
     "pm_server_get_stats": (ctypes.c_int32, [_P, ctypes.POINTER(ServerStats)]),
     "pm_server_destroy": (ctypes.c_int32, [_P]),
+    "pm_csr_from_edges": (ctypes.c_int32, [ctypes.POINTER(EdgeView), _P, _P, ctypes.c_int64,
+                                           ctypes.POINTER(ctypes.c_int64), _P]),
+    "pm_graph_from_edges": (ctypes.c_int32, [ctypes.POINTER(EdgeView), ctypes.c_uint32, _P, ctypes.POINTER(_P)]),
     "pm_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "pm_last_error": (ctypes.c_char_p, []),
 }
@@ -206,6 +215,44 @@ def _csr_view(off, col):
     return v, (off, col)
 
 
+def _edge_view(n, src, dst):
+    """EdgeView over torch CUDA tensors or host arrays (int32); returns the
+    view and the objects that keep the memory alive."""
+    try:
+        import torch
+    except ImportError:  # pragma: no cover
+        torch = None
+    if torch is not None and isinstance(src, torch.Tensor):
+        if src.dtype != torch.int32 or dst.dtype != torch.int32 or src.numel() != dst.numel():
+            raise TypeError("src and dst must be int32 tensors of one length")
+        if src.is_cuda and dst.is_cuda:
+            src, dst = src.contiguous(), dst.contiguous()
+            return EdgeView(n, src.numel(), src.data_ptr() if src.numel() else None,
+                            dst.data_ptr() if dst.numel() else None, 1), (src, dst)
+        src, dst = src.cpu().numpy(), dst.cpu().numpy()
+    src = np.ascontiguousarray(src, dtype=np.int32)
+    dst = np.ascontiguousarray(dst, dtype=np.int32)
+    if src.size != dst.size:
+        raise ValueError("src and dst differ in length")
+    return EdgeView(n, src.size, src.ctypes.data if src.size else None, dst.ctypes.data if dst.size else None,
+                    0), (src, dst)
+
+
+def csr_from_edges(n: int, src, dst, stream=None):
+    """pm_csr_from_edges: (row_offsets int64[n+1], cols int32[2m]) as CUDA tensors."""
+    import torch
+
+    view, keep = _edge_view(n, src, dst)
+    cap = 2 * view.num_edges
+    off = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    col = torch.empty(max(cap, 1), dtype=torch.int32, device="cuda")
+    slots = ctypes.c_int64()
+    _check(lib().pm_csr_from_edges(ctypes.byref(view), off.data_ptr(), col.data_ptr(), cap, ctypes.byref(slots),
+                                   _stream_ptr(stream)), "pm_csr_from_edges")
+    del keep
+    return off, col[:slots.value].clone()
+
+
 class Graph:
     """A prepared graph resident on the current device (pm_graph handle)."""
 
@@ -221,6 +268,18 @@ class Graph:
     @property
     def handle(self):
         return self._h
+
+    @classmethod
+    def from_edges(cls, n: int, src, dst, flags: int = PM_VALIDATE | PM_CHECK_SYMMETRY, stream=None):
+        """pm_graph_from_edges: ingest an edge list and prepare it in one call."""
+        view, keep = _edge_view(n, src, dst)
+        g = cls.__new__(cls)
+        h = ctypes.c_void_p()
+        _check(lib().pm_graph_from_edges(ctypes.byref(view), flags, _stream_ptr(stream), ctypes.byref(h)),
+               "pm_graph_from_edges")
+        g._h = h
+        del keep
+        return g
 
     def info(self) -> dict:
         gi = GraphInfo()
@@ -461,6 +520,12 @@ def device_copy(dst, src, stream=None):
     if dst.numel() * dst.element_size() != nbytes:
         raise ValueError("tensors differ in size")
     _check(lib().pm_device_copy(dst.data_ptr(), src.data_ptr(), nbytes, _stream_ptr(stream)), "pm_device_copy")
+
+
+def device_gather(table, count: int, seed: int = 1, stream=None):
+    """pm_device_gather over a CUDA tensor (asynchronous)."""
+    _check(lib().pm_device_gather(table.data_ptr(), table.numel() * table.element_size(), count, seed,
+                                  _stream_ptr(stream)), "pm_device_gather")
 
 
 def profile_enable(on: bool = True):

@@ -235,6 +235,14 @@ def _csr_from_edges_torch(n: int, u, v):
 def rmat_torch(scale: int, edge_factor: float, abcd=(0.57, 0.19, 0.19, 0.05), seed: int = 1,
                device="cuda", chunk: int = 1 << 25):
     """R-MAT as :func:`rmat`, drawn with torch's generator on ``device``."""
+    u, v = rmat_edges_torch(scale, edge_factor, abcd, seed, device, chunk)
+    return _csr_from_edges_torch(1 << scale, u, v)
+
+
+def rmat_edges_torch(scale: int, edge_factor: float, abcd=(0.57, 0.19, 0.19, 0.05), seed: int = 1,
+                     device="cuda", chunk: int = 1 << 25):
+    """The raw directed R-MAT draws (int64 u, v) behind :func:`rmat_torch`:
+    loops and repeats included, not symmetrised."""
     import torch
 
     n = 1 << scale
@@ -258,7 +266,7 @@ def rmat_torch(scale: int, edge_factor: float, abcd=(0.57, 0.19, 0.19, 0.05), se
     u = torch.cat(us)
     v = torch.cat(vs)
     del us, vs
-    return _csr_from_edges_torch(n, u, v)
+    return u, v
 
 
 def chung_lu_torch(n: int, m: int, gamma: float, w_max: float, seed: int, device="cuda"):
