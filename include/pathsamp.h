@@ -149,6 +149,27 @@ pm_status pm_count(const pm_graph *g, const pm_params *p, pm_result *out, void *
 pm_status pm_sample_async(const pm_graph *g, const pm_params *p, uint64_t *tallies_dev, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Exact counts (ground truth)                                               */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    uint64_t C[7];      /* induced counts, index = motif number (1..6) */
+    uint64_t N[7];      /* subgraph (not necessarily induced) counts of Eq. 1 */
+    uint64_t triangles;
+} pm_exact;
+
+/* Exact counts of a prepared graph on the device, split as the paper's
+ * enumeration code (Section 6): N_1 = sum C(d,3), N_2 = W - 3T,
+ * N_3 = sum_v t_v (d_v - 2), N_5 = sum_e C(t_e, 2) from triangles per edge;
+ * N_4 (4-cycles) and N_6 (4-cliques) by enumeration under the degree order;
+ * then Eq. 1 solved for C.  Work grows like the wedge count (hours-free up
+ * to ~1e8 edges of power-law graphs); device scratch of 8 n bytes per
+ * counting block (256 blocks) besides 4 bytes per slot.  Synchronises the
+ * stream.  Errors: PM_EINVAL, PM_EOVERFLOW (a count >= 2^64), PM_ENOMEM,
+ * PM_EDEVICE. */
+pm_status pm_exact_counts(const pm_graph *g, pm_exact *out, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Edge-list ingest                                                          */
 /* ------------------------------------------------------------------------ */
 

@@ -43,6 +43,7 @@ pm_status batch_destroy(pm_batch *b);
 pm_status csr_from_edges(const pm_edge_view *ev, int64_t *off, int32_t *col, int64_t capacity, int64_t *slots_out,
                          hipStream_t s);
 pm_status graph_from_edges(const pm_edge_view *ev, uint32_t flags, hipStream_t s, pm_graph **out);
+pm_status exact_counts(const pm_graph *g, pm_exact *out, hipStream_t s);
 pm_status samples_for_request(const uint64_t tp[PM_NUM_TALLIES], const uint64_t tc[PM_NUM_TALLIES], uint64_t k0,
                               uint64_t W, uint64_t Lambda, uint64_t N1, uint32_t mask, double rel_err, double delta,
                               uint64_t k_max, uint64_t *k_path, uint64_t *k_cent, uint32_t *capped, uint32_t *unseen);
@@ -167,6 +168,11 @@ pm_status pm_finalize(const uint64_t tally_path[PM_NUM_TALLIES], const uint64_t 
 pm_status pm_chernoff_interval(uint64_t count, uint64_t k, double delta, double *p_lo, double *p_hi)
 {
     PM_GUARD(return pm::chernoff_interval(count, k, delta, p_lo, p_hi);)
+}
+
+pm_status pm_exact_counts(const pm_graph *g, pm_exact *out, void *stream)
+{
+    PM_GUARD(return pm::exact_counts(g, out, (hipStream_t)stream);)
 }
 
 pm_status pm_csr_from_edges(const pm_edge_view *edges, int64_t *off, int32_t *col, int64_t capacity,

@@ -1,0 +1,300 @@
+// Exact induced 4-vertex counts on the device: ground truth at sizes the
+// sampler runs at, split the way the paper describes its enumeration code
+// (Section 6): the cycle-based subgraph counts by enumeration under the
+// degree order, the others by formulas, then Eq. 1 solved for the induced
+// counts.
+//
+// On the prepared graph vertex ids are ranks of the degree order and every
+// row is ascending, so N+(x) (neighbours of higher rank) is the row suffix
+// after position split[x] and the lower neighbours are the prefix.
+//   N_1 = sum_v C(d_v, 3)                  (already in the prepared graph)
+//   N_2 = W - 3T                           3-paths (W from the tau total)
+//   N_3 = sum_v t_v (d_v - 2) = 1/2 sum_e t_e (d_u + d_v - 4)
+//   N_4 = 4-cycles: at each cycle's highest vertex x, pairs of lower wedge
+//         middles between x and each lower opposite vertex y
+//   N_5 = sum_e C(t_e, 2)                  diamonds
+//   N_6 = 4-cliques u < v < w < x: x in N+(u) ^ N+(v) ^ N+(w)
+// t_e = triangles on edge e (each found once, from its lowest vertex).
+#include <algorithm>
+#include <cstring>
+
+#include "graph.hpp"
+#include "profile.hpp"
+
+namespace pm {
+
+pm_status check_device(const pm_graph *g);
+
+namespace {
+
+struct ExactAcc {
+    unsigned long long tri;           // triangles (each once)
+    unsigned long long k4;            // 4-cliques (each once)
+    unsigned long long n3_lo, n3_hi;  // 2 N_3
+    unsigned long long n5_lo, n5_hi;  // N_5
+    unsigned long long n4_lo, n4_hi;  // N_4
+};
+
+// 128-bit accumulation from per-block partial sums
+__device__ void add128(unsigned long long *lo, unsigned long long *hi, unsigned __int128 v)
+{
+    const unsigned long long l = (unsigned long long)v, h = (unsigned long long)(v >> 64);
+    const unsigned long long old = atomicAdd(lo, l);
+    const unsigned long long carry = (old + l < old) ? 1ull : 0ull;
+    if (h + carry) atomicAdd(hi, h + carry);
+}
+
+// Sum of one 128-bit value per thread over the block, valid in thread 0.
+// Every thread of the block must call it.
+template <int THREADS>
+__device__ unsigned __int128 block_sum128(unsigned __int128 v)
+{
+    __shared__ unsigned long long s_lo[THREADS], s_hi[THREADS];
+    __syncthreads();  // a previous call's readers are done with the arrays
+    s_lo[threadIdx.x] = (unsigned long long)v;
+    s_hi[threadIdx.x] = (unsigned long long)(v >> 64);
+    __syncthreads();
+    for (int d = THREADS / 2; d > 0; d >>= 1) {
+        if ((int)threadIdx.x < d) {
+            const unsigned __int128 a = (unsigned __int128)s_lo[threadIdx.x] |
+                                        ((unsigned __int128)s_hi[threadIdx.x] << 64);
+            const unsigned __int128 b = (unsigned __int128)s_lo[threadIdx.x + d] |
+                                        ((unsigned __int128)s_hi[threadIdx.x + d] << 64);
+            const unsigned __int128 c = a + b;
+            s_lo[threadIdx.x] = (unsigned long long)c;
+            s_hi[threadIdx.x] = (unsigned long long)(c >> 64);
+        }
+        __syncthreads();
+    }
+    return (unsigned __int128)s_lo[0] | ((unsigned __int128)s_hi[0] << 64);
+}
+
+// split[x] = number of neighbours of x below x (rows ascending)
+__global__ __launch_bounds__(kBlock) void k_split(const int64_t *__restrict__ off, const uint32_t *__restrict__ col,
+                                                  int64_t n, uint32_t *__restrict__ split)
+{
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+        int64_t lo = off[x], hi = off[x + 1];
+        const int64_t a = lo;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (col[mid] < (uint32_t)x)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        split[x] = (uint32_t)(lo - a);
+    }
+}
+
+// One forward slot s = (u, v), v > u, per thread: the triangles {u, v, w},
+// w > v, found by merging N+(u) beyond v with N+(v); each adds one to t_e of
+// its three edges (slots (u,v), (u,w), (v,w), all forward).  For each such w
+// the 4-cliques {u, v, w, x}, x > w, come from the rest of the merge, each x
+// checked against N+(w).
+__global__ __launch_bounds__(kBlock) void k_triangles(const int64_t *__restrict__ off,
+                                                      const uint32_t *__restrict__ col,
+                                                      const uint64_t *__restrict__ edge,
+                                                      const uint32_t *__restrict__ split, int64_t slots,
+                                                      uint32_t *__restrict__ t_e, ExactAcc *acc)
+{
+    unsigned long long tri = 0, k4 = 0;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < slots;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t e = edge[s];
+        const uint32_t u = (uint32_t)e, v = (uint32_t)(e >> 32);
+        if (v <= u) continue;
+        const int64_t a0 = s + 1, a1 = off[u + 1];
+        const int64_t b0 = off[v] + split[v], b1 = off[v + 1];
+        int64_t i = a0, j = b0;
+        uint32_t here = 0;
+        while (i < a1 && j < b1) {
+            const uint32_t x = col[i], y = col[j];
+            if (x < y) {
+                ++i;
+            } else if (y < x) {
+                ++j;
+            } else {
+                const uint32_t w = x;
+                ++here;
+                atomicAdd(&t_e[i], 1u);  // (u, w)
+                atomicAdd(&t_e[j], 1u);  // (v, w)
+                // 4-cliques through (u, v, w): the rest of N+(u) ^ N+(v), in N+(w)
+                int64_t i2 = i + 1, j2 = j + 1, k = off[w] + split[w];
+                const int64_t k1 = off[w + 1];
+                while (i2 < a1 && j2 < b1 && k < k1) {
+                    const uint32_t p = col[i2], q = col[j2];
+                    if (p < q) {
+                        ++i2;
+                    } else if (q < p) {
+                        ++j2;
+                    } else {
+                        while (k < k1 && col[k] < p) ++k;
+                        if (k < k1 && col[k] == p) ++k4;
+                        ++i2;
+                        ++j2;
+                    }
+                }
+                ++i;
+                ++j;
+            }
+        }
+        if (here) atomicAdd(&t_e[s], here);  // (u, v)
+        tri += here;
+    }
+    const unsigned __int128 bt = block_sum128<kBlock>(tri);
+    const unsigned __int128 bk = block_sum128<kBlock>(k4);
+    if (threadIdx.x == 0) {
+        if (bt) atomicAdd(&acc->tri, (unsigned long long)bt);
+        if (bk) atomicAdd(&acc->k4, (unsigned long long)bk);
+    }
+}
+
+// Sums over forward slots: 2 N_3 = sum t_e (d_u + d_v - 4), N_5 = sum C(t_e, 2)
+__global__ __launch_bounds__(kBlock) void k_edge_sums(const int64_t *__restrict__ off,
+                                                      const uint64_t *__restrict__ edge,
+                                                      const uint32_t *__restrict__ t_e, int64_t slots,
+                                                      ExactAcc *acc)
+{
+    unsigned __int128 n3 = 0, n5 = 0;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < slots;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t e = edge[s];
+        const uint32_t u = (uint32_t)e, v = (uint32_t)(e >> 32);
+        const uint64_t t = t_e[s];
+        if (v <= u || t == 0) continue;
+        const uint64_t du = (uint64_t)(off[u + 1] - off[u]), dv = (uint64_t)(off[v + 1] - off[v]);
+        n3 += (unsigned __int128)t * (du + dv - 4);  // t > 0 means both degrees >= 2
+        n5 += (unsigned __int128)(t * (t - 1) / 2);
+    }
+    n3 = block_sum128<kBlock>(n3);
+    n5 = block_sum128<kBlock>(n5);
+    if (threadIdx.x == 0) {
+        if (n3) add128(&acc->n3_lo, &acc->n3_hi, n3);
+        if (n5) add128(&acc->n5_lo, &acc->n5_hi, n5);
+    }
+}
+
+// 4-cycles by the highest vertex x: block b takes x = n-1-b, n-1-b-G, ...
+// (the hubs, with the most wedges, first).  For each lower neighbour w of x
+// and each lower neighbour y of w below x, cnt[y] += 1 in the block's own
+// counter array; then sum C(cnt[y], 2) over the touched y and clear them.
+constexpr int kC4Threads = 1024;
+
+__global__ __launch_bounds__(kC4Threads) void k_four_cycles(const int64_t *__restrict__ off,
+                                                            const uint32_t *__restrict__ col,
+                                                            const uint32_t *__restrict__ split, int64_t n,
+                                                            uint32_t *__restrict__ cnt_all,
+                                                            uint32_t *__restrict__ touched_all, ExactAcc *acc)
+{
+    __shared__ uint32_t s_nt;
+    uint32_t *cnt = cnt_all + (int64_t)blockIdx.x * n;
+    uint32_t *touched = touched_all + (int64_t)blockIdx.x * n;
+    const int w_id = threadIdx.x / kWave, lane = lane_id(), nw = kC4Threads / kWave;
+    unsigned __int128 n4 = 0;
+    for (int64_t b = blockIdx.x; b < n; b += gridDim.x) {
+        const int64_t x = n - 1 - b;
+        if (threadIdx.x == 0) s_nt = 0;
+        __syncthreads();
+        const int64_t lo_end = off[x] + split[x];
+        for (int64_t p = off[x] + w_id; p < lo_end; p += nw) {
+            const uint32_t w = col[p];  // w < x
+            const int64_t r0 = off[w], r1 = off[w + 1];
+            for (int64_t q = r0 + lane; q < r1; q += kWave) {
+                const uint32_t y = col[q];
+                if (y >= (uint32_t)x) break;  // rows ascending: the rest are higher too
+                if (atomicAdd(&cnt[y], 1u) == 0u) touched[atomicAdd(&s_nt, 1u)] = y;
+            }
+        }
+        __syncthreads();
+        const uint32_t nt = s_nt;
+        for (uint32_t i = threadIdx.x; i < nt; i += blockDim.x) {
+            const uint32_t y = touched[i];
+            const uint64_t c = cnt[y];
+            n4 += (unsigned __int128)(c * (c - 1) / 2);
+            cnt[y] = 0;
+        }
+        __syncthreads();  // counters clear before the next x
+    }
+    n4 = block_sum128<kC4Threads>(n4);
+    if (threadIdx.x == 0 && n4) add128(&acc->n4_lo, &acc->n4_hi, n4);
+}
+
+}  // namespace
+
+pm_status exact_counts(const pm_graph *g, pm_exact *out, hipStream_t s)
+{
+    if (!g || !out) {
+        set_error("exact_counts: null argument");
+        return PM_EINVAL;
+    }
+    PM_TRY(check_device(g));
+    std::memset(out, 0, sizeof(*out));
+    const int64_t n = g->n, slots = g->slots;
+    Temps tmp(s);
+    ExactAcc *acc = nullptr;
+    PM_TRY(tmp.get(&acc, 1));
+    PM_TRY(fill_async<unsigned char>((unsigned char *)acc, 0, (int64_t)sizeof(ExactAcc), s));
+    ProfScope prof_total("exact_total", s);
+    if (slots > 0) {
+        uint32_t *split = nullptr, *t_e = nullptr;
+        PM_TRY(tmp.get(&split, (size_t)n));
+        PM_TRY(tmp.get(&t_e, (size_t)slots));
+        PM_TRY(fill_async<uint32_t>(t_e, 0u, slots, s));
+        hipLaunchKernelGGL(k_split, dim3(grid_for(n, kBlock, 1 << 22)), dim3(kBlock), 0, s, g->off, g->col, n, split);
+        {
+            ProfScope prof("exact.triangles", s);
+            hipLaunchKernelGGL(k_triangles, dim3(grid_for(slots, kBlock, 1 << 16)), dim3(kBlock), 0, s, g->off,
+                               g->col, g->edge, split, slots, t_e, acc);
+        }
+        hipLaunchKernelGGL(k_edge_sums, dim3(grid_for(slots, kBlock, 4096)), dim3(kBlock), 0, s, g->off, g->edge,
+                           t_e, slots, acc);
+        PM_HIP(hipGetLastError());
+        tmp.release(t_e);
+        // 4-cycles: one counter array and one touched list of n words per block
+        const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(256, n));
+        uint32_t *cnt = nullptr, *touched = nullptr;
+        PM_TRY(tmp.get(&cnt, (size_t)blocks * (size_t)n));
+        PM_TRY(tmp.get(&touched, (size_t)blocks * (size_t)n));
+        PM_TRY(fill_async<uint32_t>(cnt, 0u, (int64_t)blocks * n, s));
+        {
+            ProfScope prof("exact.four_cycles", s);
+            hipLaunchKernelGGL(k_four_cycles, dim3(blocks), dim3(kC4Threads), 0, s, g->off, g->col, split, n, cnt,
+                               touched, acc);
+        }
+        PM_HIP(hipGetLastError());
+    }
+    ExactAcc h;
+    PM_HIP(hipMemcpyAsync(&h, acc, sizeof(h), hipMemcpyDeviceToHost, s));
+    PM_HIP(hipStreamSynchronize(s));
+
+    typedef __int128 i128;
+    typedef unsigned __int128 u128;
+    const u128 n3x2 = (u128)h.n3_lo | ((u128)h.n3_hi << 64);
+    const u128 n5 = (u128)h.n5_lo | ((u128)h.n5_hi << 64);
+    const u128 n4 = (u128)h.n4_lo | ((u128)h.n4_hi << 64);
+    const i128 N1 = (i128)g->N1, N2 = (i128)(g->R_tau / 2) - 3 * (i128)h.tri, N3 = (i128)(n3x2 / 2),
+               N4 = (i128)n4, N5 = (i128)n5, N6 = (i128)h.k4;
+    // Eq. 1 (N = A C) is upper triangular with unit diagonal; entry (i, j) is
+    // the number of copies of motif i inside motif j
+    const i128 c6 = N6;
+    const i128 c5 = N5 - 6 * c6;
+    const i128 c4 = N4 - c5 - 3 * c6;
+    const i128 c3 = N3 - 4 * c5 - 12 * c6;
+    const i128 c2 = N2 - 2 * c3 - 4 * c4 - 6 * c5 - 12 * c6;
+    const i128 c1 = N1 - c3 - 2 * c5 - 4 * c6;
+    const i128 Ns[7] = {0, N1, N2, N3, N4, N5, N6};
+    const i128 Cs[7] = {0, c1, c2, c3, c4, c5, c6};
+    for (int i = 1; i <= 6; ++i) {
+        if (Cs[i] < 0 || Cs[i] >= ((i128)1 << 64) || Ns[i] < 0 || Ns[i] >= ((i128)1 << 64)) {
+            set_error("exact_counts: a count does not fit in 64 bits");
+            return PM_EOVERFLOW;
+        }
+        out->C[i] = (uint64_t)Cs[i];
+        out->N[i] = (uint64_t)Ns[i];
+    }
+    out->triangles = h.tri;
+    return PM_OK;
+}
+
+}  // namespace pm

@@ -57,6 +57,10 @@ class ProfileEntry(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double)]
 
 
+class Exact(ctypes.Structure):
+    _fields_ = [("C", ctypes.c_uint64 * 7), ("N", ctypes.c_uint64 * 7), ("triangles", ctypes.c_uint64)]
+
+
 class EdgeView(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("num_edges", ctypes.c_int64), ("src", ctypes.c_void_p),
                 ("dst", ctypes.c_void_p), ("on_device", ctypes.c_int32)]
@@ -149,6 +153,7 @@ _SIGNATURES = {
     "pm_server_cancel": (ctypes.c_int32, [_P, ctypes.c_uint64]),
     "pm_server_get_stats": (ctypes.c_int32, [_P, ctypes.POINTER(ServerStats)]),
     "pm_server_destroy": (ctypes.c_int32, [_P]),
+    "pm_exact_counts": (ctypes.c_int32, [_P, ctypes.POINTER(Exact), _P]),
     "pm_csr_from_edges": (ctypes.c_int32, [ctypes.POINTER(EdgeView), _P, _P, ctypes.c_int64,
                                            ctypes.POINTER(ctypes.c_int64), _P]),
     "pm_graph_from_edges": (ctypes.c_int32, [ctypes.POINTER(EdgeView), ctypes.c_uint32, _P, ctypes.POINTER(_P)]),
@@ -304,6 +309,12 @@ class Graph:
         r = Result()
         _check(lib().pm_count(self._h, ctypes.byref(p), ctypes.byref(r), _stream_ptr(stream)), "pm_count")
         return r.to_dict()
+
+    def exact(self, stream=None) -> dict:
+        """pm_exact_counts: {"C": [0, C1..C6], "N": [0, N1..N6], "triangles": T}."""
+        e = Exact()
+        _check(lib().pm_exact_counts(self._h, ctypes.byref(e), _stream_ptr(stream)), "pm_exact_counts")
+        return {"C": [int(x) for x in e.C], "N": [int(x) for x in e.N], "triangles": int(e.triangles)}
 
     def sample_async(self, tallies, k_path: int, k_cent: int, seed: int, first_path: int = 0, first_cent: int = 0,
                      stream=None):
