@@ -457,18 +457,15 @@ def main():
     alg = {
         "sample_path": (BYTES_PER_SAMPLE * k, "pm::k_sample<false,"),
         "sample_centered": (BYTES_PER_SAMPLE * k, "pm::k_sample<true,"),
-        # one pass: read key + value, write key + value (the last pass of the
-        # transpose sort writes the interleaved edge array instead of the keys)
-        "transpose_sort.scatter": (16 * slots, "pm::radix_scatter"),
+        # one pass: read key + value, write key + value
         "reverse_sort.scatter": (16 * slots, "pm::radix_scatter"),
-        "transpose_sort.histogram": (4 * slots, "pm::radix_histogram"),
         "reverse_sort.histogram": (4 * slots, "pm::radix_histogram"),
+        # per slot: input column 4, its rank 4, column 4 and edge 8 written
+        "build_rows": (20 * slots, "pm::k_rows_block"),
         # per slot: edge 8 + rev 4 + key2 4, both rows' offset pairs 32, the two weights written 16
         "weights.reduce": (64 * slots, "pm::k_weights_reduce"),
         # per slot: both weights read 16, both prefixes written 16, guide entries 2 (2m/4 buckets each)
         "weights.apply": (34 * slots, "pm::scan_apply_kernel<pm::U64x2"),
-        # per input slot: column 4, its rank 4, key and value written 8
-        "place_rows": (16 * slots, "pm::k_place_rows"),
     }
     traffic = load_traffic()
     timed = {n: v for n, v in kernels.items() if n in alg}

@@ -117,84 +117,296 @@ struct OffOut {
     __device__ __forceinline__ void operator()(int64_t i, uint64_t incl, uint64_t) const { off[i + 1] = (int64_t)incl; }
 };
 
-// Row holding slot p: upper_bound(off, p) - 1 over [lo, hi), all 64 lanes
-// probing together (64-ary search); p is the same in every lane.
-__device__ __forceinline__ int64_t wave_row_of(const int64_t *__restrict__ off, int64_t n, int64_t p)
+// ---------------------------------------------------------------------------
+// Relabelled rows built sorted (Section 4's order: ids are ranks, rows
+// ascending).  New row i is input row u = order[i] with every column c
+// mapped to rank[c]; rows are sorted where they are built, by size class:
+//   degree <= 16          one lane per row, a sorting network in registers
+//   16 < degree <= 64     one wave per row, a sorting network across lanes
+//   64 < degree <= 16384  one block per row sized to the class (64, 64, 256
+//                         or 1024 threads), stable LSD radix sort in LDS
+//   degree > 16384        (the few hub rows, all at the end of the order)
+//                         placed unsorted, then two global radix sorts
+// Each class writes col, edge = row | col << 32, and ladder level 1 (every
+// 32nd column) at the row's final slots, and checks the input row (column
+// range, self-loop, strictly ascending).
+// ---------------------------------------------------------------------------
+
+constexpr int kLaneRowMax = 16;
+
+// the checks of one input slot p (row u, previous column prev or -1)
+__device__ __forceinline__ uint32_t slot_checks(int64_t c, int64_t u, int64_t prev, int64_t n)
 {
-    int64_t lo = 0, hi = n + 1;  // first x with off[x] > p lies in [lo, hi]
-    const int lane = lane_id();
-    while (hi - lo > 1) {
-        const int64_t step = (hi - lo + kWave - 1) / kWave;
-        const int64_t x = lo + (int64_t)(lane + 1) * step;
-        const bool le = x < hi && off[x] <= p;
-        const uint64_t m = __ballot(le);
-        const int cnt = __popcll(m);  // probes at or below p form a prefix
-        const int64_t nlo = lo + (int64_t)cnt * step;
-        const int64_t nhi = lo + (int64_t)(cnt + 1) * step;
-        lo = nlo;
-        hi = nhi < hi ? nhi : hi;
-    }
-    return lo;  // off[lo] <= p < off[lo + 1] (lo is the last x with off[x] <= p)
+    uint32_t e = 0;
+    if (c < 0 || c >= n) e |= ERR_RANGE;
+    if (c == u) e |= ERR_LOOP;
+    if (prev >= c) e |= ERR_ORDER;
+    return e;
 }
 
-// G1: every input slot moved into the row of its vertex's new id, columns
-// mapped to new ids (rows not yet sorted).  Slot-parallel: each wave owns
-// 1024 consecutive slots (16 coalesced rows of 64); a 64-ary search brackets
-// the rows they fall in, then each lane locates its slots' rows inside the
-// bracket, its lower bound only moving forward.  The same pass checks every
-// slot: column in range, no self-loop, strictly above the previous column of
-// its row.  An out-of-range column is flagged and left unwritten (the caller
-// stops on the flag).  Offsets were checked before this runs.
-constexpr int kPlaceItems = 16;
-
-__global__ __launch_bounds__(kBlock) void k_place_rows(const int64_t *__restrict__ off_in,
-                                                       const int32_t *__restrict__ col_in, int64_t n, int64_t slots,
-                                                       const int32_t *__restrict__ rank,
-                                                       const int64_t *__restrict__ off_new,
-                                                       uint32_t *__restrict__ key, uint32_t *__restrict__ val,
-                                                       PrepStats *st)
+__device__ __forceinline__ void emit_slot(int64_t p, uint32_t row, uint32_t c, uint32_t *__restrict__ col,
+                                          uint64_t *__restrict__ edge, uint32_t *__restrict__ ladder1)
 {
-    const int lane = lane_id();
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
-    const int64_t span = (int64_t)kWave * kPlaceItems;
-    const int64_t ranges = (slots + span - 1) / span;
+    col[p] = c;
+    edge[p] = (uint64_t)row | ((uint64_t)c << 32);
+    if (ladder1 && (p & 31) == 0) ladder1[p >> 5] = c;
+}
+
+__device__ __forceinline__ void cswap(uint32_t &a, uint32_t &b)
+{
+    const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+    a = lo;
+    b = hi;
+}
+
+// rows [r0, r1) with degree <= 16, one lane each: bitonic network on 16
+// registers (absent entries are 0xFFFFFFFF and sort last)
+__global__ __launch_bounds__(kBlock) void k_rows_lane(const int64_t *__restrict__ off_in,
+                                                      const int32_t *__restrict__ col_in,
+                                                      const uint32_t *__restrict__ order,
+                                                      const int32_t *__restrict__ rank,
+                                                      const int64_t *__restrict__ off_new, int64_t n, int64_t r0,
+                                                      int64_t r1, uint32_t *__restrict__ col,
+                                                      uint64_t *__restrict__ edge, uint32_t *__restrict__ ladder1,
+                                                      PrepStats *st)
+{
+    const int64_t i = r0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t err = 0;
-    for (int64_t rg = wave; rg < ranges; rg += nwaves) {
-        const int64_t p0 = rg * span;
-        const int64_t plast = (p0 + span - 1 < slots) ? p0 + span - 1 : slots - 1;
-        const int64_t ufirst = wave_row_of(off_in, n, p0);
-        const int64_t ulast = wave_row_of(off_in, n, plast);
-        int64_t lo0 = ufirst;  // rows of this lane's slots never decrease
-#pragma unroll 4
-        for (int i = 0; i < kPlaceItems; ++i) {
-            const int64_t p = p0 + (int64_t)i * kWave + lane;
-            if (p >= slots) break;
-            // last u in [lo0, ulast] with off_in[u] <= p
-            int64_t lo = lo0, hi = ulast + 1;
-            while (hi - lo > 1) {
-                const int64_t mid = (lo + hi) >> 1;
-                if (off_in[mid] <= p)
-                    lo = mid;
-                else
-                    hi = mid;
+    if (i < r1) {
+        const int64_t u = order[i], a = off_in[u], d = off_in[u + 1] - a;
+        uint32_t k[kLaneRowMax];
+        int64_t prev = -1;
+#pragma unroll
+        for (int j = 0; j < kLaneRowMax; ++j) {
+            k[j] = 0xFFFFFFFFu;
+            if (j < d) {
+                const int64_t c = col_in[a + j];
+                err |= slot_checks(c, u, prev, n);
+                prev = c;
+                k[j] = (c >= 0 && c < n) ? (uint32_t)rank[c] : 0u;
             }
-            lo0 = lo;
-            const int64_t u = lo, a = off_in[u];
-            const int32_t c = col_in[p];
-            if (c < 0 || (int64_t)c >= n) {
-                err |= ERR_RANGE;
-                continue;
-            }
-            if (c == (int32_t)u) err |= ERR_LOOP;
-            if (p > a && col_in[p - 1] >= c) err |= ERR_ORDER;
-            const int32_t ru = rank[u];
-            const int64_t dst = off_new[ru] + (p - a);
-            key[dst] = (uint32_t)rank[c];
-            val[dst] = (uint32_t)ru;
         }
+#pragma unroll
+        for (int size = 2; size <= kLaneRowMax; size <<= 1)
+#pragma unroll
+            for (int stride = size >> 1; stride > 0; stride >>= 1)
+#pragma unroll
+                for (int j = 0; j < kLaneRowMax; ++j) {
+                    const int l = j ^ stride;
+                    if (l > j) {
+                        if ((j & size) == 0)
+                            cswap(k[j], k[l]);
+                        else
+                            cswap(k[l], k[j]);
+                    }
+                }
+        const int64_t dst = off_new[i];
+#pragma unroll
+        for (int j = 0; j < kLaneRowMax; ++j)
+            if (j < d) emit_slot(dst + j, (uint32_t)i, k[j], col, edge, ladder1);
     }
     if (err) atomicOr(&st->err, err);
+}
+
+// rows [r0, r1) with 16 < degree <= 64, one wave each: bitonic network
+// across the 64 lanes (absent entries are 0xFFFFFFFF and sort last)
+__global__ __launch_bounds__(kBlock) void k_rows_wave(const int64_t *__restrict__ off_in,
+                                                      const int32_t *__restrict__ col_in,
+                                                      const uint32_t *__restrict__ order,
+                                                      const int32_t *__restrict__ rank,
+                                                      const int64_t *__restrict__ off_new, int64_t n, int64_t r0,
+                                                      int64_t r1, uint32_t *__restrict__ col,
+                                                      uint64_t *__restrict__ edge, uint32_t *__restrict__ ladder1,
+                                                      PrepStats *st)
+{
+    const int64_t i = r0 + ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    if (i >= r1) return;  // whole waves leave together
+    const int lane = lane_id();
+    const int64_t u = order[i], a = off_in[u], d = off_in[u + 1] - a;
+    uint32_t err = 0, v = 0xFFFFFFFFu;
+    if (lane < d) {
+        const int64_t c = col_in[a + lane];
+        const int64_t prev = lane > 0 ? (int64_t)col_in[a + lane - 1] : -1;
+        err = slot_checks(c, u, prev, n);
+        v = (c >= 0 && c < n) ? (uint32_t)rank[c] : 0u;
+    }
+#pragma unroll
+    for (int size = 2; size <= kWave; size <<= 1)
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const uint32_t o = __shfl_xor(v, stride, kWave);
+            const bool up = (lane & size) == 0, low = (lane & stride) == 0;
+            v = (up == low) ? (v < o ? v : o) : (v < o ? o : v);
+        }
+    if (lane < d) emit_slot(off_new[i] + lane, (uint32_t)i, v, col, edge, ladder1);
+    if (err) atomicOr(&st->err, err);
+}
+
+// Stable LSD radix sort of up to THREADS * ITEMS keys in LDS (8-bit digits,
+// `bits` key bits): wave w ranks its contiguous chunk with ballots and per-wave
+// digit counters, the counters become output positions, the keys move to the
+// other buffer.  Returns the buffer holding the result.  Every thread of the
+// block calls it.
+template <int THREADS, int ITEMS>
+__device__ uint32_t *block_radix_lds(uint32_t *a, uint32_t *b, int nk, int bits, uint32_t *s_cnt, uint32_t *s_tot)
+{
+    constexpr int W = THREADS / kWave;
+    const int t = threadIdx.x, w = t / kWave, lane = lane_id();
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    for (int shift = 0; shift < bits; shift += 8) {
+        const uint32_t mask = (bits - shift >= 8) ? 0xFFu : ((1u << (bits - shift)) - 1u);
+        for (int j = t; j < W * 256; j += THREADS) s_cnt[j] = 0;
+        __syncthreads();
+        uint32_t rank[ITEMS], dig[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            if ((w * ITEMS + i) * kWave >= nk) break;  // wave-uniform: the rest of this wave's rows are empty
+            const int idx = (w * ITEMS + i) * kWave + lane;
+            const bool ok = idx < nk;
+            dig[i] = ok ? (a[idx] >> shift) & mask : 0u;
+            uint64_t peers = __ballot(ok);
+#pragma unroll
+            for (int bb = 0; bb < 8; ++bb) {
+                const uint64_t bal = __ballot((dig[i] >> bb) & 1u);
+                peers &= ((dig[i] >> bb) & 1u) ? bal : ~bal;
+            }
+            const uint32_t below = __popcll(peers & lt_mask);
+            const uint32_t base = s_cnt[w * 256 + dig[i]];
+            rank[i] = base + below;
+            if (ok && below == 0) s_cnt[w * 256 + dig[i]] = base + (uint32_t)__popcll(peers);
+        }
+        __syncthreads();
+        for (int d0 = t; d0 < 256; d0 += THREADS) {
+            uint32_t tot = 0;
+            for (int ww = 0; ww < W; ++ww) tot += s_cnt[ww * 256 + d0];
+            s_tot[d0] = tot;
+        }
+        __syncthreads();
+        if (t < kWave) {  // exclusive scan of the 256 totals, 4 per lane
+            const uint32_t v0 = s_tot[4 * t], v1 = s_tot[4 * t + 1], v2 = s_tot[4 * t + 2], v3 = s_tot[4 * t + 3];
+            const uint32_t loc = v0 + v1 + v2 + v3;
+            uint32_t incl = loc;
+#pragma unroll
+            for (int dd = 1; dd < kWave; dd <<= 1) {
+                const uint32_t o = __shfl_up(incl, dd, kWave);
+                if (lane >= dd) incl += o;
+            }
+            const uint32_t ex = incl - loc;
+            s_tot[4 * t] = ex;
+            s_tot[4 * t + 1] = ex + v0;
+            s_tot[4 * t + 2] = ex + v0 + v1;
+            s_tot[4 * t + 3] = ex + v0 + v1 + v2;
+        }
+        __syncthreads();
+        for (int d0 = t; d0 < 256; d0 += THREADS) {
+            uint32_t run = s_tot[d0];
+            for (int ww = 0; ww < W; ++ww) {
+                const uint32_t c = s_cnt[ww * 256 + d0];
+                s_cnt[ww * 256 + d0] = run;
+                run += c;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            if ((w * ITEMS + i) * kWave >= nk) break;
+            const int idx = (w * ITEMS + i) * kWave + lane;
+            if (idx < nk) b[s_cnt[w * 256 + dig[i]] + rank[i]] = a[idx];
+        }
+        __syncthreads();
+        uint32_t *tmp = a;
+        a = b;
+        b = tmp;
+    }
+    return a;
+}
+
+// rows [r0, r0 + gridDim.x), degree <= THREADS * ITEMS, one block each
+template <int THREADS, int ITEMS>
+__global__ __launch_bounds__(THREADS) void k_rows_block(const int64_t *__restrict__ off_in,
+                                                        const int32_t *__restrict__ col_in,
+                                                        const uint32_t *__restrict__ order,
+                                                        const int32_t *__restrict__ rank,
+                                                        const int64_t *__restrict__ off_new, int64_t n, int64_t r0,
+                                                        int bits, uint32_t *__restrict__ col,
+                                                        uint64_t *__restrict__ edge, uint32_t *__restrict__ ladder1,
+                                                        PrepStats *st)
+{
+    constexpr int CAP = THREADS * ITEMS;
+    __shared__ uint32_t s_a[CAP], s_b[CAP];
+    __shared__ uint32_t s_cnt[(THREADS / kWave) * 256];
+    __shared__ uint32_t s_tot[256];
+    const int64_t i = r0 + blockIdx.x;
+    const int64_t u = order[i], a = off_in[u];
+    const int d = (int)(off_in[u + 1] - a);  // <= CAP by the class bounds
+    uint32_t err = 0;
+    for (int j = threadIdx.x; j < d; j += THREADS) {
+        const int64_t c = col_in[a + j];
+        const int64_t prev = j > 0 ? (int64_t)col_in[a + j - 1] : -1;
+        err |= slot_checks(c, u, prev, n);
+        s_a[j] = (c >= 0 && c < n) ? (uint32_t)rank[c] : 0u;
+    }
+    __syncthreads();
+    const uint32_t *sorted = block_radix_lds<THREADS, ITEMS>(s_a, s_b, d, bits, s_cnt, s_tot);
+    const int64_t dst = off_new[i];
+    for (int j = threadIdx.x; j < d; j += THREADS) emit_slot(dst + j, (uint32_t)i, sorted[j], col, edge, ladder1);
+    if (err) atomicOr(&st->err, err);
+}
+
+// hub rows [r0, n): one block per row places (key = new column, value = row
+// - r0) at the row's slots relative to off_new[r0]
+__global__ __launch_bounds__(kBlock) void k_rows_tail_place(const int64_t *__restrict__ off_in,
+                                                            const int32_t *__restrict__ col_in,
+                                                            const uint32_t *__restrict__ order,
+                                                            const int32_t *__restrict__ rank,
+                                                            const int64_t *__restrict__ off_new, int64_t n,
+                                                            int64_t r0, uint32_t *__restrict__ key,
+                                                            uint32_t *__restrict__ val, PrepStats *st)
+{
+    const int64_t i = r0 + blockIdx.x;
+    const int64_t u = order[i], a = off_in[u], d = off_in[u + 1] - a;
+    const int64_t base = off_new[i] - off_new[r0];
+    uint32_t err = 0;
+    for (int64_t j = threadIdx.x; j < d; j += blockDim.x) {
+        const int64_t c = col_in[a + j];
+        const int64_t prev = j > 0 ? (int64_t)col_in[a + j - 1] : -1;
+        err |= slot_checks(c, u, prev, n);
+        key[base + j] = (c >= 0 && c < n) ? (uint32_t)rank[c] : 0u;
+        val[base + j] = (uint32_t)(i - r0);
+    }
+    if (err) atomicOr(&st->err, err);
+}
+
+// the sorted hub rows (rows relative to r0, columns) to their final slots
+__global__ __launch_bounds__(kBlock) void k_rows_tail_emit(const uint32_t *__restrict__ row_rel,
+                                                           const uint32_t *__restrict__ cols_sorted, int64_t T,
+                                                           int64_t r0, int64_t p0, uint32_t *__restrict__ col,
+                                                           uint64_t *__restrict__ edge, uint32_t *__restrict__ ladder1)
+{
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < T; q += (int64_t)gridDim.x * blockDim.x)
+        emit_slot(p0 + q, (uint32_t)(r0 + row_rel[q]), cols_sorted[q], col, edge, ladder1);
+}
+
+// first row of each size class (degrees ascend along the new order): cls[c]
+// = first row with degree > {0, 16, 64, 256, 1024, 4096, 16384}[c]; cls[7] =
+// the first slot of row cls[6]
+constexpr int kRowClasses = 7;
+__global__ void k_row_classes(const uint32_t *__restrict__ deg, const int64_t *__restrict__ off, int64_t n,
+                              int64_t *cls)
+{
+    const uint32_t bound[kRowClasses] = {0u, 16u, 64u, 256u, 1024u, 4096u, 16384u};
+    const int c = threadIdx.x;
+    if (c >= kRowClasses) return;
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {  // first row with deg > bound[c]
+        const int64_t mid = (lo + hi) >> 1;
+        if (deg[mid] > bound[c])
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    cls[c] = lo;
+    if (c == kRowClasses - 1) cls[kRowClasses] = off[lo];
 }
 
 // ladder level l from level l-1: next[i] = prev[32 i]
@@ -666,19 +878,12 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
         PM_TRY(tmp.get(&scr, ScanScratch<uint64_t>::bytes_for(n, 16)));
         PM_TRY((scan_launch<uint64_t, 16>(DegIn{g->deg}, OffOut{g->off}, n, SumOp<uint64_t>(), 0ull, scr, s)));
     }
-    tmp.release(vk0);
-    tmp.release(vv0);
-    tmp.release(vk1);
-    tmp.release(vv1);
-
     const int vbits = bits_for(n > 0 ? (uint64_t)(n - 1) : 0);
-    // the column buffers are padded to whole 128-byte lines (ladder level 0)
+    // the column array is padded to whole 128-byte lines (ladder level 0)
     const int64_t ssp = (ss + 31) / 32 * 32 + 32;
-    uint32_t *ka, *va, *kb, *vb;
-    PM_TRY(tmp.get(&ka, ss));
-    PM_TRY(tmp.get(&va, ssp));
-    PM_TRY(tmp.get(&kb, ss));
-    PM_TRY(tmp.get(&vb, ssp));
+    PM_TRY(dev_alloc((void **)&g->col, sizeof(uint32_t) * ssp, s));
+    PM_TRY(dev_alloc((void **)&g->edge, sizeof(uint64_t) * ss, s));
+    g->bytes += (sizeof(uint32_t) + sizeof(uint64_t)) * ss;
 
     // ladder levels 1..top, count(l) = ceil(slots / 32^l); top is the smallest
     // level whose single line covers every slot (32^(top+1) >= slots)
@@ -696,35 +901,96 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
             g->bytes += sizeof(uint32_t) * (total + 32);
         }
     }
+    uint32_t *ladder1 = g->ladder_top > 0 ? g->ladder + g->ladder_off[1] : nullptr;
+
+    // the rows, sorted where they are built (by size class)
     if (slots > 0) {
-        ProfScope prof("place_rows", s);
-        hipLaunchKernelGGL(k_place_rows, dim3(grid_for((slots + kPlaceItems - 1) / kPlaceItems, kBlock, 1 << 22)),
-                           dim3(kBlock), 0, s, off_in, col_in, n, slots, g->rank, g->off, kb, vb, st);
+        int64_t *cls_d = nullptr;
+        PM_TRY(tmp.get(&cls_d, kRowClasses + 1));
+        hipLaunchKernelGGL(k_row_classes, dim3(1), dim3(kWave), 0, s, g->deg, g->off, n, cls_d);
         PM_HIP(hipGetLastError());
+        int64_t cls[kRowClasses + 1];
+        PM_HIP(hipMemcpyAsync(cls, cls_d, sizeof(cls), hipMemcpyDeviceToHost, s));
+        PM_HIP(hipStreamSynchronize(s));
+        ProfScope prof("build_rows", s);
+        if (cls[1] > cls[0]) {
+            ProfScope pc("build_rows.lane", s);
+            hipLaunchKernelGGL(k_rows_lane, dim3((unsigned)((cls[1] - cls[0] + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                               s, off_in, col_in, order, g->rank, g->off, n, cls[0], cls[1], g->col, g->edge, ladder1,
+                               st);
+        }
+        if (cls[2] > cls[1]) {
+            ProfScope pc("build_rows.wave", s);
+            hipLaunchKernelGGL(k_rows_wave, dim3((unsigned)((cls[2] - cls[1] + 3) / 4)), dim3(kBlock), 0, s, off_in,
+                               col_in, order, g->rank, g->off, n, cls[1], cls[2], g->col, g->edge, ladder1, st);
+        }
+        if (cls[3] > cls[2]) {
+            ProfScope pc("build_rows.b256", s);
+            hipLaunchKernelGGL((k_rows_block<64, 4>), dim3((unsigned)(cls[3] - cls[2])), dim3(64), 0, s, off_in,
+                               col_in, order, g->rank, g->off, n, cls[2], vbits, g->col, g->edge, ladder1, st);
+        }
+        if (cls[4] > cls[3]) {
+            ProfScope pc("build_rows.b1024", s);
+            hipLaunchKernelGGL((k_rows_block<64, 16>), dim3((unsigned)(cls[4] - cls[3])), dim3(64), 0, s, off_in,
+                               col_in, order, g->rank, g->off, n, cls[3], vbits, g->col, g->edge, ladder1, st);
+        }
+        if (cls[5] > cls[4]) {
+            ProfScope pc("build_rows.b4096", s);
+            hipLaunchKernelGGL((k_rows_block<256, 16>), dim3((unsigned)(cls[5] - cls[4])), dim3(256), 0, s, off_in,
+                               col_in, order, g->rank, g->off, n, cls[4], vbits, g->col, g->edge, ladder1, st);
+        }
+        if (cls[6] > cls[5]) {
+            ProfScope pc("build_rows.b16384", s);
+            hipLaunchKernelGGL((k_rows_block<1024, 16>), dim3((unsigned)(cls[6] - cls[5])), dim3(1024), 0, s, off_in,
+                               col_in, order, g->rank, g->off, n, cls[5], vbits, g->col, g->edge, ladder1, st);
+        }
+        PM_HIP(hipGetLastError());
+        const int64_t T = slots - cls[kRowClasses];
+        if (T > 0) {
+            // hub rows: placed unsorted, then stably by column and by row
+            uint32_t *tk0, *tv0, *tk1, *tv1, *tk2, *tv2;
+            PM_TRY(tmp.get(&tk0, (size_t)T));
+            PM_TRY(tmp.get(&tv0, (size_t)T));
+            PM_TRY(tmp.get(&tk1, (size_t)T));
+            PM_TRY(tmp.get(&tv1, (size_t)T));
+            PM_TRY(tmp.get(&tk2, (size_t)T));
+            PM_TRY(tmp.get(&tv2, (size_t)T));
+            const int64_t rt = cls[kRowClasses - 1];
+            hipLaunchKernelGGL(k_rows_tail_place, dim3((unsigned)(n - rt)), dim3(kBlock), 0, s, off_in, col_in,
+                               order, g->rank, g->off, n, rt, tk0, tv0, st);
+            PM_HIP(hipGetLastError());
+            uint32_t *kc, *vr;
+            PM_TRY(radix_sort("hub_sort.col", tk0, tv0, tk1, tv1, tk2, tv2, T, vbits, rscr, s, &kc, &vr));
+            uint32_t *ok_ = (kc == tk1) ? tk2 : tk1, *ov_ = (vr == tv1) ? tv2 : tv1;
+            uint32_t *rr, *cc;
+            PM_TRY(radix_sort("hub_sort.row", vr, kc, ok_, ov_, tk0, tv0, T, bits_for((uint64_t)(n - rt - 1)), rscr,
+                              s, &rr, &cc));
+            hipLaunchKernelGGL(k_rows_tail_emit, dim3(grid_for(T, kBlock, 1 << 22)), dim3(kBlock), 0, s, rr, cc, T,
+                               rt, cls[kRowClasses], g->col, g->edge, ladder1);
+            PM_HIP(hipGetLastError());
+        }
     }
-    // the sorts and the weights trust the columns: read the slot checks
+    tmp.release(vk0);
+    tmp.release(vv0);
+    tmp.release(vk1);
+    tmp.release(vv1);
+    // the reverse sort and the weights trust the columns: read the slot checks
     PM_HIP(hipMemcpyAsync(&hst, st, sizeof(hst), hipMemcpyDeviceToHost, s));
     PM_HIP(hipStreamSynchronize(s));
     if (hst.err) {
         set_error(err_text(hst.err));
         return PM_EGRAPH;
     }
-    uint32_t *src_fin, *col_fin;
-    PM_TRY(dev_alloc((void **)&g->edge, sizeof(uint64_t) * ss, s));
-    // G1 sits in (kb, vb); the sort alternates (ka, va) and (kb, vb)
-    PM_TRY(radix_sort("transpose_sort", kb, vb, ka, va, kb, vb, slots, vbits, rscr, s, &src_fin, &col_fin, g->edge,
-                      g->ladder_top > 0 ? g->ladder + g->ladder_off[1] : nullptr));
-    g->col = col_fin;
-    tmp.keep(col_fin);
     for (int l = 2; l <= g->ladder_top; ++l) {
         const int64_t cnt = (int64_t)ladder_count(slots, l);
         hipLaunchKernelGGL(k_ladder_level, dim3(grid_for(cnt, kBlock, 1024)), dim3(kBlock), 0, s,
                            g->ladder + g->ladder_off[l - 1], cnt, g->ladder + g->ladder_off[l]);
         PM_HIP(hipGetLastError());
     }
-    g->bytes += (sizeof(uint32_t) + sizeof(uint64_t)) * ss;
-    uint32_t *vfree = (col_fin == va) ? vb : va;  // keys went into edge: ka, kb are free too
-    uint32_t *v2a;
+    uint32_t *ka, *kb, *vfree, *v2a;
+    PM_TRY(tmp.get(&ka, ss));
+    PM_TRY(tmp.get(&kb, ss));
+    PM_TRY(tmp.get(&vfree, ss));
     PM_TRY(tmp.get(&v2a, ss));
 
     // reverse slots and the symmetry check: the slots' columns sorted stably,
