@@ -123,8 +123,8 @@ struct OffOut {
 // mapped to rank[c]; rows are sorted where they are built, by size class:
 //   degree <= 16          one lane per row, a sorting network in registers
 //   16 < degree <= 64     one wave per row, a sorting network across lanes
-//   64 < degree <= 16384  one block per row sized to the class (64, 64, 256
-//                         or 1024 threads), stable LSD radix sort in LDS
+//   64 < degree <= 16384  one block per row sized to the class (64, 64, 256,
+//                         512 or 1024 threads), stable LSD radix sort in LDS
 //   degree > 16384        (the few hub rows, all at the end of the order)
 //                         placed unsorted, then two global radix sorts
 // Each class writes col, edge = row | col << 32, and ladder level 1 (every
@@ -353,26 +353,35 @@ __global__ __launch_bounds__(THREADS) void k_rows_block(const int64_t *__restric
     if (err) atomicOr(&st->err, err);
 }
 
-// hub rows [r0, n): one block per row places (key = new column, value = row
-// - r0) at the row's slots relative to off_new[r0]
+// hub rows [r0, n), slot-parallel (their degrees run to the hundreds of
+// thousands): tail slot q = off_new[r0] + q finds its row by binary search
+// over the hub rows' offsets, then places (key = new column, value = row - r0)
 __global__ __launch_bounds__(kBlock) void k_rows_tail_place(const int64_t *__restrict__ off_in,
                                                             const int32_t *__restrict__ col_in,
                                                             const uint32_t *__restrict__ order,
                                                             const int32_t *__restrict__ rank,
                                                             const int64_t *__restrict__ off_new, int64_t n,
-                                                            int64_t r0, uint32_t *__restrict__ key,
+                                                            int64_t r0, int64_t T, uint32_t *__restrict__ key,
                                                             uint32_t *__restrict__ val, PrepStats *st)
 {
-    const int64_t i = r0 + blockIdx.x;
-    const int64_t u = order[i], a = off_in[u], d = off_in[u + 1] - a;
-    const int64_t base = off_new[i] - off_new[r0];
+    const int64_t p0 = off_new[r0];
     uint32_t err = 0;
-    for (int64_t j = threadIdx.x; j < d; j += blockDim.x) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < T; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = p0 + q;
+        int64_t lo = r0, hi = n;  // last row i in [r0, n) with off_new[i] <= p
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (off_new[mid] <= p)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const int64_t i = lo, u = order[i], j = p - off_new[i], a = off_in[u];
         const int64_t c = col_in[a + j];
         const int64_t prev = j > 0 ? (int64_t)col_in[a + j - 1] : -1;
         err |= slot_checks(c, u, prev, n);
-        key[base + j] = (c >= 0 && c < n) ? (uint32_t)rank[c] : 0u;
-        val[base + j] = (uint32_t)(i - r0);
+        key[q] = (c >= 0 && c < n) ? (uint32_t)rank[c] : 0u;
+        val[q] = (uint32_t)(i - r0);
     }
     if (err) atomicOr(&st->err, err);
 }
@@ -388,13 +397,13 @@ __global__ __launch_bounds__(kBlock) void k_rows_tail_emit(const uint32_t *__res
 }
 
 // first row of each size class (degrees ascend along the new order): cls[c]
-// = first row with degree > {0, 16, 64, 256, 1024, 4096, 16384}[c]; cls[7] =
-// the first slot of row cls[6]
-constexpr int kRowClasses = 7;
+// = first row with degree > {0, 16, 64, 256, 1024, 4096, 8192, 16384}[c];
+// cls[8] = the first slot of row cls[7]
+constexpr int kRowClasses = 8;
 __global__ void k_row_classes(const uint32_t *__restrict__ deg, const int64_t *__restrict__ off, int64_t n,
                               int64_t *cls)
 {
-    const uint32_t bound[kRowClasses] = {0u, 16u, 64u, 256u, 1024u, 4096u, 16384u};
+    const uint32_t bound[kRowClasses] = {0u, 16u, 64u, 256u, 1024u, 4096u, 8192u, 16384u};
     const int c = threadIdx.x;
     if (c >= kRowClasses) return;
     int64_t lo = 0, hi = n;
@@ -940,9 +949,14 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
                                col_in, order, g->rank, g->off, n, cls[4], vbits, g->col, g->edge, ladder1, st);
         }
         if (cls[6] > cls[5]) {
-            ProfScope pc("build_rows.b16384", s);
-            hipLaunchKernelGGL((k_rows_block<1024, 16>), dim3((unsigned)(cls[6] - cls[5])), dim3(1024), 0, s, off_in,
+            ProfScope pc("build_rows.b8192", s);
+            hipLaunchKernelGGL((k_rows_block<512, 16>), dim3((unsigned)(cls[6] - cls[5])), dim3(512), 0, s, off_in,
                                col_in, order, g->rank, g->off, n, cls[5], vbits, g->col, g->edge, ladder1, st);
+        }
+        if (cls[7] > cls[6]) {
+            ProfScope pc("build_rows.b16384", s);
+            hipLaunchKernelGGL((k_rows_block<1024, 16>), dim3((unsigned)(cls[7] - cls[6])), dim3(1024), 0, s, off_in,
+                               col_in, order, g->rank, g->off, n, cls[6], vbits, g->col, g->edge, ladder1, st);
         }
         PM_HIP(hipGetLastError());
         const int64_t T = slots - cls[kRowClasses];
@@ -956,8 +970,9 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
             PM_TRY(tmp.get(&tk2, (size_t)T));
             PM_TRY(tmp.get(&tv2, (size_t)T));
             const int64_t rt = cls[kRowClasses - 1];
-            hipLaunchKernelGGL(k_rows_tail_place, dim3((unsigned)(n - rt)), dim3(kBlock), 0, s, off_in, col_in,
-                               order, g->rank, g->off, n, rt, tk0, tv0, st);
+            ProfScope pt("build_rows.hubs", s);
+            hipLaunchKernelGGL(k_rows_tail_place, dim3(grid_for(T, kBlock, 1 << 22)), dim3(kBlock), 0, s, off_in,
+                               col_in, order, g->rank, g->off, n, rt, T, tk0, tv0, st);
             PM_HIP(hipGetLastError());
             uint32_t *kc, *vr;
             PM_TRY(radix_sort("hub_sort.col", tk0, tv0, tk1, tv1, tk2, tv2, T, vbits, rscr, s, &kc, &vr));
