@@ -116,13 +116,6 @@ __device__ __forceinline__ void divmod_small(uint64_t a, uint32_t d, uint64_t &q
 }
 
 // wave-wide sums
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
-{
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
-}
-
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
 {
 #pragma unroll

@@ -96,12 +96,6 @@ __global__ __launch_bounds__(kBlock) void k_degrees(const int64_t *__restrict__ 
     }
 }
 
-__global__ void k_iota(uint32_t *p, int64_t n)
-{
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = (uint32_t)i;
-}
-
 __global__ void k_rank_from_order(const uint32_t *__restrict__ order, int32_t *__restrict__ rank, int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)

@@ -21,11 +21,6 @@ struct SumOp {
     __device__ __forceinline__ T operator()(T a, T b) const { return a + b; }
 };
 
-template <typename T>
-struct MaxOp {
-    __device__ __forceinline__ T operator()(T a, T b) const { return a > b ? a : b; }
-};
-
 // a pair of 64-bit sums scanned together
 struct U64x2 {
     uint64_t a, b;
@@ -178,59 +173,6 @@ __global__ __launch_bounds__(kBlock) void scan_apply_kernel(In in, Out out, int6
         if (idx < N) out(idx, op(run, sc), v[i]);
         run = op(run, shfl_idx_t(sc, kWave - 1));
     }
-}
-
-// Variant that evaluates the input functor once: launch 1 also stores each
-// element through St (st(i, x)), launch 3 reads it back through Ld (ld(i)).
-template <typename T, int ITEMS, typename Op, typename In, typename St>
-__global__ __launch_bounds__(kBlock) void scan_reduce_store_kernel(In in, St st, int64_t N, Op op, T identity,
-                                                                   T *tile_sums)
-{
-    __shared__ T s_wave[kBlock / kWave];
-    const int w = threadIdx.x / kWave;
-    const int lane = lane_id();
-    const int64_t wave_base = (int64_t)blockIdx.x * (kBlock * ITEMS) + (int64_t)w * kWave * ITEMS;
-    T acc = identity;
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        int64_t idx = wave_base + (int64_t)i * kWave + lane;
-        if (idx < N) {
-            T x = in(idx);
-            st(idx, x);
-            acc = op(acc, x);
-        }
-    }
-    acc = wave_reduce(acc, op);
-    if (lane == 0) s_wave[w] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        T t = identity;
-#pragma unroll
-        for (int i = 0; i < kBlock / kWave; ++i) t = op(t, s_wave[i]);
-        tile_sums[blockIdx.x] = t;
-    }
-}
-
-// total_out (device, may be null) receives the sum of all elements before
-// launch 3; mid() is called on the host between the tile scan and launch 3
-// (to enqueue work that depends on the total).
-template <typename T, int ITEMS, typename Op, typename In, typename St, typename Ld, typename Out, typename Mid>
-pm_status scan_launch_stored(In in, St st, Ld ld, Out out, int64_t N, Op op, T identity, void *scratch,
-                             hipStream_t s, T *total_out, Mid mid)
-{
-    if (N <= 0) return PM_OK;
-    const int64_t tiles = (N + (int64_t)kBlock * ITEMS - 1) / ((int64_t)kBlock * ITEMS);
-    T *sums = (T *)scratch;
-    hipLaunchKernelGGL((scan_reduce_store_kernel<T, ITEMS, Op, In, St>), dim3((unsigned)tiles), dim3(kBlock), 0, s,
-                       in, st, N, op, identity, sums);
-    PM_HIP(hipGetLastError());
-    hipLaunchKernelGGL((scan_tiles_kernel<T, Op>), dim3(1), dim3(1024), 0, s, sums, tiles, op, identity, total_out);
-    PM_HIP(hipGetLastError());
-    PM_TRY(mid());
-    hipLaunchKernelGGL((scan_apply_kernel<T, ITEMS, Op, Ld, Out>), dim3((unsigned)tiles), dim3(kBlock), 0, s, ld,
-                       out, N, op, identity, (const T *)sums);
-    PM_HIP(hipGetLastError());
-    return PM_OK;
 }
 
 // Scratch for one scan of N elements.
