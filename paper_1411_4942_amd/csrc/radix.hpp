@@ -17,8 +17,8 @@
 
 namespace pm {
 
-// Kernels and helpers are local to each translation unit that sorts.
-namespace {
+// The kernels have internal linkage: each translation unit that sorts keeps
+// its own copy.
 
 #ifndef PM_RADIX_THREADS
 #define PM_RADIX_THREADS 512
@@ -54,7 +54,7 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb)
     return x * per + (x < extra ? x : extra) + i;
 }
 
-__global__ __launch_bounds__(kRadixThreads) void radix_histogram(const uint32_t *__restrict__ keys, int64_t N,
+static __global__ __launch_bounds__(kRadixThreads) void radix_histogram(const uint32_t *__restrict__ keys, int64_t N,
                                                                   int shift, uint32_t mask,
                                                                   uint32_t *__restrict__ counts, int64_t tiles)
 {
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(kRadixThreads) void radix_histogram(const uint32_t 
 // keys_out may be null when pair_out is given: then pair_out[dst] =
 // key | val << 32 replaces the key array (vals_out is always written).
 // sample_out, when given, receives every 32nd value: sample_out[dst / 32].
-__global__ __launch_bounds__(kRadixThreads) void radix_scatter(const uint32_t *__restrict__ keys_in,
+static __global__ __launch_bounds__(kRadixThreads) void radix_scatter(const uint32_t *__restrict__ keys_in,
                                                         const uint32_t *__restrict__ vals_in, int64_t N, int shift,
                                                         uint32_t mask, const uint32_t *__restrict__ offsets,
                                                         int64_t tiles, uint32_t *__restrict__ keys_out,
@@ -219,7 +219,7 @@ constexpr int kRadixChunk = 64;
 constexpr int kRadixBatch = 8;  // loads in flight per thread
 constexpr int kRadixParts = 4;  // threads per digit in the chunk scan
 
-__global__ __launch_bounds__(kBlock) void radix_chunk_sums(const uint32_t *__restrict__ counts, int64_t tiles,
+static __global__ __launch_bounds__(kBlock) void radix_chunk_sums(const uint32_t *__restrict__ counts, int64_t tiles,
                                                            uint32_t *__restrict__ chunk)
 {
     const int d = threadIdx.x;
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(kBlock) void radix_chunk_sums(const uint32_t *__res
 // One block of kRadixParts * 256 threads: thread (p, d) owns a contiguous
 // range of chunks of digit d.  chunk[c][d] becomes the output position of
 // digit d's first key in chunk c.
-__global__ __launch_bounds__(kRadixParts *kBlock) void radix_chunk_scan(uint32_t *__restrict__ chunk,
+static __global__ __launch_bounds__(kRadixParts *kBlock) void radix_chunk_scan(uint32_t *__restrict__ chunk,
                                                                         int64_t nchunks)
 {
     __shared__ uint32_t s_part[kRadixParts][kRadixBins];
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(kRadixParts *kBlock) void radix_chunk_scan(uint32_t
     }
 }
 
-__global__ __launch_bounds__(kBlock) void radix_chunk_apply(const uint32_t *__restrict__ counts,
+static __global__ __launch_bounds__(kBlock) void radix_chunk_apply(const uint32_t *__restrict__ counts,
                                                             const uint32_t *__restrict__ chunk, int64_t tiles,
                                                             uint32_t *__restrict__ offs)
 {
@@ -344,7 +344,7 @@ inline size_t radix_scratch_bytes(int64_t N)
 // With pair_out, the last pass writes key | val << 32 there instead of the
 // keys (*out_k is then null); with sample_out it also writes every 32nd
 // value.  N < 2^32.
-__global__ void radix_pair_copy(const uint32_t *__restrict__ k, const uint32_t *__restrict__ v, int64_t N,
+static __global__ void radix_pair_copy(const uint32_t *__restrict__ k, const uint32_t *__restrict__ v, int64_t N,
                                 uint64_t *__restrict__ pair, uint32_t *__restrict__ sample, uint32_t *__restrict__ vcopy)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
@@ -419,7 +419,5 @@ inline pm_status radix_sort(const char *name, const uint32_t *in_k, const uint32
     if (pair_out) *out_k = nullptr;
     return PM_OK;
 }
-
-}  // namespace
 
 }  // namespace pm
