@@ -70,7 +70,7 @@ __device__ unsigned __int128 block_sum128(unsigned __int128 v)
 }
 
 // split[x] = number of neighbours of x below x (rows ascending)
-__global__ __launch_bounds__(kBlock) void k_split(const int64_t *__restrict__ off, const uint32_t *__restrict__ col,
+__global__ __launch_bounds__(kBlock) void k_split(const uint32_t *__restrict__ off, const uint32_t *__restrict__ col,
                                                   int64_t n, uint32_t *__restrict__ split)
 {
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kBlock) void k_split(const int64_t *__restrict__ of
 // its three edges (slots (u,v), (u,w), (v,w), all forward).  For each such w
 // the 4-cliques {u, v, w, x}, x > w, come from the rest of the merge, each x
 // checked against N+(w).
-__global__ __launch_bounds__(kBlock) void k_triangles(const int64_t *__restrict__ off,
+__global__ __launch_bounds__(kBlock) void k_triangles(const uint32_t *__restrict__ off,
                                                       const uint32_t *__restrict__ col,
                                                       const uint64_t *__restrict__ edge,
                                                       const uint32_t *__restrict__ split, int64_t slots,
@@ -151,7 +151,7 @@ __global__ __launch_bounds__(kBlock) void k_triangles(const int64_t *__restrict_
 }
 
 // Sums over forward slots: 2 N_3 = sum t_e (d_u + d_v - 4), N_5 = sum C(t_e, 2)
-__global__ __launch_bounds__(kBlock) void k_edge_sums(const int64_t *__restrict__ off,
+__global__ __launch_bounds__(kBlock) void k_edge_sums(const uint32_t *__restrict__ off,
                                                       const uint64_t *__restrict__ edge,
                                                       const uint32_t *__restrict__ t_e, int64_t slots,
                                                       ExactAcc *acc)
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(kBlock) void k_edge_sums(const int64_t *__restrict_
 // counter array; then sum C(cnt[y], 2) over the touched y and clear them.
 constexpr int kC4Threads = 1024;
 
-__global__ __launch_bounds__(kC4Threads) void k_four_cycles(const int64_t *__restrict__ off,
+__global__ __launch_bounds__(kC4Threads) void k_four_cycles(const uint32_t *__restrict__ off,
                                                             const uint32_t *__restrict__ col,
                                                             const uint32_t *__restrict__ split, int64_t n,
                                                             uint32_t *__restrict__ cnt_all,

@@ -15,7 +15,7 @@ struct pm_graph {
     int device = 0;
     int64_t n = 0;
     int64_t slots = 0;            // 2m
-    int64_t *off = nullptr;       // [n+1]
+    uint32_t *off = nullptr;      // [n+1] (every slot index is below 2^32)
     uint32_t *col = nullptr;      // [slots]
     uint64_t *edge = nullptr;     // [slots] row | col << 32
     uint32_t *deg = nullptr;      // [n]
@@ -41,7 +41,7 @@ namespace pm {
 
 // Everything one sampler needs about one graph.
 struct SamplerView {
-    const int64_t *off;
+    const uint32_t *off;
     const uint32_t *col;
     Ladder ladder;
     const uint64_t *edge;    // row | col << 32 per slot

@@ -107,8 +107,8 @@ struct DegIn {
     __device__ __forceinline__ uint64_t operator()(int64_t i) const { return d[i]; }
 };
 struct OffOut {
-    int64_t *off;  // writes off[i+1]
-    __device__ __forceinline__ void operator()(int64_t i, uint64_t incl, uint64_t) const { off[i + 1] = (int64_t)incl; }
+    uint32_t *off;  // writes off[i+1] (below 2^32: the slot count is)
+    __device__ __forceinline__ void operator()(int64_t i, uint64_t incl, uint64_t) const { off[i + 1] = (uint32_t)incl; }
 };
 
 // ---------------------------------------------------------------------------
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(kBlock) void k_rows_lane(const int64_t *__restrict_
                                                       const int32_t *__restrict__ col_in,
                                                       const uint32_t *__restrict__ order,
                                                       const int32_t *__restrict__ rank,
-                                                      const int64_t *__restrict__ off_new, int64_t n, int64_t r0,
+                                                      const uint32_t *__restrict__ off_new, int64_t n, int64_t r0,
                                                       int64_t r1, uint32_t *__restrict__ col,
                                                       uint64_t *__restrict__ edge, uint32_t *__restrict__ ladder1,
                                                       PrepStats *st)
@@ -208,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void k_rows_wave(const int64_t *__restrict_
                                                       const int32_t *__restrict__ col_in,
                                                       const uint32_t *__restrict__ order,
                                                       const int32_t *__restrict__ rank,
-                                                      const int64_t *__restrict__ off_new, int64_t n, int64_t r0,
+                                                      const uint32_t *__restrict__ off_new, int64_t n, int64_t r0,
                                                       int64_t r1, uint32_t *__restrict__ col,
                                                       uint64_t *__restrict__ edge, uint32_t *__restrict__ ladder1,
                                                       PrepStats *st)
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(THREADS) void k_rows_block(const int64_t *__restric
                                                         const int32_t *__restrict__ col_in,
                                                         const uint32_t *__restrict__ order,
                                                         const int32_t *__restrict__ rank,
-                                                        const int64_t *__restrict__ off_new, int64_t n, int64_t r0,
+                                                        const uint32_t *__restrict__ off_new, int64_t n, int64_t r0,
                                                         int bits, uint32_t *__restrict__ col,
                                                         uint64_t *__restrict__ edge, uint32_t *__restrict__ ladder1,
                                                         PrepStats *st)
@@ -354,7 +354,7 @@ __global__ __launch_bounds__(kBlock) void k_rows_tail_place(const int64_t *__res
                                                             const int32_t *__restrict__ col_in,
                                                             const uint32_t *__restrict__ order,
                                                             const int32_t *__restrict__ rank,
-                                                            const int64_t *__restrict__ off_new, int64_t n,
+                                                            const uint32_t *__restrict__ off_new, int64_t n,
                                                             int64_t r0, int64_t T, uint32_t *__restrict__ key,
                                                             uint32_t *__restrict__ val, PrepStats *st)
 {
@@ -394,7 +394,7 @@ __global__ __launch_bounds__(kBlock) void k_rows_tail_emit(const uint32_t *__res
 // = first row with degree > {0, 16, 64, 256, 1024, 4096, 8192, 16384}[c];
 // cls[8] = the first slot of row cls[7]
 constexpr int kRowClasses = 8;
-__global__ void k_row_classes(const uint32_t *__restrict__ deg, const int64_t *__restrict__ off, int64_t n,
+__global__ void k_row_classes(const uint32_t *__restrict__ deg, const uint32_t *__restrict__ off, int64_t n,
                               int64_t *cls)
 {
     const uint32_t bound[kRowClasses] = {0u, 16u, 64u, 256u, 1024u, 4096u, 8192u, 16384u};
@@ -445,7 +445,7 @@ constexpr int kWBatch = 8;
 __global__ __launch_bounds__(kBlock) void k_weights_reduce(const uint64_t *__restrict__ edge,
                                                            const uint32_t *__restrict__ rev,
                                                            const uint32_t *__restrict__ key2,
-                                                           const int64_t *__restrict__ off, int64_t N,
+                                                           const uint32_t *__restrict__ off, int64_t N,
                                                            uint64_t *__restrict__ p_tau,
                                                            uint64_t *__restrict__ p_lam, U64x2 *__restrict__ tile_sums,
                                                            PrepStats *st)
@@ -756,7 +756,7 @@ void graph_free(pm_graph *g, hipStream_t s)
 uint64_t graph_bytes_for(int64_t n, int64_t slots)
 {
     const uint64_t nn = (uint64_t)std::max<int64_t>(n, 1), ss = (uint64_t)std::max<int64_t>(slots, 1);
-    uint64_t b = 4 * nn + 4 * nn + 8 * ((uint64_t)n + 1);
+    uint64_t b = 4 * nn + 4 * nn + 4 * ((uint64_t)n + 1);
     const int top = ladder_top_for(slots);
     uint64_t total = 0;
     for (int l = 1; l <= top; ++l) total += (ladder_count(slots, l) + 31) / 32 * 32;
@@ -868,14 +868,14 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
 
     PM_TRY(dev_alloc((void **)&g->rank, sizeof(int32_t) * nn, s));
     PM_TRY(dev_alloc((void **)&g->deg, sizeof(uint32_t) * nn, s));
-    PM_TRY(dev_alloc((void **)&g->off, sizeof(int64_t) * (n + 1), s));
-    g->bytes += sizeof(int32_t) * nn + sizeof(uint32_t) * nn + sizeof(int64_t) * (n + 1);
+    PM_TRY(dev_alloc((void **)&g->off, sizeof(uint32_t) * (n + 1), s));
+    g->bytes += sizeof(int32_t) * nn + sizeof(uint32_t) * nn + sizeof(uint32_t) * (n + 1);
     if (n > 0) {
         hipLaunchKernelGGL(k_rank_from_order, dim3(grid_stream(n)), dim3(kBlock), 0, s, order, g->rank, n);
         hipLaunchKernelGGL(k_copy_u32, dim3(grid_stream(n)), dim3(kBlock), 0, s, sorted_deg, g->deg, n);
         PM_HIP(hipGetLastError());
     }
-    PM_TRY(fill_async<int64_t>(g->off, 0, 1, s));
+    PM_TRY(fill_async<uint32_t>(g->off, 0u, 1, s));
     {
         char *scr = nullptr;
         PM_TRY(tmp.get(&scr, ScanScratch<uint64_t>::bytes_for(n, 16)));
@@ -1109,7 +1109,11 @@ pm_status graph_export(const pm_graph *g, int64_t *off, int32_t *col, int32_t *r
         set_error("null graph");
         return PM_EINVAL;
     }
-    if (off) PM_HIP(hipMemcpyAsync(off, g->off, sizeof(int64_t) * (g->n + 1), hipMemcpyDeviceToHost, s));
+    std::vector<uint32_t> off32;
+    if (off) {
+        off32.resize((size_t)g->n + 1);
+        PM_HIP(hipMemcpyAsync(off32.data(), g->off, sizeof(uint32_t) * (g->n + 1), hipMemcpyDeviceToHost, s));
+    }
     if (g->slots > 0) {
         if (col) PM_HIP(hipMemcpyAsync(col, g->col, sizeof(int32_t) * g->slots, hipMemcpyDeviceToHost, s));
         if (p_tau) PM_HIP(hipMemcpyAsync(p_tau, g->p_tau, sizeof(uint64_t) * g->slots, hipMemcpyDeviceToHost, s));
@@ -1117,6 +1121,7 @@ pm_status graph_export(const pm_graph *g, int64_t *off, int32_t *col, int32_t *r
     }
     if (rank && g->n > 0) PM_HIP(hipMemcpyAsync(rank, g->rank, sizeof(int32_t) * g->n, hipMemcpyDeviceToHost, s));
     PM_HIP(hipStreamSynchronize(s));
+    for (size_t i = 0; i < off32.size(); ++i) off[i] = off32[i];  // the ABI's offsets are int64
     return PM_OK;
 }
 

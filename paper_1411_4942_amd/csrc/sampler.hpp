@@ -19,14 +19,14 @@ struct RowSearch {
     uint32_t lo, hi, key;
 };
 
-__device__ __forceinline__ RowSearch row_search(const int64_t *__restrict__ off, uint32_t known, uint32_t klo,
+__device__ __forceinline__ RowSearch row_search(const uint32_t *__restrict__ off, uint32_t known, uint32_t klo,
                                                 uint32_t khi, uint32_t other)
 {
     if (known < other) return RowSearch{klo, khi, other};
     return RowSearch{(uint32_t)off[other], (uint32_t)off[other + 1], known};
 }
 
-__device__ __forceinline__ RowSearch row_search2(const int64_t *__restrict__ off, uint32_t a, uint32_t b)
+__device__ __forceinline__ RowSearch row_search2(const uint32_t *__restrict__ off, uint32_t a, uint32_t b)
 {
     const uint32_t x = a < b ? a : b;
     return RowSearch{(uint32_t)off[x], (uint32_t)off[x + 1], a < b ? b : a};
