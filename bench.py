@@ -281,6 +281,39 @@ def ingest_leg(scale: int, edge_factor: float, seed: int, k: int, want: dict, re
     return out
 
 
+def exact_leg(k: int = 2_000_000) -> dict:
+    """Sampling against exact enumeration on Chung-Lu n = 1e6, m = 1e7
+    (exponent 2.3, weight cap 5000, seed 1): times and the estimates' error."""
+    import torch
+
+    from paper_1411_4942_amd import pathsamp as ps
+    from paper_1411_4942_amd import synth
+
+    off, col = synth.chung_lu_torch(1_000_000, 10_000_000, 2.3, 5000.0, 1, device="cuda")
+    g = ps.Graph(off, col)
+    g.exact()
+    res = g.count(k, k, seed=1)
+    t_ex = t_sa = 1e30
+    for _ in range(3):
+        ex, dt = _graph_seconds(g.exact)
+        t_ex = min(t_ex, dt)
+        res, dt = _graph_seconds(lambda: g.count(k, k, seed=1))
+        t_sa = min(t_sa, dt)
+    g.destroy()
+    del off, col
+    torch.cuda.empty_cache()
+    C = ex["C"]
+    return {
+        "workload": f"Chung-Lu n=1e6, m=1e7, gamma 2.3, w_max 5000, seed 1; k={k} per sampler, Philox seed 1",
+        "exact_ms": 1e3 * t_ex,
+        "sampling_ms": 1e3 * t_sa,
+        "exact_over_sampling": t_ex / t_sa,
+        "exact_counts": C[1:],
+        "rel_err": [abs(res["est"][i] - C[i]) / C[i] if C[i] else None for i in range(1, 7)],
+        "inside_99pct_bars": [res["lo"][i] <= C[i] <= res["hi"][i] for i in range(1, 7)],
+    }
+
+
 def served_leg(count: int, n_sat: int, n_open: int, loads, rel_err: float, delta: float, k_max: int,
                plain_check: int) -> dict:
     """A pool of resident graphs behind the request server: closed-loop
@@ -397,6 +430,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-ingest", action="store_true")
+    ap.add_argument("--no-exact", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--batch-graphs", type=int, default=256)
     ap.add_argument("--batch-k", type=int, default=200_000)
@@ -519,6 +553,10 @@ def main():
         log("[bench] ingest leg ...")
         out["ingest"] = ingest_leg(args.scale, args.edge_factor, args.seed, k, res)
         log(f"[bench] ingest: {out['ingest']['ingest_ms']:.2f} ms, end to end {out['ingest']['end_to_end_ms']:.2f} ms")
+    if not args.no_exact:
+        log("[bench] exact leg ...")
+        out["exact"] = exact_leg()
+        log(f"[bench] exact: {out['exact']['exact_ms']:.1f} ms vs sampling {out['exact']['sampling_ms']:.2f} ms")
     if not args.no_batched:
         log("[bench] batched leg ...")
         out["batched"] = batched_leg(args.batch_graphs, args.batch_k, replays=5)
