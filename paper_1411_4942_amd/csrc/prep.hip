@@ -2,14 +2,13 @@
 // Section 4, tau/lambda weights with their prefix sums (Sections 3 and 4),
 // N_1 (Algorithm 2) and the guide tables of the edge draw.
 //
-// Relabel by two stable sorts and one transposition identity: with the rows
-// placed in the new order (G1, columns mapped but unsorted), a stable sort of
-// G1's entries by column yields them ordered by (column, row), which for a
-// symmetric graph is exactly the new CSR with every row ascending (the
-// transpose of a symmetric graph is itself).  A second stable sort of the
-// result's slots by column lists, at position q, the slot holding the reverse
-// of slot q: that permutation is at once the symmetry check and the reverse
-// slot map the lambda weights need.
+// The relabelled rows are built already sorted, one size class of rows per
+// launch (lane, wave and block sorts; global radix sorts for the few hub
+// rows).  One stable sort of the finished slots by column then lists, at
+// position q, the slot holding the reverse of slot q: that permutation is at
+// once the symmetry check and the reverse slot map the lambda weights need.
+// The weights are parked with per-tile sums, and a second pass turns them
+// into both prefix sums and fills the guide tables.
 #include "graph.hpp"
 #include "profile.hpp"
 #include "radix.hpp"
@@ -468,7 +467,7 @@ __global__ __launch_bounds__(kBlock) void k_weights_reduce(const uint64_t *__res
             r[i] = ok ? rev[idx] : 0u;
             k2[i] = ok ? key2[idx] : 0u;
         }
-        int64_t ou[kWBatch], ou1[kWBatch], ov[kWBatch], ov1[kWBatch];
+        uint32_t ou[kWBatch], ou1[kWBatch], ov[kWBatch], ov1[kWBatch];
 #pragma unroll
         for (int i = 0; i < kWBatch; ++i) {
             const uint32_t u = (uint32_t)e[i], v = (uint32_t)(e[i] >> 32);
@@ -484,11 +483,11 @@ __global__ __launch_bounds__(kBlock) void k_weights_reduce(const uint64_t *__res
             const uint32_t u = (uint32_t)e[i];
             const int64_t rr = r[i];
             if (k2[i] != u) err |= ERR_ASYM;  // symmetry, half 1
-            if (rr < ov[i] || rr >= ov1[i]) err |= ERR_ASYM;  // half 2
-            const int64_t du = ou1[i] - ou[i], dv = ov1[i] - ov[i];
+            if (rr < (int64_t)ov[i] || rr >= (int64_t)ov1[i]) err |= ERR_ASYM;  // half 2
+            const int64_t du = (int64_t)ou1[i] - ou[i], dv = (int64_t)ov1[i] - ov[i];
             const uint64_t tau = (uint64_t)(du - 1) * (uint64_t)(dv - 1);
-            const uint64_t luv = (uint64_t)(du - 1 - (idx - ou[i]));
-            const uint64_t lvu = (uint64_t)(dv - 1 - (rr - ov[i]));
+            const uint64_t luv = (uint64_t)(du - 1 - (idx - (int64_t)ou[i]));
+            const uint64_t lvu = (uint64_t)(dv - 1 - (rr - (int64_t)ov[i]));
             const uint64_t lam = luv * lvu;
             p_tau[idx] = tau;
             p_lam[idx] = lam;
@@ -555,10 +554,14 @@ __global__ void k_guide_setup(PrepStats *st, int64_t slots, uint32_t *guide_tau,
 }
 
 // Launch 3 of the weights scan: the prefixes from the parked weights, the
-// wrap checks and the guide entries.  Blocked arrangement: thread t of a tile
-// owns kWItems consecutive slots, scans them sequentially, and only the
-// thread totals go through a wave scan (one 64-lane scan per thread instead
-// of one per item).  The tiles are those of k_weights_reduce.
+// wrap checks and the guide entries.  The tiles are those of
+// k_weights_reduce; each wave covers kWRounds rounds of kWave * kWV
+// consecutive slots, and in a round lane l owns kWV consecutive slots
+// (16-byte loads and stores that cover whole cache lines per instruction),
+// sums them sequentially, and one wave scan places the lane totals.
+constexpr int kWV = 4;
+constexpr int kWRounds = kWItems / kWV;
+
 __global__ __launch_bounds__(kBlock) void k_weights_apply(uint64_t *__restrict__ p_tau, uint64_t *__restrict__ p_lam,
                                                           int64_t N, const U64x2 *__restrict__ tile_prefix,
                                                           uint32_t *__restrict__ guide_tau,
@@ -570,78 +573,93 @@ __global__ __launch_bounds__(kBlock) void k_weights_apply(uint64_t *__restrict__
     __shared__ U64x2 s_wave[kBlock / kWave];
     const int w = threadIdx.x / kWave;
     const int lane = lane_id();
-    const int64_t base = (int64_t)blockIdx.x * (kBlock * kWItems) + (int64_t)threadIdx.x * kWItems;
+    const int64_t wave_base = (int64_t)blockIdx.x * (kBlock * kWItems) + (int64_t)w * (kWave * kWItems);
     const uint32_t sh_t = st->shift_tau, sh_l = st->shift_lam;
     const uint64_t nb_t = st->nb_tau, nb_l = st->nb_lam;
     uint64_t a[kWItems], b[kWItems];
-    if (base + kWItems <= N) {
-        // 128 contiguous bytes per array and thread, as 16-byte loads
-        const uint4 *pa = reinterpret_cast<const uint4 *>(p_tau + base);
-        const uint4 *pb = reinterpret_cast<const uint4 *>(p_lam + base);
 #pragma unroll
-        for (int i = 0; i < kWItems / 2; ++i) {
-            const uint4 x = pa[i], y = pb[i];
-            a[2 * i] = (uint64_t)x.x | ((uint64_t)x.y << 32);
-            a[2 * i + 1] = (uint64_t)x.z | ((uint64_t)x.w << 32);
-            b[2 * i] = (uint64_t)y.x | ((uint64_t)y.y << 32);
-            b[2 * i + 1] = (uint64_t)y.z | ((uint64_t)y.w << 32);
-        }
-    } else {
+    for (int rd = 0; rd < kWRounds; ++rd) {
+        const int64_t s0 = wave_base + (int64_t)rd * (kWave * kWV) + (int64_t)lane * kWV;
+        uint64_t *x = a + rd * kWV, *y = b + rd * kWV;
+        if (s0 + kWV <= N) {
+            const uint4 *pa = reinterpret_cast<const uint4 *>(p_tau + s0);
+            const uint4 *pb = reinterpret_cast<const uint4 *>(p_lam + s0);
+            const uint4 x0 = pa[0], x1 = pa[1], y0 = pb[0], y1 = pb[1];
+            x[0] = (uint64_t)x0.x | ((uint64_t)x0.y << 32);
+            x[1] = (uint64_t)x0.z | ((uint64_t)x0.w << 32);
+            x[2] = (uint64_t)x1.x | ((uint64_t)x1.y << 32);
+            x[3] = (uint64_t)x1.z | ((uint64_t)x1.w << 32);
+            y[0] = (uint64_t)y0.x | ((uint64_t)y0.y << 32);
+            y[1] = (uint64_t)y0.z | ((uint64_t)y0.w << 32);
+            y[2] = (uint64_t)y1.x | ((uint64_t)y1.y << 32);
+            y[3] = (uint64_t)y1.z | ((uint64_t)y1.w << 32);
+        } else {
 #pragma unroll
-        for (int i = 0; i < kWItems; ++i) {
-            a[i] = base + i < N ? p_tau[base + i] : 0ull;
-            b[i] = base + i < N ? p_lam[base + i] : 0ull;
-        }
-    }
-    // thread-local inclusive sums
-#pragma unroll
-    for (int i = 1; i < kWItems; ++i) {
-        a[i] += a[i - 1];
-        b[i] += b[i - 1];
-    }
-    // exclusive prefix of the thread inside the tile
-    const U64x2 tot{a[kWItems - 1], b[kWItems - 1]};
-    const U64x2 incl = wave_inclusive(tot, PairSumOp(), U64x2{0, 0});
-    if (lane == kWave - 1) s_wave[w] = incl;
-    __syncthreads();
-    U64x2 run = tile_prefix[blockIdx.x];
-    for (int i = 0; i < w; ++i) run = PairSumOp()(run, s_wave[i]);
-    run.a += incl.a - tot.a;
-    run.b += incl.b - tot.b;
-    uint32_t err = 0;
-    uint64_t prev_a = run.a, prev_b = run.b;
-#pragma unroll
-    for (int i = 0; i < kWItems; ++i) {
-        const int64_t idx = base + i;
-        if (idx >= N) break;
-        const uint64_t ia = run.a + a[i], ib = run.b + b[i];
-        // the running sum passed 2^64 exactly where it decreases
-        if (ia < prev_a) err |= ERR_OVF_TAU;
-        if (ib < prev_b) err |= ERR_OVF_LAM;
-        guide_fill(prev_a, ia, sh_t, nb_t, (uint32_t)idx, guide_tau, long_tau, long_cap, &st->nlong_tau, &st->err);
-        guide_fill(prev_b, ib, sh_l, nb_l, (uint32_t)idx, guide_lam, long_lam, long_cap, &st->nlong_lam, &st->err);
-        a[i] = ia;
-        b[i] = ib;
-        prev_a = ia;
-        prev_b = ib;
-    }
-    if (base + kWItems <= N) {
-        uint4 *pa = reinterpret_cast<uint4 *>(p_tau + base);
-        uint4 *pb = reinterpret_cast<uint4 *>(p_lam + base);
-#pragma unroll
-        for (int i = 0; i < kWItems / 2; ++i) {
-            pa[i] = make_uint4((uint32_t)a[2 * i], (uint32_t)(a[2 * i] >> 32), (uint32_t)a[2 * i + 1],
-                               (uint32_t)(a[2 * i + 1] >> 32));
-            pb[i] = make_uint4((uint32_t)b[2 * i], (uint32_t)(b[2 * i] >> 32), (uint32_t)b[2 * i + 1],
-                               (uint32_t)(b[2 * i + 1] >> 32));
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < kWItems; ++i)
-            if (base + i < N) {
-                p_tau[base + i] = a[i];
-                p_lam[base + i] = b[i];
+            for (int j = 0; j < kWV; ++j) {
+                x[j] = s0 + j < N ? p_tau[s0 + j] : 0ull;
+                y[j] = s0 + j < N ? p_lam[s0 + j] : 0ull;
             }
+        }
+    }
+    // per round: lane-local inclusive sums, then the lane's place in the wave
+    U64x2 lane_excl[kWRounds];
+    U64x2 wave_run{0, 0};
+#pragma unroll
+    for (int rd = 0; rd < kWRounds; ++rd) {
+#pragma unroll
+        for (int j = 1; j < kWV; ++j) {
+            a[rd * kWV + j] += a[rd * kWV + j - 1];
+            b[rd * kWV + j] += b[rd * kWV + j - 1];
+        }
+        const U64x2 tot{a[rd * kWV + kWV - 1], b[rd * kWV + kWV - 1]};
+        const U64x2 incl = wave_inclusive(tot, PairSumOp(), U64x2{0, 0});
+        lane_excl[rd] = U64x2{wave_run.a + incl.a - tot.a, wave_run.b + incl.b - tot.b};
+        wave_run = PairSumOp()(wave_run, shfl_idx_t(incl, kWave - 1));
+    }
+    if (lane == 0) s_wave[w] = wave_run;
+    __syncthreads();
+    U64x2 wave_pre = tile_prefix[blockIdx.x];
+    for (int i = 0; i < w; ++i) wave_pre = PairSumOp()(wave_pre, s_wave[i]);
+    uint32_t err = 0;
+#pragma unroll
+    for (int rd = 0; rd < kWRounds; ++rd) {
+        const int64_t s0 = wave_base + (int64_t)rd * (kWave * kWV) + (int64_t)lane * kWV;
+        const uint64_t ra = wave_pre.a + lane_excl[rd].a, rb = wave_pre.b + lane_excl[rd].b;
+        uint64_t prev_a = ra, prev_b = rb;
+        uint64_t *x = a + rd * kWV, *y = b + rd * kWV;
+#pragma unroll
+        for (int j = 0; j < kWV; ++j) {
+            const int64_t idx = s0 + j;
+            const uint64_t ia = ra + x[j], ib = rb + y[j];
+            if (idx < N) {
+                // the running sum passed 2^64 exactly where it decreases
+                if (ia < prev_a) err |= ERR_OVF_TAU;
+                if (ib < prev_b) err |= ERR_OVF_LAM;
+                guide_fill(prev_a, ia, sh_t, nb_t, (uint32_t)idx, guide_tau, long_tau, long_cap, &st->nlong_tau,
+                           &st->err);
+                guide_fill(prev_b, ib, sh_l, nb_l, (uint32_t)idx, guide_lam, long_lam, long_cap, &st->nlong_lam,
+                           &st->err);
+            }
+            x[j] = ia;
+            y[j] = ib;
+            prev_a = ia;
+            prev_b = ib;
+        }
+        if (s0 + kWV <= N) {
+            uint4 *pa = reinterpret_cast<uint4 *>(p_tau + s0);
+            uint4 *pb = reinterpret_cast<uint4 *>(p_lam + s0);
+            pa[0] = make_uint4((uint32_t)x[0], (uint32_t)(x[0] >> 32), (uint32_t)x[1], (uint32_t)(x[1] >> 32));
+            pa[1] = make_uint4((uint32_t)x[2], (uint32_t)(x[2] >> 32), (uint32_t)x[3], (uint32_t)(x[3] >> 32));
+            pb[0] = make_uint4((uint32_t)y[0], (uint32_t)(y[0] >> 32), (uint32_t)y[1], (uint32_t)(y[1] >> 32));
+            pb[1] = make_uint4((uint32_t)y[2], (uint32_t)(y[2] >> 32), (uint32_t)y[3], (uint32_t)(y[3] >> 32));
+        } else {
+#pragma unroll
+            for (int j = 0; j < kWV; ++j)
+                if (s0 + j < N) {
+                    p_tau[s0 + j] = x[j];
+                    p_lam[s0 + j] = y[j];
+                }
+        }
     }
     if (err) atomicOr(&st->err, err);
 }
