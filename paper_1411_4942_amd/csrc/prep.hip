@@ -118,7 +118,9 @@ struct OffOut {
 //   16 < degree <= 64     one wave per row, a sorting network across lanes
 //   64 < degree <= 16384  one block per row sized to the class (64, 64, 256,
 //                         512 or 1024 threads), stable LSD radix sort in LDS
-//   degree > 16384        (the few hub rows, all at the end of the order)
+//   16384 < degree <= 32768  one block of 1024 per row, keys in registers
+//                         and one LDS exchange buffer (128 KB)
+//   degree > 32768        (the few hub rows, all at the end of the order)
 //                         placed unsorted, then two global radix sorts
 // Each class writes col, edge = row | col << 32, and ladder level 1 (every
 // 32nd column) at the row's final slots, and checks the input row (column
@@ -240,12 +242,84 @@ __global__ __launch_bounds__(kBlock) void k_rows_wave(const int64_t *__restrict_
 // digit counters, the counters become output positions, the keys move to the
 // other buffer.  Returns the buffer holding the result.  Every thread of the
 // block calls it.
+// Rank of a key with digit `dig` among the keys of its wave pass (stable:
+// lanes below first), counted on top of the wave's running digit counts cnt.
+__device__ __forceinline__ uint32_t wave_digit_rank(uint32_t dig, bool ok, uint64_t lt_mask, uint32_t *cnt)
+{
+    uint64_t peers = __ballot(ok);
+#pragma unroll
+    for (int bb = 0; bb < 8; ++bb) {
+        const uint64_t bal = __ballot((dig >> bb) & 1u);
+        peers &= ((dig >> bb) & 1u) ? bal : ~bal;
+    }
+    const uint32_t below = __popcll(peers & lt_mask);
+    const uint32_t base = cnt[dig];
+    if (ok && below == 0) cnt[dig] = base + (uint32_t)__popcll(peers);
+    return base + below;
+}
+
+// Per-wave digit counts s_cnt[w * 256 + d] to the first output position of
+// wave w's keys with digit d (digits in order, waves in order within one).
+template <int THREADS>
+__device__ __forceinline__ void block_digit_offsets(uint32_t *s_cnt, uint32_t *s_tot)
+{
+    constexpr int W = THREADS / kWave;
+    const int t = threadIdx.x, lane = lane_id();
+    for (int d0 = t; d0 < 256; d0 += THREADS) {
+        uint32_t tot = 0;
+        for (int ww = 0; ww < W; ++ww) tot += s_cnt[ww * 256 + d0];
+        s_tot[d0] = tot;
+    }
+    __syncthreads();
+    if (t < kWave) {  // exclusive scan of the 256 totals, 4 per lane
+        const uint32_t v0 = s_tot[4 * t], v1 = s_tot[4 * t + 1], v2 = s_tot[4 * t + 2], v3 = s_tot[4 * t + 3];
+        const uint32_t loc = v0 + v1 + v2 + v3;
+        uint32_t incl = loc;
+#pragma unroll
+        for (int dd = 1; dd < kWave; dd <<= 1) {
+            const uint32_t o = __shfl_up(incl, dd, kWave);
+            if (lane >= dd) incl += o;
+        }
+        const uint32_t ex = incl - loc;
+        s_tot[4 * t] = ex;
+        s_tot[4 * t + 1] = ex + v0;
+        s_tot[4 * t + 2] = ex + v0 + v1;
+        s_tot[4 * t + 3] = ex + v0 + v1 + v2;
+    }
+    __syncthreads();
+    for (int d0 = t; d0 < 256; d0 += THREADS) {
+        uint32_t run = s_tot[d0];
+        for (int ww = 0; ww < W; ++ww) {
+            const uint32_t c = s_cnt[ww * 256 + d0];
+            s_cnt[ww * 256 + d0] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+}
+
+// Keys per wave in the block sorts: the nk keys split into W contiguous runs
+// of a whole number of wave rows, so every wave has work whatever nk is (a
+// fixed ITEMS-row run per wave would idle the upper waves on rows near the
+// lower bound of their size class).  Wave w ranks keys [w * per, (w + 1) *
+// per) in order, item i of it being key w * per + i * kWave + lane; per <=
+// ITEMS * kWave when nk <= THREADS * ITEMS.
+template <int THREADS>
+__device__ __forceinline__ int keys_per_wave(int nk)
+{
+    constexpr int W = THREADS / kWave;
+    return (nk + W * kWave - 1) / (W * kWave) * kWave;
+}
+
+// Stable LSD radix sort (8-bit digits) of nk <= THREADS * ITEMS keys in LDS,
+// ping-ponging between a and b; returns the buffer holding the result.
 template <int THREADS, int ITEMS>
 __device__ uint32_t *block_radix_lds(uint32_t *a, uint32_t *b, int nk, int bits, uint32_t *s_cnt, uint32_t *s_tot)
 {
     constexpr int W = THREADS / kWave;
     const int t = threadIdx.x, w = t / kWave, lane = lane_id();
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    const int per = keys_per_wave<THREADS>(nk);
     for (int shift = 0; shift < bits; shift += 8) {
         const uint32_t mask = (bits - shift >= 8) ? 0xFFu : ((1u << (bits - shift)) - 1u);
         for (int j = t; j < W * 256; j += THREADS) s_cnt[j] = 0;
@@ -253,57 +327,18 @@ __device__ uint32_t *block_radix_lds(uint32_t *a, uint32_t *b, int nk, int bits,
         uint32_t rank[ITEMS], dig[ITEMS];
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
-            if ((w * ITEMS + i) * kWave >= nk) break;  // wave-uniform: the rest of this wave's rows are empty
-            const int idx = (w * ITEMS + i) * kWave + lane;
+            if (i * kWave >= per) break;  // wave-uniform
+            const int idx = w * per + i * kWave + lane;
             const bool ok = idx < nk;
             dig[i] = ok ? (a[idx] >> shift) & mask : 0u;
-            uint64_t peers = __ballot(ok);
-#pragma unroll
-            for (int bb = 0; bb < 8; ++bb) {
-                const uint64_t bal = __ballot((dig[i] >> bb) & 1u);
-                peers &= ((dig[i] >> bb) & 1u) ? bal : ~bal;
-            }
-            const uint32_t below = __popcll(peers & lt_mask);
-            const uint32_t base = s_cnt[w * 256 + dig[i]];
-            rank[i] = base + below;
-            if (ok && below == 0) s_cnt[w * 256 + dig[i]] = base + (uint32_t)__popcll(peers);
+            rank[i] = wave_digit_rank(dig[i], ok, lt_mask, s_cnt + w * 256);
         }
         __syncthreads();
-        for (int d0 = t; d0 < 256; d0 += THREADS) {
-            uint32_t tot = 0;
-            for (int ww = 0; ww < W; ++ww) tot += s_cnt[ww * 256 + d0];
-            s_tot[d0] = tot;
-        }
-        __syncthreads();
-        if (t < kWave) {  // exclusive scan of the 256 totals, 4 per lane
-            const uint32_t v0 = s_tot[4 * t], v1 = s_tot[4 * t + 1], v2 = s_tot[4 * t + 2], v3 = s_tot[4 * t + 3];
-            const uint32_t loc = v0 + v1 + v2 + v3;
-            uint32_t incl = loc;
-#pragma unroll
-            for (int dd = 1; dd < kWave; dd <<= 1) {
-                const uint32_t o = __shfl_up(incl, dd, kWave);
-                if (lane >= dd) incl += o;
-            }
-            const uint32_t ex = incl - loc;
-            s_tot[4 * t] = ex;
-            s_tot[4 * t + 1] = ex + v0;
-            s_tot[4 * t + 2] = ex + v0 + v1;
-            s_tot[4 * t + 3] = ex + v0 + v1 + v2;
-        }
-        __syncthreads();
-        for (int d0 = t; d0 < 256; d0 += THREADS) {
-            uint32_t run = s_tot[d0];
-            for (int ww = 0; ww < W; ++ww) {
-                const uint32_t c = s_cnt[ww * 256 + d0];
-                s_cnt[ww * 256 + d0] = run;
-                run += c;
-            }
-        }
-        __syncthreads();
+        block_digit_offsets<THREADS>(s_cnt, s_tot);
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
-            if ((w * ITEMS + i) * kWave >= nk) break;
-            const int idx = (w * ITEMS + i) * kWave + lane;
+            if (i * kWave >= per) break;
+            const int idx = w * per + i * kWave + lane;
             if (idx < nk) b[s_cnt[w * 256 + dig[i]] + rank[i]] = a[idx];
         }
         __syncthreads();
@@ -312,6 +347,56 @@ __device__ uint32_t *block_radix_lds(uint32_t *a, uint32_t *b, int nk, int bits,
         b = tmp;
     }
     return a;
+}
+
+// The same sort with the keys held in registers between passes (key[i] is
+// item i as above) and one LDS buffer for the exchange: twice the capacity in
+// the same LDS.  No ranks are kept: after the counts become digit offsets,
+// the scatter ranks every key again on top of them, which yields its output
+// position directly.  buf holds THREADS * ITEMS words; the sorted keys end
+// in its first nk (it must hold the input keys when bits == 0).
+template <int THREADS, int ITEMS>
+__device__ __forceinline__ void block_radix_reg(uint32_t (&key)[ITEMS], uint32_t *buf, int nk, int bits,
+                                                uint32_t *s_cnt, uint32_t *s_tot)
+{
+    constexpr int W = THREADS / kWave;
+    const int t = threadIdx.x, w = t / kWave, lane = lane_id();
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    const int per = keys_per_wave<THREADS>(nk);
+    for (int shift = 0; shift < bits; shift += 8) {
+        const uint32_t mask = (bits - shift >= 8) ? 0xFFu : ((1u << (bits - shift)) - 1u);
+        for (int j = t; j < W * 256; j += THREADS) s_cnt[j] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            if (i * kWave >= per) break;  // wave-uniform
+            const int idx = w * per + i * kWave + lane;
+            const bool ok = idx < nk;
+            (void)wave_digit_rank(ok ? (key[i] >> shift) & mask : 0u, ok, lt_mask, s_cnt + w * 256);
+        }
+        __syncthreads();
+        block_digit_offsets<THREADS>(s_cnt, s_tot);
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            if (i * kWave >= per) break;
+            const int idx = w * per + i * kWave + lane;
+            const bool ok = idx < nk;
+            // an opaque copy: the compiler would otherwise keep the counting
+            // loop's masks of all ITEMS keys alive to reuse them here
+            uint32_t k = key[i];
+            asm volatile("" : "+v"(k));
+            const uint32_t pos = wave_digit_rank(ok ? (k >> shift) & mask : 0u, ok, lt_mask, s_cnt + w * 256);
+            if (ok) buf[pos] = k;
+        }
+        __syncthreads();
+        if (shift + 8 >= bits) break;  // the result stays in buf
+        // unconditional reads (every index is below THREADS * ITEMS): a
+        // conditional write to one register of key would make the compiler
+        // spill the whole array at every branch
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) key[i] = buf[w * per + i * kWave + lane];
+        // buf is written again only after the next pass's first barrier
+    }
 }
 
 // rows [r0, r0 + gridDim.x), degree <= THREADS * ITEMS, one block each
@@ -343,6 +428,47 @@ __global__ __launch_bounds__(THREADS) void k_rows_block(const int64_t *__restric
     const uint32_t *sorted = block_radix_lds<THREADS, ITEMS>(s_a, s_b, d, bits, s_cnt, s_tot);
     const int64_t dst = off_new[i];
     for (int j = threadIdx.x; j < d; j += THREADS) emit_slot(dst + j, (uint32_t)i, sorted[j], col, edge, ladder1);
+    if (err) atomicOr(&st->err, err);
+}
+
+// rows [r0, r0 + gridDim.x), degree <= THREADS * ITEMS, one block each,
+// keys in registers (block_radix_reg); the row enters and leaves through
+// the LDS buffer
+template <int THREADS, int ITEMS>
+__global__ __launch_bounds__(THREADS) void k_rows_block_reg(const int64_t *__restrict__ off_in,
+                                                            const int32_t *__restrict__ col_in,
+                                                            const uint32_t *__restrict__ order,
+                                                            const int32_t *__restrict__ rank,
+                                                            const uint32_t *__restrict__ off_new, int64_t n,
+                                                            int64_t r0, int bits, uint32_t *__restrict__ col,
+                                                            uint64_t *__restrict__ edge,
+                                                            uint32_t *__restrict__ ladder1, PrepStats *st)
+{
+    constexpr int CAP = THREADS * ITEMS;
+    __shared__ uint32_t s_buf[CAP];
+    __shared__ uint32_t s_cnt[(THREADS / kWave) * 256];
+    __shared__ uint32_t s_tot[256];
+    const int64_t i = r0 + blockIdx.x;
+    const int64_t u = order[i], a = off_in[u];
+    const int d = (int)(off_in[u + 1] - a);  // <= CAP by the class bounds
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    uint32_t err = 0;
+    for (int j = threadIdx.x; j < d; j += THREADS) {
+        const int64_t c = col_in[a + j];
+        const int64_t prev = j > 0 ? (int64_t)col_in[a + j - 1] : -1;
+        err |= slot_checks(c, u, prev, n);
+        s_buf[j] = (c >= 0 && c < n) ? (uint32_t)rank[c] : 0u;
+    }
+    __syncthreads();
+    uint32_t key[ITEMS];
+    // unconditional reads, as in block_radix_reg
+    const int per = keys_per_wave<THREADS>(d);
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) key[it] = s_buf[w * per + it * kWave + lane];
+    // the first pass writes s_buf only after its own barriers
+    block_radix_reg<THREADS, ITEMS>(key, s_buf, d, bits, s_cnt, s_tot);
+    const int64_t dst = off_new[i];
+    for (int j = threadIdx.x; j < d; j += THREADS) emit_slot(dst + j, (uint32_t)i, s_buf[j], col, edge, ladder1);
     if (err) atomicOr(&st->err, err);
 }
 
@@ -390,13 +516,13 @@ __global__ __launch_bounds__(kBlock) void k_rows_tail_emit(const uint32_t *__res
 }
 
 // first row of each size class (degrees ascend along the new order): cls[c]
-// = first row with degree > {0, 16, 64, 256, 1024, 4096, 8192, 16384}[c];
-// cls[8] = the first slot of row cls[7]
-constexpr int kRowClasses = 8;
+// = first row with degree > {0, 16, 64, 256, 1024, 4096, 8192, 16384,
+// 32768}[c]; cls[9] = the first slot of row cls[8]
+constexpr int kRowClasses = 9;
 __global__ void k_row_classes(const uint32_t *__restrict__ deg, const uint32_t *__restrict__ off, int64_t n,
                               int64_t *cls)
 {
-    const uint32_t bound[kRowClasses] = {0u, 16u, 64u, 256u, 1024u, 4096u, 8192u, 16384u};
+    const uint32_t bound[kRowClasses] = {0u, 16u, 64u, 256u, 1024u, 4096u, 8192u, 16384u, 32768u};
     const int c = threadIdx.x;
     if (c >= kRowClasses) return;
     int64_t lo = 0, hi = n;
@@ -969,6 +1095,11 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
             ProfScope pc("build_rows.b16384", s);
             hipLaunchKernelGGL((k_rows_block<1024, 16>), dim3((unsigned)(cls[7] - cls[6])), dim3(1024), 0, s, off_in,
                                col_in, order, g->rank, g->off, n, cls[6], vbits, g->col, g->edge, ladder1, st);
+        }
+        if (cls[8] > cls[7]) {
+            ProfScope pc("build_rows.b32768", s);
+            hipLaunchKernelGGL((k_rows_block_reg<1024, 32>), dim3((unsigned)(cls[8] - cls[7])), dim3(1024), 0, s,
+                               off_in, col_in, order, g->rank, g->off, n, cls[7], vbits, g->col, g->edge, ladder1, st);
         }
         PM_HIP(hipGetLastError());
         const int64_t T = slots - cls[kRowClasses];

@@ -132,6 +132,30 @@ def erdos_renyi(n: int, m: int, seed: int):
     return csr_from_edges(n, keys // n, keys % n)
 
 
+def hubs(hub_degrees, n_rest: int, m_rest: int, seed: int):
+    """Hubs of exactly the given degrees over n_rest other vertices, plus
+    m_rest random pairs among those others (repeats and loops dropped).
+
+    Vertex ids: hubs first (0 .. len(hub_degrees) - 1), in the given order.
+    Each hub's neighbours are distinct non-hub vertices, and no other edge
+    touches a hub, so hub degrees are exact: graphs whose degree sequence hits
+    chosen values (e.g. both sides of a size-class boundary).
+    """
+    rng = np.random.default_rng(seed)
+    h = len(hub_degrees)
+    n = h + n_rest
+    us, vs = [], []
+    for i, d in enumerate(hub_degrees):
+        if d > n_rest:
+            raise ValueError("hub degree above the number of other vertices")
+        nb = rng.choice(n_rest, size=int(d), replace=False) + h
+        us.append(np.full(int(d), i, dtype=np.int64))
+        vs.append(nb.astype(np.int64))
+    us.append(rng.integers(h, n, size=m_rest))
+    vs.append(rng.integers(h, n, size=m_rest))
+    return csr_from_edges(n, np.concatenate(us), np.concatenate(vs))
+
+
 def chung_lu_weights(n: int, mean_degree: float, gamma: float, w_max: float):
     """w_i = min(w_max, w_min (1 - (i+1/2)/n)^(-1/(gamma-1))), w_min solved so
     that the mean weight is mean_degree (bisection)."""

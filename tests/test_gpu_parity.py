@@ -52,6 +52,10 @@ def _graphs():
     gs.append(("chunglu_3k", synth.chung_lu(3000, 20000, 2.2, 300.0, 3)))
     gs.append(("rmat_s12", synth.rmat(12, 16, seed=2)))
     gs.append(("er_tiles", synth.erdos_renyi(9000, 70000, 4)))  # > several scan/radix tiles, ragged tail
+    # rows on both sides of every row-build size-class bound (16 .. 32768) and
+    # above it (the global hub sort)
+    gs.append(("hub_classes", synth.hubs([16, 17, 64, 65, 256, 257, 1024, 1025, 4096, 4097, 8192, 8193, 16384,
+                                          16385, 32768, 32769, 70001], 100000, 150000, 9)))
     return gs
 
 
