@@ -20,7 +20,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SOURCES = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "exact.c")]
+_SOURCES = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "exact.c"), os.path.join(_HERE, "alias.c")]
 
 OK, EINVAL, EGRAPH, EOVERFLOW, ENOMEM = 0, -1, -2, -3, -4
 STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", EGRAPH: "EGRAPH", EOVERFLOW: "EOVERFLOW", ENOMEM: "ENOMEM"}
@@ -92,6 +92,10 @@ def _load():
         "or_enumerate_centered": (None, [gp, P]),
         "or_exact_brute": (i32, [i64, P, P, P, ctypes.POINTER(u64)]),
         "or_exact_formula": (i32, [i64, P, P, P, ctypes.POINTER(u64)]),
+        "or_alias_build": (i32, [P, i64, P, P]),
+        "or_draw_alias": (u64, [P, P, P, i64, u64, u64, u32, u64]),
+        "or_sample_path_alias": (None, [gp, P, P, u64, u64, u64, P]),
+        "or_sample_centered_alias": (None, [gp, P, P, u64, u64, u64, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -195,6 +199,42 @@ class Graph:
         q = np.ascontiguousarray(q, np.int32)
         return _load().or_classify_centered(ctypes.byref(self._g), _ptr(q))
 
+    def weights(self, centered: bool) -> np.ndarray:
+        """tau (or lambda) per slot, from the inclusive prefix."""
+        P = self.p_lam if centered else self.p_tau
+        return np.diff(P, prepend=np.uint64(0)).astype(np.uint64)
+
+    def alias_table(self, centered: bool):
+        """(K, alias) of the sampler's weights (alias.c), built once."""
+        key = "_alias_c" if centered else "_alias_p"
+        if not hasattr(self, key):
+            setattr(self, key, alias_build(self.weights(centered)))
+        return getattr(self, key)
+
+    def sample_path_alias(self, seed: int, k: int, first: int = 0) -> np.ndarray:
+        t = np.zeros(8, np.uint64)
+        if self.R_tau == 0:
+            return t
+        K, A = self.alias_table(False)
+        _load().or_sample_path_alias(ctypes.byref(self._g), _ptr(K), _ptr(A), seed, first, k, _ptr(t))
+        return t
+
+    def sample_centered_alias(self, seed: int, k: int, first: int = 0) -> np.ndarray:
+        t = np.zeros(8, np.uint64)
+        if self.R_lam == 0:
+            return t
+        K, A = self.alias_table(True)
+        _load().or_sample_centered_alias(ctypes.byref(self._g), _ptr(K), _ptr(A), seed, first, k, _ptr(t))
+        return t
+
+    def draw_alias(self, centered: bool, seed: int, sample_id: int) -> int:
+        """r in [0, R) of one alias draw (tag 3 centered, 2 otherwise)."""
+        K, A = self.alias_table(centered)
+        P = self.p_lam if centered else self.p_tau
+        R = self.R_lam if centered else self.R_tau
+        return int(_load().or_draw_alias(_ptr(P), _ptr(K), _ptr(A), self.slots, R, seed, 3 if centered else 2,
+                                         sample_id))
+
 
 def philox4x32_10(ctr, key) -> np.ndarray:
     c = np.ascontiguousarray(ctr, np.uint32)
@@ -213,6 +253,17 @@ def lemire(x: int, R: int, bits: int):
 
 def draw(seed: int, tag: int, sample_id: int, R: int) -> int:
     return int(_load().or_draw(seed, tag, sample_id, R))
+
+
+def alias_build(w):
+    """(K uint64[N], alias int64[N]) of weights w (alias.c)."""
+    w = np.ascontiguousarray(w, np.uint64)
+    K = np.zeros(w.size, np.uint64)
+    A = np.zeros(w.size, np.int64)
+    st = _load().or_alias_build(_ptr(w), w.size, _ptr(K), _ptr(A))
+    if st != OK:
+        raise OracleError(st, "or_alias_build")
+    return K, A
 
 
 def exact_brute(off, col):

@@ -87,6 +87,20 @@ void or_sample_centered(const or_graph *g, uint64_t seed, uint64_t first, uint64
 void or_enumerate_path(const or_graph *g, uint64_t tally[8]);
 void or_enumerate_centered(const or_graph *g, uint64_t tally[8]);
 
+/* Alias-table edge draw (alias.c): the variant of the weighted edge pick.
+ * or_alias_build fills K[N] and alias[N] for weights w[N] (total R in
+ * (0, 2^64)); or_draw_alias returns r = P[s-1] + o for sample `id` from the
+ * table (b, x and o drawn in that order from the sample's Philox stream);
+ * the alias samplers decode r exactly as the main samplers do, with tags 2
+ * (3-path) and 3 (centered). */
+int or_alias_build(const uint64_t *w, int64_t N, uint64_t *K, int64_t *alias);
+uint64_t or_draw_alias(const uint64_t *P, const uint64_t *K, const int64_t *alias, int64_t N, uint64_t R,
+                       uint64_t seed, uint32_t tag, uint64_t id);
+void or_sample_path_alias(const or_graph *g, const uint64_t *K, const int64_t *alias, uint64_t seed, uint64_t first,
+                          uint64_t k, uint64_t tally[8]);
+void or_sample_centered_alias(const or_graph *g, const uint64_t *K, const int64_t *alias, uint64_t seed,
+                              uint64_t first, uint64_t k, uint64_t tally[8]);
+
 /* Exact induced counts C[1..6] (C[0] unused) and triangle count.
  * Brute force over every 4-subset (n <= 512). */
 int or_exact_brute(int64_t n, const int64_t *off, const int32_t *col, uint64_t C[7], uint64_t *T);
