@@ -143,6 +143,34 @@ pm_status pm_graph_destroy(pm_graph *g);
  * estimates and bars are exactly 0.  k_path = k_cent = 0 is PM_EINVAL. */
 pm_status pm_count(const pm_graph *g, const pm_params *p, pm_result *out, void *stream);
 
+/* Alias-table edge draw: the variant of the weighted edge pick of
+ * Algorithm 1 step 2 and Algorithm 3 step 2 by Walker's alias method (the
+ * paper leaves the mechanism open).  pm_graph_build_alias adds one table per
+ * sampler of nonzero total weight to a prepared graph (32 bytes per slot
+ * each, counted in device_bytes, freed with the graph); calling it again is a
+ * no-op.  The table is exact and fixed by the weights: N = 2m buckets of
+ * capacity R (= 2W or 2 Lambda), slot s owning mass N w_s; light slots
+ * (N w_s < R) in index order each keep their mass and fill their bucket from
+ * the current heavy slot (index order), a heavy slot drawn below R filling
+ * its own bucket from the next one.  Calls on one graph must not overlap
+ * with each other or with samplers on it.  Errors: PM_EINVAL (null graph),
+ * PM_ENOMEM, PM_EDEVICE. */
+pm_status pm_graph_build_alias(pm_graph *g, void *stream);
+
+/* pm_count through the alias tables.  Each sample draws, from its own
+ * Philox stream (tag 2 for the 3-path sampler, 3 for the centered one; the
+ * candidates of attempts 0, 1, ... in order), a bucket b in [0, 2m), a coin
+ * x in [0, R) and then a position o in [0, w_s) inside the picked slot s, and
+ * is decoded from (s, o) as in pm_count.  Tallies therefore differ from
+ * pm_count's for the same seed, with the same distribution.  PM_EINVAL when
+ * a sampler with nonzero weight has no table (pm_graph_build_alias first). */
+pm_status pm_count_alias(const pm_graph *g, const pm_params *p, pm_result *out, void *stream);
+
+/* Copy one sampler's alias table (centered = 0: tau, 1: lambda) to host
+ * arrays K[2m] (kept mass of each bucket) and alias[2m].  PM_EINVAL when
+ * that table was not built (or the sampler's total weight is 0). */
+pm_status pm_graph_alias_export(const pm_graph *g, int32_t centered, uint64_t *K, int64_t *alias, void *stream);
+
 /* Tallies only (no host finalize), written to the device buffer
  * tallies_dev[16] (path then centered, uint64) on the stream, without
  * synchronising.  The buffer is overwritten, not accumulated. */

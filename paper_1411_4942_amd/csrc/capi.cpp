@@ -23,6 +23,9 @@ pm_status graph_export(const pm_graph *g, int64_t *off, int32_t *col, int32_t *r
                        uint64_t *p_lam, hipStream_t s);
 pm_status graph_info(const pm_graph *g, pm_graph_info *out);
 pm_status sample_async(const pm_graph *g, const pm_params *p, uint64_t *tallies_dev, hipStream_t s);
+pm_status graph_build_alias(pm_graph *g, hipStream_t s);
+pm_status graph_alias_export(const pm_graph *g, int32_t centered, uint64_t *K, int64_t *alias, hipStream_t s);
+pm_status count_alias(const pm_graph *g, const pm_params *p, pm_result *out, hipStream_t s);
 pm_status finalize(const uint64_t tp[PM_NUM_TALLIES], const uint64_t tc[PM_NUM_TALLIES], uint64_t W,
                    uint64_t Lambda, uint64_t N1, uint64_t k_path, uint64_t k_cent, double delta, pm_result *out);
 pm_status chernoff_interval(uint64_t count, uint64_t k, double delta, double *p_lo, double *p_hi);
@@ -129,6 +132,21 @@ pm_status pm_sample_async(const pm_graph *g, const pm_params *p, uint64_t *talli
 pm_status pm_count(const pm_graph *g, const pm_params *p, pm_result *out, void *stream)
 {
     PM_GUARD(return pm::count_on_graph(g, p, out, (hipStream_t)stream);)
+}
+
+pm_status pm_graph_build_alias(pm_graph *g, void *stream)
+{
+    PM_GUARD(return pm::graph_build_alias(g, (hipStream_t)stream);)
+}
+
+pm_status pm_count_alias(const pm_graph *g, const pm_params *p, pm_result *out, void *stream)
+{
+    PM_GUARD(return pm::count_alias(g, p, out, (hipStream_t)stream);)
+}
+
+pm_status pm_graph_alias_export(const pm_graph *g, int32_t centered, uint64_t *K, int64_t *alias, void *stream)
+{
+    PM_GUARD(return pm::graph_alias_export(g, centered, K, alias, (hipStream_t)stream);)
 }
 
 pm_status pm_count_motifs(const pm_csr_view *csr, uint64_t k, uint64_t seed, pm_result *out)

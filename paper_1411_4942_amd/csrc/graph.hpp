@@ -31,6 +31,8 @@ struct pm_graph {
     uint64_t nb_tau = 0, nb_lam = 0;
     uint64_t R_tau = 0;  // 2W
     uint64_t R_lam = 0;  // 2 Lambda
+    void *alias_tau = nullptr;  // [slots] alias-draw tables (pm::AliasEntry), built on request
+    void *alias_lam = nullptr;
     uint64_t N1 = 0;
     int64_t dmax = 0;
     int64_t isolated = 0;
@@ -38,6 +40,18 @@ struct pm_graph {
 };
 
 namespace pm {
+
+// One bucket of an alias-draw table (32 bytes, so a draw reads one line):
+// the bucket keeps K of its own slot's mass (capacity R) and holds R - K of
+// slot `alias`; both slots' weights ride along for the position draw.
+struct AliasEntry {
+    uint64_t K;
+    uint64_t w_self;
+    uint64_t w_alias;
+    uint32_t alias;
+    uint32_t pad;
+};
+static_assert(sizeof(AliasEntry) == 32, "alias entry is 32 bytes");
 
 // Everything one sampler needs about one graph.
 struct SamplerView {

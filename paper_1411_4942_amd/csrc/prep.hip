@@ -892,6 +892,8 @@ void graph_free(pm_graph *g, hipStream_t s)
     dev_free(g->p_lam, s);
     dev_free(g->guide_tau, s);
     dev_free(g->guide_lam, s);
+    dev_free(g->alias_tau, s);
+    dev_free(g->alias_lam, s);
     delete g;
 }
 

@@ -237,7 +237,10 @@ pm_status check_device(const pm_graph *g)
     return PM_OK;
 }
 
-pm_status count_on_graph(const pm_graph *g, const pm_params *p, pm_result *out, hipStream_t s)
+// Run both samplers of one graph through `run` (which fills 2 x PM_NUM_TALLIES
+// device tallies), read the tallies back and finalize.
+pm_status count_with(const pm_graph *g, const pm_params *p, pm_result *out, hipStream_t s,
+                     pm_status (*run)(const pm_graph *, const pm_params *, uint64_t *, hipStream_t))
 {
     if (!g || !p || !out) {
         set_error("null argument");
@@ -255,7 +258,7 @@ pm_status count_on_graph(const pm_graph *g, const pm_params *p, pm_result *out, 
     uint64_t *t = nullptr;
     PM_TRY(dev_alloc((void **)&t, 2 * PM_NUM_TALLIES * sizeof(uint64_t), s));
     uint64_t host[2 * PM_NUM_TALLIES];
-    pm_status st = sample_async(g, p, t, s);
+    pm_status st = run(g, p, t, s);
     if (st == PM_OK) {
         hipError_t e = hipMemcpyAsync(host, t, sizeof(host), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -268,6 +271,11 @@ pm_status count_on_graph(const pm_graph *g, const pm_params *p, pm_result *out, 
     if (st != PM_OK) return st;
     return finalize(host, host + PM_NUM_TALLIES, g->R_tau / 2, g->R_lam / 2, g->N1, p->k_path, p->k_cent, p->delta,
                     out);
+}
+
+pm_status count_on_graph(const pm_graph *g, const pm_params *p, pm_result *out, hipStream_t s)
+{
+    return count_with(g, p, out, s, sample_async);
 }
 
 }  // namespace pm

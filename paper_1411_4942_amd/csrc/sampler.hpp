@@ -1,6 +1,6 @@
 // One sample of Algorithm 1 classified as in Algorithm 2, or of Algorithm 3
 // classified as in Algorithm 4, on a prepared graph (shared by the
-// single-graph and the batched kernels).
+// single-graph, batched and alias-draw kernels).
 //   r      exact uniform in [0, R) from Philox keyed by (seed, id)
 //   slot   first s with P[s] > r: guide table, then a short binary search
 //   picks  o = r - P[s-1] split in mixed radix into the two neighbour picks
@@ -32,29 +32,16 @@ __device__ __forceinline__ RowSearch row_search2(const uint32_t *__restrict__ of
     return RowSearch{(uint32_t)off[x], (uint32_t)off[x + 1], a < b ? b : a};
 }
 
-// Tally index of sample `id` (R > 0; positions below 2^32).
+// Tally index of the sample at slot s with offset o in [0, w_s) inside the
+// slot's weight w_s (Algorithms 1 and 3 from the picked edge on, classified
+// as in Algorithms 2 and 4).  w_s is read by the centered sampler only.
 template <bool CENTERED>
-__device__ __forceinline__ uint32_t sample_class(const SamplerView &g, uint64_t seed, uint64_t id)
+__device__ __forceinline__ uint32_t sample_decode(const SamplerView &g, uint32_t s, uint64_t o, uint64_t ws)
 {
-    const uint64_t r = draw_bounded(seed, CENTERED ? 1u : 0u, id, g.R);
-
-    // edge draw: s = min{s : P[s] > r}, window from the guide table
-    const uint64_t j = r >> g.shift;
-    uint32_t lo = g.guide[j], hi = g.guide[j + 1];
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (g.P[mid] > r)
-            hi = mid;
-        else
-            lo = mid + 1;
-    }
-    const uint32_t s = lo;
     const uint64_t e = g.edge[s];
     const uint32_t u = (uint32_t)e, v = (uint32_t)(e >> 32);
-    const uint64_t below = s ? g.P[s - 1] : 0ull;
     const uint32_t ou = (uint32_t)g.off[u], du = (uint32_t)g.off[u + 1] - ou;
     const uint32_t ov = (uint32_t)g.off[v], dv = (uint32_t)g.off[v + 1] - ov;
-    const uint64_t o = r - below;
     const uint32_t pos_v = s - ou;  // position of v in row u
 
     uint32_t up, vp;
@@ -71,7 +58,7 @@ __device__ __forceinline__ uint32_t sample_class(const SamplerView &g, uint64_t 
         // among the L_vu neighbours of v after u (row suffixes)
         const uint32_t luv = du - 1 - pos_v;
         uint64_t lvu, rem, a, b;
-        divmod_small(g.P[s] - below, luv, lvu, rem);
+        divmod_small(ws, luv, lvu, rem);
         divmod_small(o, (uint32_t)lvu, a, b);
         up = g.col[s + 1 + (uint32_t)a];
         vp = g.col[ov + (dv - (uint32_t)lvu) + (uint32_t)b];
@@ -99,6 +86,28 @@ __device__ __forceinline__ uint32_t sample_class(const SamplerView &g, uint64_t 
         const uint32_t y = ladder_contains(g.ladder, ou, ou + du, vp);
         return 4u + x + y;
     }
+}
+
+// Tally index of sample `id` (R > 0; positions below 2^32): r exact uniform
+// in [0, R), its slot from the guide table and a short binary search.
+template <bool CENTERED>
+__device__ __forceinline__ uint32_t sample_class(const SamplerView &g, uint64_t seed, uint64_t id)
+{
+    const uint64_t r = draw_bounded(seed, CENTERED ? 1u : 0u, id, g.R);
+
+    // edge draw: s = min{s : P[s] > r}, window from the guide table
+    const uint64_t j = r >> g.shift;
+    uint32_t lo = g.guide[j], hi = g.guide[j + 1];
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (g.P[mid] > r)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    const uint32_t s = lo;
+    const uint64_t below = s ? g.P[s - 1] : 0ull;
+    return sample_decode<CENTERED>(g, s, r - below, CENTERED ? g.P[s] - below : 0ull);
 }
 
 __device__ __forceinline__ void tally_add(uint32_t (&cnt)[PM_NUM_TALLIES], uint32_t cls)

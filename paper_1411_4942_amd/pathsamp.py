@@ -118,6 +118,9 @@ _SIGNATURES = {
     "pm_graph_export": (ctypes.c_int32, [_P, _P, _P, _P, _P, _P, _P]),
     "pm_graph_destroy": (ctypes.c_int32, [_P]),
     "pm_count": (ctypes.c_int32, [_P, ctypes.POINTER(Params), ctypes.POINTER(Result), _P]),
+    "pm_graph_build_alias": (ctypes.c_int32, [_P, _P]),
+    "pm_count_alias": (ctypes.c_int32, [_P, ctypes.POINTER(Params), ctypes.POINTER(Result), _P]),
+    "pm_graph_alias_export": (ctypes.c_int32, [_P, ctypes.c_int32, _P, _P, _P]),
     "pm_sample_async": (ctypes.c_int32, [_P, ctypes.POINTER(Params), _P, _P]),
     "pm_finalize": (ctypes.c_int32, [_P, _P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
                                      ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(Result)]),
@@ -309,6 +312,28 @@ class Graph:
         r = Result()
         _check(lib().pm_count(self._h, ctypes.byref(p), ctypes.byref(r), _stream_ptr(stream)), "pm_count")
         return r.to_dict()
+
+    def build_alias(self, stream=None):
+        """pm_graph_build_alias: the alias-draw tables of both samplers."""
+        _check(lib().pm_graph_build_alias(self._h, _stream_ptr(stream)), "pm_graph_build_alias")
+
+    def count_alias(self, k_path: int, k_cent: int | None = None, seed: int = 1, first_path: int = 0,
+                    first_cent: int = 0, delta: float = 0.01, stream=None) -> dict:
+        """pm_count_alias: both samplers through the alias tables."""
+        p = Params(k_path, k_path if k_cent is None else k_cent, seed, first_path, first_cent, delta)
+        r = Result()
+        _check(lib().pm_count_alias(self._h, ctypes.byref(p), ctypes.byref(r), _stream_ptr(stream)),
+               "pm_count_alias")
+        return r.to_dict()
+
+    def alias_export(self, centered: bool, stream=None):
+        """(K uint64[2m], alias int64[2m]) of one sampler's alias table."""
+        slots = 2 * self.info()["m"]
+        K = np.zeros(max(slots, 1), np.uint64)
+        A = np.zeros(max(slots, 1), np.int64)
+        _check(lib().pm_graph_alias_export(self._h, 1 if centered else 0, K.ctypes.data, A.ctypes.data,
+                                           _stream_ptr(stream)), "pm_graph_alias_export")
+        return K[:slots], A[:slots]
 
     def exact(self, stream=None) -> dict:
         """pm_exact_counts: {"C": [0, C1..C6], "N": [0, N1..N6], "triangles": T}."""
