@@ -281,6 +281,48 @@ def ingest_leg(scale: int, edge_factor: float, seed: int, k: int, want: dict, re
     return out
 
 
+def alias_leg(off, col, k: int, stream, reps: int = 3) -> dict:
+    """The alias-table edge draw on the benchmark graph: table build time and
+    both samplers' time against the main draw's (guide table and search)."""
+    from paper_1411_4942_amd import pathsamp as ps
+
+    g = ps.Graph(off, col, stream=stream)
+    g.build_alias(stream=stream)  # first build: allocations warmed
+    g.destroy()
+    g = ps.Graph(off, col, stream=stream)
+    ps.profile_enable(True)
+    g.build_alias(stream=stream)
+    for _ in range(reps):
+        a = g.count_alias(k, k, seed=1, stream=stream)
+        m = g.count(k, k, seed=1, stream=stream)
+    prof = ps.profile_read()
+    ps.profile_enable(False)
+    g.destroy()
+
+    def avg(name):
+        n, ms = prof[name]
+        return ms / n
+
+    alias_ms = avg("sample_path_alias") + avg("sample_centered_alias")
+    main_ms = avg("sample_path") + avg("sample_centered")
+    build_ms = avg("alias_build")
+    saved_per_sample = (main_ms - alias_ms) / (2 * k)
+    return {
+        "workload": f"the benchmark graph; k={k} per sampler, Philox seed 1, {reps} runs each",
+        "table_build_ms": build_ms,
+        "table_bytes": 2 * 32 * int(off[-1].item()),  # two tables, 32 bytes per slot
+        "alias_sampling_ms": alias_ms,
+        "main_sampling_ms": main_ms,
+        "alias_samples_per_s": 2 * k / (alias_ms * 1e-3),
+        "main_samples_per_s": 2 * k / (main_ms * 1e-3),
+        "breakeven_samples": (build_ms / saved_per_sample) if saved_per_sample > 0 else None,
+        "kernels_ms": {n: avg(n) for n in prof if n.startswith("alias") or n.startswith("sample_")},
+        "estimates_within_bars": all(
+            abs(a["est"][i] - m["est"][i]) <= (a["hi"][i] - a["lo"][i]) / 2 + (m["hi"][i] - m["lo"][i]) / 2
+            for i in range(1, 7)),
+    }
+
+
 def exact_leg(k: int = 2_000_000) -> dict:
     """Sampling against exact enumeration on Chung-Lu n = 1e6, m = 1e7
     (exponent 2.3, weight cap 5000, seed 1): times and the estimates' error."""
@@ -431,6 +473,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-ingest", action="store_true")
     ap.add_argument("--no-exact", action="store_true")
+    ap.add_argument("--no-alias", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--batch-graphs", type=int, default=256)
     ap.add_argument("--batch-k", type=int, default=200_000)
@@ -553,6 +596,11 @@ def main():
         log("[bench] ingest leg ...")
         out["ingest"] = ingest_leg(args.scale, args.edge_factor, args.seed, k, res)
         log(f"[bench] ingest: {out['ingest']['ingest_ms']:.2f} ms, end to end {out['ingest']['end_to_end_ms']:.2f} ms")
+    if not args.no_alias:
+        log("[bench] alias leg ...")
+        out["alias"] = alias_leg(off, col, k, stream)
+        log(f"[bench] alias: tables {out['alias']['table_build_ms']:.2f} ms, sampling "
+            f"{out['alias']['alias_sampling_ms']:.2f} ms vs {out['alias']['main_sampling_ms']:.2f} ms")
     if not args.no_exact:
         log("[bench] exact leg ...")
         out["exact"] = exact_leg()
