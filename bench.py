@@ -540,10 +540,10 @@ def main():
         # per slot: input column 4, its rank 4, column 4 and edge 8 written
         # (a scope over several kernels: reported, never the dominant kernel)
         "build_rows": (20 * slots, "pm::k_rows_block"),
-        # per slot: edge 8 + rev 4 + key2 4, both rows' 32-bit offset pairs 16, the two weights written 16
+        # per slot: edge 8 + rev 4 + key2 4, both rows' 32-bit offset pairs 16, both segment prefixes written 16
         "weights.reduce": (48 * slots, "pm::k_weights_reduce"),
-        # per slot: both weights read 16, both prefixes written 16, guide entries 2 (2m/4 buckets each)
-        "weights.apply": (34 * slots, "pm::k_weights_apply"),
+        # per slot: both segment prefixes read 16, guide entries 2 (2m/4 buckets of 4 bytes per table)
+        "weights.guide": (18 * slots, "pm::k_guide_fill"),
     }
     traffic = load_traffic()
     multi = {"build_rows"}  # scopes spanning several kernels

@@ -54,9 +54,10 @@ struct U128SumOp {
 
 __device__ __forceinline__ bool le128(U64x2 x, U64x2 y) { return x.b < y.b || (x.b == y.b && x.a <= y.a); }
 
+// weight of slot s from the per-segment prefix (it restarts at each segment)
 __device__ __forceinline__ uint64_t weight_of(const uint64_t *__restrict__ P, int64_t s)
 {
-    return P[s] - (s > 0 ? P[s - 1] : 0ull);
+    return P[s] - ((s & (kPrefixSeg - 1)) ? P[s - 1] : 0ull);
 }
 
 // M = N w in 128 bits
@@ -207,7 +208,8 @@ __global__ __launch_bounds__(kBlock) void k_alias_fill(const uint64_t *__restric
     }
 }
 
-// The table of one sampler's weights (prefix P over N slots, total R > 0).
+// The table of one sampler's weights (per-segment prefix P over N slots,
+// total R > 0).
 pm_status build_table(const uint64_t *P, int64_t N, uint64_t R, AliasEntry *T, hipStream_t s)
 {
     Temps tmp(s);

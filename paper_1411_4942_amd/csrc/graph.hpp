@@ -20,8 +20,10 @@ struct pm_graph {
     uint64_t *edge = nullptr;     // [slots] row | col << 32
     uint32_t *deg = nullptr;      // [n]
     int32_t *rank = nullptr;      // [n] input id -> relabelled id
-    uint64_t *p_tau = nullptr;    // [slots] inclusive prefix of tau
-    uint64_t *p_lam = nullptr;    // [slots] inclusive prefix of lambda
+    uint64_t *p_tau = nullptr;    // [slots] inclusive prefix of tau inside each kPrefixSeg-slot segment
+    uint64_t *p_lam = nullptr;    // [slots] the same for lambda
+    uint64_t *seg_tau = nullptr;  // [nseg + 1] tau before each segment; [nseg] = 2W
+    uint64_t *seg_lam = nullptr;  // [nseg + 1] the same for lambda; [nseg] = 2 Lambda
     uint32_t *ladder = nullptr;   // levels 1..ladder_top of the row search index
     int ladder_top = 0;
     uint64_t ladder_off[8] = {0};  // start of level l inside `ladder`
@@ -53,13 +55,22 @@ struct AliasEntry {
 };
 static_assert(sizeof(AliasEntry) == 32, "alias entry is 32 bytes");
 
+// Prefix sums are stored per segment of kPrefixSeg slots (one wave of the
+// weights pass): P[s] is the inclusive sum from the segment's first slot, and
+// the global prefix is P[s] + seg[s >> kPrefixSegShift].
+constexpr int kPrefixSegShift = 10;
+constexpr int64_t kPrefixSeg = 1ll << kPrefixSegShift;
+
+inline int64_t prefix_segments(int64_t slots) { return (slots + kPrefixSeg - 1) / kPrefixSeg; }
+
 // Everything one sampler needs about one graph.
 struct SamplerView {
     const uint32_t *off;
     const uint32_t *col;
     Ladder ladder;
     const uint64_t *edge;    // row | col << 32 per slot
-    const uint64_t *P;       // inclusive prefix of the sampler's weights
+    const uint64_t *P;       // inclusive prefix of the sampler's weights, per segment
+    const uint64_t *Pseg;    // prefix before each segment
     const uint32_t *guide;   // guide[j] = first slot with P > j << shift
     uint64_t R;              // total weight (0: sampler skipped)
     uint32_t shift;
@@ -75,6 +86,7 @@ inline SamplerView view_of(const pm_graph *g, bool centered)
     for (int l = 1; l < kLadderMax; ++l) v.ladder.lvl[l] = l <= g->ladder_top ? g->ladder + g->ladder_off[l] : nullptr;
     v.edge = g->edge;
     v.P = centered ? g->p_lam : g->p_tau;
+    v.Pseg = centered ? g->seg_lam : g->seg_tau;
     v.guide = centered ? g->guide_lam : g->guide_tau;
     v.R = centered ? g->R_lam : g->R_tau;
     v.shift = centered ? g->shift_lam : g->shift_tau;

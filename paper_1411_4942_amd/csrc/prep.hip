@@ -560,27 +560,30 @@ __global__ void k_copy_u32(const uint32_t *__restrict__ a, uint32_t *__restrict_
 // v (half 2).
 //
 // Launch 1 of the weights scan, written out for memory-level parallelism:
-// both weights of every slot, parked in the prefix arrays, and one pair of
-// sums per tile of kBlock * kWItems slots (the tiling of the apply launch).
-// Each thread issues the loads of kWBatch items before any store, so their
-// gathers overlap.
+// both weights of every slot and their inclusive prefix sums inside the
+// slot's segment of kPrefixSeg slots (one wave: kWItems rows of 64), and one
+// pair of sums per segment.  Each thread issues the loads of kWBatch items
+// before any store, so their gathers overlap; each row is one wave scan on
+// top of the running sum of the rows before it.
 constexpr int kWItems = 16;
 constexpr int kWBatch = 8;
+static_assert((int64_t)kWave * kWItems == kPrefixSeg, "one wave per prefix segment");
 
 __global__ __launch_bounds__(kBlock) void k_weights_reduce(const uint64_t *__restrict__ edge,
                                                            const uint32_t *__restrict__ rev,
                                                            const uint32_t *__restrict__ key2,
                                                            const uint32_t *__restrict__ off, int64_t N,
                                                            uint64_t *__restrict__ p_tau,
-                                                           uint64_t *__restrict__ p_lam, U64x2 *__restrict__ tile_sums,
+                                                           uint64_t *__restrict__ p_lam, U64x2 *__restrict__ seg_sums,
                                                            PrepStats *st)
 {
-    __shared__ U64x2 s_wave[kBlock / kWave];
     const int w = threadIdx.x / kWave;
     const int lane = lane_id();
-    const int64_t wave_base = (int64_t)blockIdx.x * (kBlock * kWItems) + (int64_t)w * kWave * kWItems;
+    const int64_t seg = (int64_t)blockIdx.x * (kBlock / kWave) + w;
+    const int64_t wave_base = seg * kPrefixSeg;
+    if (wave_base >= N) return;  // wave-uniform; no barrier below
     uint32_t err = 0;
-    uint64_t acc_t = 0, acc_l = 0;
+    U64x2 carry{0, 0};
 #pragma unroll
     for (int h = 0; h < kWItems; h += kWBatch) {
         uint64_t e[kWBatch];
@@ -605,33 +608,50 @@ __global__ __launch_bounds__(kBlock) void k_weights_reduce(const uint64_t *__res
 #pragma unroll
         for (int i = 0; i < kWBatch; ++i) {
             const int64_t idx = wave_base + (int64_t)(h + i) * kWave + lane;
-            if (idx >= N) continue;
-            const uint32_t u = (uint32_t)e[i];
-            const int64_t rr = r[i];
-            if (k2[i] != u) err |= ERR_ASYM;  // symmetry, half 1
-            if (rr < (int64_t)ov[i] || rr >= (int64_t)ov1[i]) err |= ERR_ASYM;  // half 2
-            const int64_t du = (int64_t)ou1[i] - ou[i], dv = (int64_t)ov1[i] - ov[i];
-            const uint64_t tau = (uint64_t)(du - 1) * (uint64_t)(dv - 1);
-            const uint64_t luv = (uint64_t)(du - 1 - (idx - (int64_t)ou[i]));
-            const uint64_t lvu = (uint64_t)(dv - 1 - (rr - (int64_t)ov[i]));
-            const uint64_t lam = luv * lvu;
-            p_tau[idx] = tau;
-            p_lam[idx] = lam;
-            acc_t += tau;
-            acc_l += lam;
+            uint64_t tau = 0, lam = 0;
+            if (idx < N) {
+                const uint32_t u = (uint32_t)e[i];
+                const int64_t rr = r[i];
+                if (k2[i] != u) err |= ERR_ASYM;                                    // symmetry, half 1
+                if (rr < (int64_t)ov[i] || rr >= (int64_t)ov1[i]) err |= ERR_ASYM;  // half 2
+                const int64_t du = (int64_t)ou1[i] - ou[i], dv = (int64_t)ov1[i] - ov[i];
+                tau = (uint64_t)(du - 1) * (uint64_t)(dv - 1);
+                const uint64_t luv = (uint64_t)(du - 1 - (idx - (int64_t)ou[i]));
+                const uint64_t lvu = (uint64_t)(dv - 1 - (rr - (int64_t)ov[i]));
+                lam = luv * lvu;
+            }
+            const U64x2 incl = wave_inclusive(U64x2{tau, lam}, PairSumOp(), U64x2{0, 0});
+            if (idx < N) {
+                p_tau[idx] = carry.a + incl.a;
+                p_lam[idx] = carry.b + incl.b;
+            }
+            carry = PairSumOp()(carry, shfl_idx_t(incl, kWave - 1));
         }
     }
     if (err) atomicOr(&st->err, err);
-    const U64x2 acc = wave_reduce(U64x2{acc_t, acc_l}, PairSumOp());
-    if (lane == 0) s_wave[w] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        U64x2 t{0, 0};
-#pragma unroll
-        for (int i = 0; i < kBlock / kWave; ++i) t = PairSumOp()(t, s_wave[i]);
-        tile_sums[blockIdx.x] = t;
-    }
+    if (lane == 0) seg_sums[seg] = carry;
 }
+
+// exclusive prefixes of the segment sums, the totals after the last one
+struct SegIn {
+    const U64x2 *sums;
+    __device__ __forceinline__ U64x2 operator()(int64_t i) const { return sums[i]; }
+};
+struct SegOut {
+    uint64_t *seg_tau, *seg_lam;
+    int64_t nseg;
+    U64x2 *totals;
+    __device__ __forceinline__ void operator()(int64_t i, U64x2 incl, U64x2 x) const
+    {
+        seg_tau[i] = incl.a - x.a;
+        seg_lam[i] = incl.b - x.b;
+        if (i == nseg - 1) {
+            seg_tau[nseg] = incl.a;
+            seg_lam[nseg] = incl.b;
+            *totals = incl;
+        }
+    }
+};
 
 // Guide entries of slot i: the buckets whose start j << shift lies in
 // [P[i-1], P[i]) point at slot i.  Runs longer than 64 buckets go to a list
@@ -679,112 +699,77 @@ __global__ void k_guide_setup(PrepStats *st, int64_t slots, uint32_t *guide_tau,
     if (Rl) guide_lam[nbl] = (uint32_t)(slots - 1);
 }
 
-// Launch 3 of the weights scan: the prefixes from the parked weights, the
-// wrap checks and the guide entries.  The tiles are those of
-// k_weights_reduce; each wave covers kWRounds rounds of kWave * kWV
-// consecutive slots, and in a round lane l owns kWV consecutive slots
-// (16-byte loads and stores that cover whole cache lines per instruction),
-// sums them sequentially, and one wave scan places the lane totals.
+// Launch 3 of the weights scan: the guide entries from the global prefixes
+// (segment prefix + offset), and the wrap checks.  Each wave covers kWRounds
+// rounds of kWave * kWV consecutive slots; in a round lane l owns kWV
+// consecutive slots (16-byte loads covering whole lines per instruction) and
+// the prefix before them.
 constexpr int kWV = 4;
 constexpr int kWRounds = kWItems / kWV;
 
-__global__ __launch_bounds__(kBlock) void k_weights_apply(uint64_t *__restrict__ p_tau, uint64_t *__restrict__ p_lam,
-                                                          int64_t N, const U64x2 *__restrict__ tile_prefix,
-                                                          uint32_t *__restrict__ guide_tau,
-                                                          uint32_t *__restrict__ guide_lam,
-                                                          uint32_t *__restrict__ long_tau,
-                                                          uint32_t *__restrict__ long_lam, uint32_t long_cap,
-                                                          PrepStats *st)
+__device__ __forceinline__ uint64_t global_prefix(const uint64_t *__restrict__ P, const uint64_t *__restrict__ seg,
+                                                  int64_t i)
 {
-    __shared__ U64x2 s_wave[kBlock / kWave];
+    return P[i] + seg[i >> kPrefixSegShift];
+}
+
+__global__ __launch_bounds__(kBlock) void k_guide_fill(const uint64_t *__restrict__ p_tau,
+                                                       const uint64_t *__restrict__ p_lam,
+                                                       const uint64_t *__restrict__ seg_tau,
+                                                       const uint64_t *__restrict__ seg_lam, int64_t N,
+                                                       uint32_t *__restrict__ guide_tau,
+                                                       uint32_t *__restrict__ guide_lam,
+                                                       uint32_t *__restrict__ long_tau,
+                                                       uint32_t *__restrict__ long_lam, uint32_t long_cap,
+                                                       PrepStats *st)
+{
     const int w = threadIdx.x / kWave;
     const int lane = lane_id();
     const int64_t wave_base = (int64_t)blockIdx.x * (kBlock * kWItems) + (int64_t)w * (kWave * kWItems);
     const uint32_t sh_t = st->shift_tau, sh_l = st->shift_lam;
     const uint64_t nb_t = st->nb_tau, nb_l = st->nb_lam;
-    uint64_t a[kWItems], b[kWItems];
-#pragma unroll
-    for (int rd = 0; rd < kWRounds; ++rd) {
-        const int64_t s0 = wave_base + (int64_t)rd * (kWave * kWV) + (int64_t)lane * kWV;
-        uint64_t *x = a + rd * kWV, *y = b + rd * kWV;
-        if (s0 + kWV <= N) {
-            const uint4 *pa = reinterpret_cast<const uint4 *>(p_tau + s0);
-            const uint4 *pb = reinterpret_cast<const uint4 *>(p_lam + s0);
-            const uint4 x0 = pa[0], x1 = pa[1], y0 = pb[0], y1 = pb[1];
-            x[0] = (uint64_t)x0.x | ((uint64_t)x0.y << 32);
-            x[1] = (uint64_t)x0.z | ((uint64_t)x0.w << 32);
-            x[2] = (uint64_t)x1.x | ((uint64_t)x1.y << 32);
-            x[3] = (uint64_t)x1.z | ((uint64_t)x1.w << 32);
-            y[0] = (uint64_t)y0.x | ((uint64_t)y0.y << 32);
-            y[1] = (uint64_t)y0.z | ((uint64_t)y0.w << 32);
-            y[2] = (uint64_t)y1.x | ((uint64_t)y1.y << 32);
-            y[3] = (uint64_t)y1.z | ((uint64_t)y1.w << 32);
-        } else {
-#pragma unroll
-            for (int j = 0; j < kWV; ++j) {
-                x[j] = s0 + j < N ? p_tau[s0 + j] : 0ull;
-                y[j] = s0 + j < N ? p_lam[s0 + j] : 0ull;
-            }
-        }
-    }
-    // per round: lane-local inclusive sums, then the lane's place in the wave
-    U64x2 lane_excl[kWRounds];
-    U64x2 wave_run{0, 0};
-#pragma unroll
-    for (int rd = 0; rd < kWRounds; ++rd) {
-#pragma unroll
-        for (int j = 1; j < kWV; ++j) {
-            a[rd * kWV + j] += a[rd * kWV + j - 1];
-            b[rd * kWV + j] += b[rd * kWV + j - 1];
-        }
-        const U64x2 tot{a[rd * kWV + kWV - 1], b[rd * kWV + kWV - 1]};
-        const U64x2 incl = wave_inclusive(tot, PairSumOp(), U64x2{0, 0});
-        lane_excl[rd] = U64x2{wave_run.a + incl.a - tot.a, wave_run.b + incl.b - tot.b};
-        wave_run = PairSumOp()(wave_run, shfl_idx_t(incl, kWave - 1));
-    }
-    if (lane == 0) s_wave[w] = wave_run;
-    __syncthreads();
-    U64x2 wave_pre = tile_prefix[blockIdx.x];
-    for (int i = 0; i < w; ++i) wave_pre = PairSumOp()(wave_pre, s_wave[i]);
     uint32_t err = 0;
 #pragma unroll
     for (int rd = 0; rd < kWRounds; ++rd) {
         const int64_t s0 = wave_base + (int64_t)rd * (kWave * kWV) + (int64_t)lane * kWV;
-        const uint64_t ra = wave_pre.a + lane_excl[rd].a, rb = wave_pre.b + lane_excl[rd].b;
-        uint64_t prev_a = ra, prev_b = rb;
-        uint64_t *x = a + rd * kWV, *y = b + rd * kWV;
+        if (s0 >= N) break;
+        uint64_t a[kWV], b[kWV];
+        if (s0 + kWV <= N) {
+            // kWV slots never straddle a segment (kWV divides kPrefixSeg)
+            const uint4 *pa = reinterpret_cast<const uint4 *>(p_tau + s0);
+            const uint4 *pb = reinterpret_cast<const uint4 *>(p_lam + s0);
+            const uint4 x0 = pa[0], x1 = pa[1], y0 = pb[0], y1 = pb[1];
+            const uint64_t ot = seg_tau[s0 >> kPrefixSegShift], ol = seg_lam[s0 >> kPrefixSegShift];
+            a[0] = ((uint64_t)x0.x | ((uint64_t)x0.y << 32)) + ot;
+            a[1] = ((uint64_t)x0.z | ((uint64_t)x0.w << 32)) + ot;
+            a[2] = ((uint64_t)x1.x | ((uint64_t)x1.y << 32)) + ot;
+            a[3] = ((uint64_t)x1.z | ((uint64_t)x1.w << 32)) + ot;
+            b[0] = ((uint64_t)y0.x | ((uint64_t)y0.y << 32)) + ol;
+            b[1] = ((uint64_t)y0.z | ((uint64_t)y0.w << 32)) + ol;
+            b[2] = ((uint64_t)y1.x | ((uint64_t)y1.y << 32)) + ol;
+            b[3] = ((uint64_t)y1.z | ((uint64_t)y1.w << 32)) + ol;
+        } else {
+#pragma unroll
+            for (int j = 0; j < kWV; ++j) {
+                a[j] = s0 + j < N ? global_prefix(p_tau, seg_tau, s0 + j) : 0ull;
+                b[j] = s0 + j < N ? global_prefix(p_lam, seg_lam, s0 + j) : 0ull;
+            }
+        }
+        uint64_t prev_a = s0 > 0 ? global_prefix(p_tau, seg_tau, s0 - 1) : 0ull;
+        uint64_t prev_b = s0 > 0 ? global_prefix(p_lam, seg_lam, s0 - 1) : 0ull;
 #pragma unroll
         for (int j = 0; j < kWV; ++j) {
             const int64_t idx = s0 + j;
-            const uint64_t ia = ra + x[j], ib = rb + y[j];
-            if (idx < N) {
-                // the running sum passed 2^64 exactly where it decreases
-                if (ia < prev_a) err |= ERR_OVF_TAU;
-                if (ib < prev_b) err |= ERR_OVF_LAM;
-                guide_fill(prev_a, ia, sh_t, nb_t, (uint32_t)idx, guide_tau, long_tau, long_cap, &st->nlong_tau,
-                           &st->err);
-                guide_fill(prev_b, ib, sh_l, nb_l, (uint32_t)idx, guide_lam, long_lam, long_cap, &st->nlong_lam,
-                           &st->err);
-            }
-            x[j] = ia;
-            y[j] = ib;
-            prev_a = ia;
-            prev_b = ib;
-        }
-        if (s0 + kWV <= N) {
-            uint4 *pa = reinterpret_cast<uint4 *>(p_tau + s0);
-            uint4 *pb = reinterpret_cast<uint4 *>(p_lam + s0);
-            pa[0] = make_uint4((uint32_t)x[0], (uint32_t)(x[0] >> 32), (uint32_t)x[1], (uint32_t)(x[1] >> 32));
-            pa[1] = make_uint4((uint32_t)x[2], (uint32_t)(x[2] >> 32), (uint32_t)x[3], (uint32_t)(x[3] >> 32));
-            pb[0] = make_uint4((uint32_t)y[0], (uint32_t)(y[0] >> 32), (uint32_t)y[1], (uint32_t)(y[1] >> 32));
-            pb[1] = make_uint4((uint32_t)y[2], (uint32_t)(y[2] >> 32), (uint32_t)y[3], (uint32_t)(y[3] >> 32));
-        } else {
-#pragma unroll
-            for (int j = 0; j < kWV; ++j)
-                if (s0 + j < N) {
-                    p_tau[s0 + j] = x[j];
-                    p_lam[s0 + j] = y[j];
-                }
+            if (idx >= N) break;
+            // the running sum passed 2^64 exactly where it decreases
+            if (a[j] < prev_a) err |= ERR_OVF_TAU;
+            if (b[j] < prev_b) err |= ERR_OVF_LAM;
+            guide_fill(prev_a, a[j], sh_t, nb_t, (uint32_t)idx, guide_tau, long_tau, long_cap, &st->nlong_tau,
+                       &st->err);
+            guide_fill(prev_b, b[j], sh_l, nb_l, (uint32_t)idx, guide_lam, long_lam, long_cap, &st->nlong_lam,
+                       &st->err);
+            prev_a = a[j];
+            prev_b = b[j];
         }
     }
     if (err) atomicOr(&st->err, err);
@@ -841,7 +826,8 @@ __global__ __launch_bounds__(kBlock) void k_n1(const uint32_t *__restrict__ deg,
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_guide_long(const uint64_t *__restrict__ P, const uint32_t *shift_p,
+__global__ __launch_bounds__(kBlock) void k_guide_long(const uint64_t *__restrict__ P,
+                                                       const uint64_t *__restrict__ seg, const uint32_t *shift_p,
                                                        uint32_t *__restrict__ guide,
                                                        const uint32_t *__restrict__ long_list,
                                                        const uint32_t *nlong, uint32_t cap)
@@ -851,7 +837,7 @@ __global__ __launch_bounds__(kBlock) void k_guide_long(const uint64_t *__restric
     const uint32_t cnt = *nlong < cap ? *nlong : cap;  // listed runs were checked against nb
     for (uint32_t e = blockIdx.x; e < cnt; e += gridDim.x) {
         uint32_t s = long_list[e];
-        uint64_t prev = s > 0 ? P[s - 1] : 0ull, cur = P[s];
+        uint64_t prev = s > 0 ? global_prefix(P, seg, s - 1) : 0ull, cur = global_prefix(P, seg, s);
         uint64_t j0 = (prev >> shift) + ((prev & mask) != 0 ? 1u : 0u);
         uint64_t j1 = (cur - 1) >> shift;
         for (uint64_t j = j0 + threadIdx.x; j <= j1; j += blockDim.x) guide[j] = s;
@@ -890,6 +876,8 @@ void graph_free(pm_graph *g, hipStream_t s)
     dev_free(g->rank, s);
     dev_free(g->p_tau, s);
     dev_free(g->p_lam, s);
+    dev_free(g->seg_tau, s);
+    dev_free(g->seg_lam, s);
     dev_free(g->guide_tau, s);
     dev_free(g->guide_lam, s);
     dev_free(g->alias_tau, s);
@@ -908,6 +896,7 @@ uint64_t graph_bytes_for(int64_t n, int64_t slots)
     for (int l = 1; l <= top; ++l) total += (ladder_count(slots, l) + 31) / 32 * 32;
     if (top > 0) b += 4 * (total + 32);
     b += 12 * ss + 16 * ss;
+    b += 2 * 8 * ((uint64_t)prefix_segments(slots) + 1);
     b += 2 * 4 * (guide_target(slots) + 1);
     return b;
 }
@@ -1160,9 +1149,12 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
 
     // weights, their prefixes and the guide tables of the edge draws (nothing
     // below indexes memory through the weights until the checks are read back)
+    const int64_t nseg = prefix_segments(slots);
     PM_TRY(dev_alloc((void **)&g->p_tau, sizeof(uint64_t) * ss, s));
     PM_TRY(dev_alloc((void **)&g->p_lam, sizeof(uint64_t) * ss, s));
-    g->bytes += 2 * sizeof(uint64_t) * ss;
+    PM_TRY(dev_alloc((void **)&g->seg_tau, sizeof(uint64_t) * (nseg + 1), s));
+    PM_TRY(dev_alloc((void **)&g->seg_lam, sizeof(uint64_t) * (nseg + 1), s));
+    g->bytes += 2 * sizeof(uint64_t) * ss + 2 * sizeof(uint64_t) * (nseg + 1);
     const uint64_t gtarget = guide_target(slots);
     const uint64_t long_cap = gtarget / 64 + 2;
     PM_TRY(dev_alloc((void **)&g->guide_tau, sizeof(uint32_t) * (gtarget + 1), s));
@@ -1171,51 +1163,47 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
     uint32_t *long_tau = nullptr, *long_lam = nullptr;
     PM_TRY(tmp.get(&long_tau, long_cap));
     PM_TRY(tmp.get(&long_lam, long_cap));
-    {
+    if (slots == 0) {
+        PM_TRY(fill_async<uint64_t>(g->seg_tau, 0ull, 1, s));
+        PM_TRY(fill_async<uint64_t>(g->seg_lam, 0ull, 1, s));
+    } else {
+        U64x2 *sums = nullptr;
         char *scr = nullptr;
-        PM_TRY(tmp.get(&scr, ScanScratch<U64x2>::bytes_for(slots, 16)));
+        PM_TRY(tmp.get(&sums, (size_t)nseg));
+        PM_TRY(tmp.get(&scr, ScanScratch<U64x2>::bytes_for(nseg, 16)));
         ProfScope prof("weights_scan", s);
-        auto mid = [&]() -> pm_status {
-            hipLaunchKernelGGL(k_guide_setup, dim3(1), dim3(1), 0, s, st, slots, g->guide_tau, g->guide_lam);
+        const int64_t tiles = (slots + (int64_t)kBlock * kWItems - 1) / ((int64_t)kBlock * kWItems);
+        {
+            ProfScope pr("weights.reduce", s);
+            hipLaunchKernelGGL(k_weights_reduce, dim3((unsigned)tiles), dim3(kBlock), 0, s, g->edge, rev, key2, g->off,
+                               slots, g->p_tau, g->p_lam, sums, st);
             PM_HIP(hipGetLastError());
-            return PM_OK;
-        };
-        if (slots > 0) {
-            const int64_t tiles = (slots + (int64_t)kBlock * kWItems - 1) / ((int64_t)kBlock * kWItems);
-            U64x2 *sums = (U64x2 *)scr;
-            {
-                ProfScope pr("weights.reduce", s);
-                hipLaunchKernelGGL(k_weights_reduce, dim3((unsigned)tiles), dim3(kBlock), 0, s, g->edge, rev, key2,
-                                   g->off, slots, g->p_tau, g->p_lam, sums, st);
-            }
-            hipLaunchKernelGGL((scan_tiles_kernel<U64x2, PairSumOp>), dim3(1), dim3(1024), 0, s, sums, tiles,
-                               PairSumOp(), U64x2{0, 0}, &st->totals);
-            PM_HIP(hipGetLastError());
-            PM_TRY(mid());
-            ProfScope pa("weights.apply", s);
-            hipLaunchKernelGGL(k_weights_apply, dim3((unsigned)tiles), dim3(kBlock), 0, s, g->p_tau, g->p_lam, slots,
-                               (const U64x2 *)sums, g->guide_tau, g->guide_lam, long_tau, long_lam,
+        }
+        PM_TRY((scan_launch<U64x2, 16>(SegIn{sums}, SegOut{g->seg_tau, g->seg_lam, nseg, &st->totals}, nseg,
+                                       PairSumOp(), U64x2{0, 0}, scr, s)));
+        hipLaunchKernelGGL(k_guide_setup, dim3(1), dim3(1), 0, s, st, slots, g->guide_tau, g->guide_lam);
+        PM_HIP(hipGetLastError());
+        {
+            ProfScope pg("weights.guide", s);
+            hipLaunchKernelGGL(k_guide_fill, dim3((unsigned)tiles), dim3(kBlock), 0, s, g->p_tau, g->p_lam,
+                               g->seg_tau, g->seg_lam, slots, g->guide_tau, g->guide_lam, long_tau, long_lam,
                                (uint32_t)long_cap, st);
             PM_HIP(hipGetLastError());
         }
-        if (slots > 0) {
-            const unsigned gl = (unsigned)std::min<uint64_t>(long_cap, 2048);
-            hipLaunchKernelGGL(k_guide_long, dim3(gl), dim3(kBlock), 0, s, g->p_tau, &st->shift_tau, g->guide_tau,
-                               long_tau, &st->nlong_tau, (uint32_t)long_cap);
-            hipLaunchKernelGGL(k_guide_long, dim3(gl), dim3(kBlock), 0, s, g->p_lam, &st->shift_lam, g->guide_lam,
-                               long_lam, &st->nlong_lam, (uint32_t)long_cap);
-            PM_HIP(hipGetLastError());
-        }
+        const unsigned gl = (unsigned)std::min<uint64_t>(long_cap, 2048);
+        hipLaunchKernelGGL(k_guide_long, dim3(gl), dim3(kBlock), 0, s, g->p_tau, g->seg_tau, &st->shift_tau,
+                           g->guide_tau, long_tau, &st->nlong_tau, (uint32_t)long_cap);
+        hipLaunchKernelGGL(k_guide_long, dim3(gl), dim3(kBlock), 0, s, g->p_lam, g->seg_lam, &st->shift_lam,
+                           g->guide_lam, long_lam, &st->nlong_lam, (uint32_t)long_cap);
+        PM_HIP(hipGetLastError());
     }
     if (n > 0) {
         hipLaunchKernelGGL(k_n1, dim3(grid_for(n, kBlock, 1024)), dim3(kBlock), 0, s, g->deg, n, st);
         PM_HIP(hipGetLastError());
     }
     uint64_t R[2] = {0, 0};
-    if (slots > 0) {
-        PM_HIP(hipMemcpyAsync(&R[0], g->p_tau + slots - 1, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-        PM_HIP(hipMemcpyAsync(&R[1], g->p_lam + slots - 1, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-    }
+    PM_HIP(hipMemcpyAsync(&R[0], g->seg_tau + nseg, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    PM_HIP(hipMemcpyAsync(&R[1], g->seg_lam + nseg, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     PM_HIP(hipMemcpyAsync(&hst, st, sizeof(hst), hipMemcpyDeviceToHost, s));
     PM_HIP(hipStreamSynchronize(s));
     if (hst.err & ERR_ASYM) {
@@ -1265,14 +1253,27 @@ pm_status graph_export(const pm_graph *g, int64_t *off, int32_t *col, int32_t *r
         off32.resize((size_t)g->n + 1);
         PM_HIP(hipMemcpyAsync(off32.data(), g->off, sizeof(uint32_t) * (g->n + 1), hipMemcpyDeviceToHost, s));
     }
+    const int64_t nseg = prefix_segments(g->slots);
+    std::vector<uint64_t> seg_t, seg_l;
     if (g->slots > 0) {
         if (col) PM_HIP(hipMemcpyAsync(col, g->col, sizeof(int32_t) * g->slots, hipMemcpyDeviceToHost, s));
-        if (p_tau) PM_HIP(hipMemcpyAsync(p_tau, g->p_tau, sizeof(uint64_t) * g->slots, hipMemcpyDeviceToHost, s));
-        if (p_lam) PM_HIP(hipMemcpyAsync(p_lam, g->p_lam, sizeof(uint64_t) * g->slots, hipMemcpyDeviceToHost, s));
+        if (p_tau) {
+            seg_t.resize((size_t)nseg);
+            PM_HIP(hipMemcpyAsync(p_tau, g->p_tau, sizeof(uint64_t) * g->slots, hipMemcpyDeviceToHost, s));
+            PM_HIP(hipMemcpyAsync(seg_t.data(), g->seg_tau, sizeof(uint64_t) * nseg, hipMemcpyDeviceToHost, s));
+        }
+        if (p_lam) {
+            seg_l.resize((size_t)nseg);
+            PM_HIP(hipMemcpyAsync(p_lam, g->p_lam, sizeof(uint64_t) * g->slots, hipMemcpyDeviceToHost, s));
+            PM_HIP(hipMemcpyAsync(seg_l.data(), g->seg_lam, sizeof(uint64_t) * nseg, hipMemcpyDeviceToHost, s));
+        }
     }
     if (rank && g->n > 0) PM_HIP(hipMemcpyAsync(rank, g->rank, sizeof(int32_t) * g->n, hipMemcpyDeviceToHost, s));
     PM_HIP(hipStreamSynchronize(s));
     for (size_t i = 0; i < off32.size(); ++i) off[i] = off32[i];  // the ABI's offsets are int64
+    // the ABI's prefixes are global: segment prefix + the segment's offset
+    for (size_t i = 0; i < (p_tau ? (size_t)g->slots : 0); ++i) p_tau[i] += seg_t[i >> kPrefixSegShift];
+    for (size_t i = 0; i < (p_lam ? (size_t)g->slots : 0); ++i) p_lam[i] += seg_l[i >> kPrefixSegShift];
     return PM_OK;
 }
 

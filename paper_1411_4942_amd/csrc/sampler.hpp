@@ -88,6 +88,12 @@ __device__ __forceinline__ uint32_t sample_decode(const SamplerView &g, uint32_t
     }
 }
 
+// global inclusive prefix of the sampler's weights at slot i
+__device__ __forceinline__ uint64_t prefix_at(const SamplerView &g, uint32_t i)
+{
+    return g.P[i] + g.Pseg[i >> kPrefixSegShift];
+}
+
 // Tally index of sample `id` (R > 0; positions below 2^32): r exact uniform
 // in [0, R), its slot from the guide table and a short binary search.
 template <bool CENTERED>
@@ -95,19 +101,38 @@ __device__ __forceinline__ uint32_t sample_class(const SamplerView &g, uint64_t 
 {
     const uint64_t r = draw_bounded(seed, CENTERED ? 1u : 0u, id, g.R);
 
-    // edge draw: s = min{s : P[s] > r}, window from the guide table
+    // edge draw: s = min{s : P[s] > r}, window from the guide table.  Inside
+    // one prefix segment the search compares the stored (segment) prefixes
+    // with r less the segment's offset: one offset load instead of one per
+    // probe (a window nearly always lies in one segment).
     const uint64_t j = r >> g.shift;
     uint32_t lo = g.guide[j], hi = g.guide[j + 1];
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (g.P[mid] > r)
-            hi = mid;
-        else
-            lo = mid + 1;
+    const uint32_t sg = lo >> kPrefixSegShift;
+    const uint64_t off_sg = g.Pseg[sg];
+    if (hi == lo || ((hi - 1) >> kPrefixSegShift) == sg) {
+        const uint64_t rl = r - off_sg;  // slots before lo have prefix <= r, so rl >= 0
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (g.P[mid] > rl)
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+    } else {
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (prefix_at(g, mid) > r)
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
     }
     const uint32_t s = lo;
-    const uint64_t below = s ? g.P[s - 1] : 0ull;
-    return sample_decode<CENTERED>(g, s, r - below, CENTERED ? g.P[s] - below : 0ull);
+    // the global prefix just before a segment is that segment's offset
+    const bool first = (s & (kPrefixSeg - 1)) == 0;
+    const uint64_t p_prev = first ? 0ull : g.P[s - 1];
+    const uint64_t below = ((s >> kPrefixSegShift) == sg ? off_sg : g.Pseg[s >> kPrefixSegShift]) + p_prev;
+    return sample_decode<CENTERED>(g, s, r - below, CENTERED ? g.P[s] - p_prev : 0ull);
 }
 
 __device__ __forceinline__ void tally_add(uint32_t (&cnt)[PM_NUM_TALLIES], uint32_t cls)
