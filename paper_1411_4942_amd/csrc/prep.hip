@@ -702,8 +702,10 @@ __global__ void k_guide_setup(PrepStats *st, int64_t slots, uint32_t *guide_tau,
 // Launch 3 of the weights scan: the guide entries from the global prefixes
 // (segment prefix + offset), and the wrap checks.  Each wave covers kWRounds
 // rounds of kWave * kWV consecutive slots; in a round lane l owns kWV
-// consecutive slots (16-byte loads covering whole lines per instruction) and
-// the prefix before them.
+// consecutive slots (16-byte loads covering whole lines per instruction).
+// All rounds are loaded first; the prefix before a lane's first slot comes
+// from the lane before it (lane 0: the previous round's last lane, or memory
+// at the wave's first slot).
 constexpr int kWV = 4;
 constexpr int kWRounds = kWItems / kWV;
 
@@ -729,47 +731,57 @@ __global__ __launch_bounds__(kBlock) void k_guide_fill(const uint64_t *__restric
     const uint32_t sh_t = st->shift_tau, sh_l = st->shift_lam;
     const uint64_t nb_t = st->nb_tau, nb_l = st->nb_lam;
     uint32_t err = 0;
+    uint64_t A[kWRounds][kWV], B[kWRounds][kWV];
 #pragma unroll
     for (int rd = 0; rd < kWRounds; ++rd) {
         const int64_t s0 = wave_base + (int64_t)rd * (kWave * kWV) + (int64_t)lane * kWV;
-        if (s0 >= N) break;
-        uint64_t a[kWV], b[kWV];
         if (s0 + kWV <= N) {
-            // kWV slots never straddle a segment (kWV divides kPrefixSeg)
             const uint4 *pa = reinterpret_cast<const uint4 *>(p_tau + s0);
             const uint4 *pb = reinterpret_cast<const uint4 *>(p_lam + s0);
             const uint4 x0 = pa[0], x1 = pa[1], y0 = pb[0], y1 = pb[1];
             const uint64_t ot = seg_tau[s0 >> kPrefixSegShift], ol = seg_lam[s0 >> kPrefixSegShift];
-            a[0] = ((uint64_t)x0.x | ((uint64_t)x0.y << 32)) + ot;
-            a[1] = ((uint64_t)x0.z | ((uint64_t)x0.w << 32)) + ot;
-            a[2] = ((uint64_t)x1.x | ((uint64_t)x1.y << 32)) + ot;
-            a[3] = ((uint64_t)x1.z | ((uint64_t)x1.w << 32)) + ot;
-            b[0] = ((uint64_t)y0.x | ((uint64_t)y0.y << 32)) + ol;
-            b[1] = ((uint64_t)y0.z | ((uint64_t)y0.w << 32)) + ol;
-            b[2] = ((uint64_t)y1.x | ((uint64_t)y1.y << 32)) + ol;
-            b[3] = ((uint64_t)y1.z | ((uint64_t)y1.w << 32)) + ol;
+            A[rd][0] = ((uint64_t)x0.x | ((uint64_t)x0.y << 32)) + ot;
+            A[rd][1] = ((uint64_t)x0.z | ((uint64_t)x0.w << 32)) + ot;
+            A[rd][2] = ((uint64_t)x1.x | ((uint64_t)x1.y << 32)) + ot;
+            A[rd][3] = ((uint64_t)x1.z | ((uint64_t)x1.w << 32)) + ot;
+            B[rd][0] = ((uint64_t)y0.x | ((uint64_t)y0.y << 32)) + ol;
+            B[rd][1] = ((uint64_t)y0.z | ((uint64_t)y0.w << 32)) + ol;
+            B[rd][2] = ((uint64_t)y1.x | ((uint64_t)y1.y << 32)) + ol;
+            B[rd][3] = ((uint64_t)y1.z | ((uint64_t)y1.w << 32)) + ol;
         } else {
 #pragma unroll
             for (int j = 0; j < kWV; ++j) {
-                a[j] = s0 + j < N ? global_prefix(p_tau, seg_tau, s0 + j) : 0ull;
-                b[j] = s0 + j < N ? global_prefix(p_lam, seg_lam, s0 + j) : 0ull;
+                A[rd][j] = s0 + j < N ? global_prefix(p_tau, seg_tau, s0 + j) : 0ull;
+                B[rd][j] = s0 + j < N ? global_prefix(p_lam, seg_lam, s0 + j) : 0ull;
             }
         }
-        uint64_t prev_a = s0 > 0 ? global_prefix(p_tau, seg_tau, s0 - 1) : 0ull;
-        uint64_t prev_b = s0 > 0 ? global_prefix(p_lam, seg_lam, s0 - 1) : 0ull;
+    }
+    uint64_t carry_a = 0, carry_b = 0;  // the prefix before the round's first slot
+    if (wave_base > 0 && wave_base <= N) {
+        carry_a = global_prefix(p_tau, seg_tau, wave_base - 1);
+        carry_b = global_prefix(p_lam, seg_lam, wave_base - 1);
+    }
+#pragma unroll
+    for (int rd = 0; rd < kWRounds; ++rd) {
+        const int64_t s0 = wave_base + (int64_t)rd * (kWave * kWV) + (int64_t)lane * kWV;
+        const uint64_t up_a = __shfl_up(A[rd][kWV - 1], 1, kWave), up_b = __shfl_up(B[rd][kWV - 1], 1, kWave);
+        uint64_t prev_a = lane ? up_a : carry_a, prev_b = lane ? up_b : carry_b;
+        carry_a = __shfl(A[rd][kWV - 1], kWave - 1, kWave);
+        carry_b = __shfl(B[rd][kWV - 1], kWave - 1, kWave);
 #pragma unroll
         for (int j = 0; j < kWV; ++j) {
             const int64_t idx = s0 + j;
-            if (idx >= N) break;
-            // the running sum passed 2^64 exactly where it decreases
-            if (a[j] < prev_a) err |= ERR_OVF_TAU;
-            if (b[j] < prev_b) err |= ERR_OVF_LAM;
-            guide_fill(prev_a, a[j], sh_t, nb_t, (uint32_t)idx, guide_tau, long_tau, long_cap, &st->nlong_tau,
-                       &st->err);
-            guide_fill(prev_b, b[j], sh_l, nb_l, (uint32_t)idx, guide_lam, long_lam, long_cap, &st->nlong_lam,
-                       &st->err);
-            prev_a = a[j];
-            prev_b = b[j];
+            if (idx < N) {
+                // the running sum passed 2^64 exactly where it decreases
+                if (A[rd][j] < prev_a) err |= ERR_OVF_TAU;
+                if (B[rd][j] < prev_b) err |= ERR_OVF_LAM;
+                guide_fill(prev_a, A[rd][j], sh_t, nb_t, (uint32_t)idx, guide_tau, long_tau, long_cap, &st->nlong_tau,
+                           &st->err);
+                guide_fill(prev_b, B[rd][j], sh_l, nb_l, (uint32_t)idx, guide_lam, long_lam, long_cap,
+                           &st->nlong_lam, &st->err);
+            }
+            prev_a = A[rd][j];
+            prev_b = B[rd][j];
         }
     }
     if (err) atomicOr(&st->err, err);

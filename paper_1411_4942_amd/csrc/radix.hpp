@@ -54,18 +54,24 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb)
     return x * per + (x < extra ? x : extra) + i;
 }
 
+// Digit counts of one tile.  Four LDS histograms per wave (lane & 3 picks
+// one) quarter the atomic conflicts of skewed digits (R-MAT's high column
+// bits); the copies are summed at the end.
+constexpr int kHistCopies = 4;
+
 static __global__ __launch_bounds__(kRadixThreads) void radix_histogram(const uint32_t *__restrict__ keys, int64_t N,
                                                                   int shift, uint32_t mask,
                                                                   uint32_t *__restrict__ counts, int64_t tiles)
 {
-    __shared__ uint32_t hist[kRadixWaves][kRadixBins];
-    const int t = threadIdx.x, w = t / kWave, lane = lane_id();
-    for (int j = t; j < kRadixWaves * kRadixBins; j += kRadixThreads) (&hist[0][0])[j] = 0;
+    __shared__ uint32_t hist[kRadixWaves * kHistCopies][kRadixBins];
+    const int t = threadIdx.x, w0 = t / kWave, lane = lane_id();
+    const int w = w0 * kHistCopies + (lane & (kHistCopies - 1));  // this lane's histogram copy
+    for (int j = t; j < kRadixWaves * kHistCopies * kRadixBins; j += kRadixThreads) (&hist[0][0])[j] = 0;
     __syncthreads();
     const int64_t tile0 = (int64_t)blockIdx.x * kRadixTile;
     if (tile0 + kRadixTile <= N && ((uintptr_t)keys & 15u) == 0) {
         // whole tile: counting ignores order, so each lane takes 16-byte loads
-        const uint4 *k4 = reinterpret_cast<const uint4 *>(keys + tile0 + (int64_t)w * kRadixWaveSpan);
+        const uint4 *k4 = reinterpret_cast<const uint4 *>(keys + tile0 + (int64_t)w0 * kRadixWaveSpan);
         uint4 v[kRadixItems / 4];
 #pragma unroll
         for (int q = 0; q < kRadixItems / 4; ++q) v[q] = k4[q * kWave + lane];
@@ -79,7 +85,7 @@ static __global__ __launch_bounds__(kRadixThreads) void radix_histogram(const ui
     } else {
 #pragma unroll
         for (int i = 0; i < kRadixItems; ++i) {
-            int64_t idx = radix_index(blockIdx.x, w, i, lane);
+            int64_t idx = radix_index(blockIdx.x, w0, i, lane);
             if (idx < N) atomicAdd(&hist[w][(keys[idx] >> shift) & mask], 1u);
         }
     }
@@ -87,7 +93,7 @@ static __global__ __launch_bounds__(kRadixThreads) void radix_histogram(const ui
     if (t < kRadixBins) {
         uint32_t c = 0;
 #pragma unroll
-        for (int i = 0; i < kRadixWaves; ++i) c += hist[i][t];
+        for (int i = 0; i < kRadixWaves * kHistCopies; ++i) c += hist[i][t];
         counts[(int64_t)blockIdx.x * kRadixBins + t] = c;
     }
 }
