@@ -566,7 +566,7 @@ __global__ void k_copy_u32(const uint32_t *__restrict__ a, uint32_t *__restrict_
 // before any store, so their gathers overlap; each row is one wave scan on
 // top of the running sum of the rows before it.
 constexpr int kWItems = 16;
-constexpr int kWBatch = 8;
+constexpr int kWBatch = 16;
 static_assert((int64_t)kWave * kWItems == kPrefixSeg, "one wave per prefix segment");
 
 __global__ __launch_bounds__(kBlock) void k_weights_reduce(const uint64_t *__restrict__ edge,
