@@ -532,8 +532,12 @@ def main():
     slots = 2 * info["m"]
     # algorithmic bytes per launch of the kernels the roofline can name
     alg = {
-        "sample_path": (BYTES_PER_SAMPLE * k, "pm::k_sample<false,"),
-        "sample_centered": (BYTES_PER_SAMPLE * k, "pm::k_sample<true,"),
+        # both samplers whole (draw keys, draw sort, sampling: several kernels)
+        "sample_path": (BYTES_PER_SAMPLE * k, "pm::k_sample"),
+        "sample_centered": (BYTES_PER_SAMPLE * k, "pm::k_sample"),
+        # the sampling kernels over draw-ordered ids
+        "sample_path.sorted": (BYTES_PER_SAMPLE * k, "pm::k_sample_sorted<false>"),
+        "sample_centered.sorted": (BYTES_PER_SAMPLE * k, "pm::k_sample_sorted<true>"),
         # one pass: read key + value, write key + value
         "reverse_sort.scatter": (16 * slots, "pm::radix_scatter"),
         "reverse_sort.histogram": (4 * slots, "pm::radix_histogram"),
@@ -546,11 +550,12 @@ def main():
         "weights.guide": (18 * slots, "pm::k_guide_fill"),
     }
     traffic = load_traffic()
-    multi = {"build_rows"}  # scopes spanning several kernels
+    multi = {"build_rows", "sample_path", "sample_centered"}  # scopes spanning several kernels
     timed = {n: v for n, v in kernels.items() if n in alg and n not in multi}
     dom_name = max(timed, key=lambda n: timed[n]["ms_per_step"])
     roofline = roofline_for(dom_name, kernels[dom_name], alg[dom_name], traffic, copy_gbs)
-    roofline_sampler = roofline_for("sample_path", kernels["sample_path"], alg["sample_path"], traffic, copy_gbs)
+    samp = "sample_path.sorted" if "sample_path.sorted" in kernels else "sample_path"
+    roofline_sampler = roofline_for(samp, kernels[samp], alg[samp], traffic, copy_gbs)
     roofline_all = {n: {"achieved_gbs": alg[n][0] / (kernels[n]["avg_ms"] * 1e-3) / 1e9,
                         "frac": alg[n][0] / (kernels[n]["avg_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
                         "ms_per_step": kernels[n]["ms_per_step"]} for n in alg if n in kernels}
@@ -559,7 +564,7 @@ def main():
     if roofline_sampler["traffic"]:
         lines = roofline_sampler["traffic"] / 128.0 / k
         roofline_sampler["lines_per_sample"] = lines
-        roofline_sampler["lines_per_s"] = lines * k / (kernels["sample_path"]["avg_ms"] * 1e-3)
+        roofline_sampler["lines_per_s"] = lines * k / (kernels[samp]["avg_ms"] * 1e-3)
         roofline_sampler["frac_of_random_ceiling"] = roofline_sampler["lines_per_s"] / gather_per_s
     samp_ms = [kernels[n]["avg_ms"] for n in ("sample_path", "sample_centered") if n in kernels]
 

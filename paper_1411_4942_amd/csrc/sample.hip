@@ -4,6 +4,7 @@
 // over sample ids; per-lane counters, one wave reduction and atomic per class.
 #include "graph.hpp"
 #include "profile.hpp"
+#include "radix.hpp"
 #include "sampler.hpp"
 
 #include <algorithm>
@@ -36,6 +37,13 @@ __global__ __launch_bounds__(kBlock) void k_sample(SamplerView g, uint64_t seed,
 // launch shape of the samplers (pm_set_sampler_shape)
 static std::atomic<int> g_samples_per_lane{1};
 static std::atomic<int> g_blocks_per_cu{4};
+static std::atomic<int> g_draw_order{1};  // draw-ordered sampling for large k (pm_set_sampler_shape)
+
+pm_status set_draw_order(int32_t enabled)
+{
+    g_draw_order.store(enabled ? 1 : 0);
+    return PM_OK;
+}
 
 pm_status set_sampler_shape(int32_t samples_per_lane, int32_t blocks_per_cu)
 {
@@ -71,6 +79,82 @@ int sampler_cu_count(int dev)
     return cache[dev];
 }
 
+// Draw-ordered sampling.  Tallies are sums over sample ids, so the order in
+// which samples run is free: sorting the ids of a chunk by the top
+// kDrawKeyBits bits of their draw r lets neighbouring lanes read neighbouring
+// guide entries, prefix lines, edge records and row-u data (r picks the
+// slot), so a sample touches fewer distinct random lines.  Each sample then
+// redraws its r from its id; tallies equal the unsorted kernel's exactly.
+constexpr int kDrawKeyBits = 24;
+constexpr uint64_t kSortedMinK = 1ull << 20;   // below this the sort costs more than it saves
+constexpr uint64_t kSortedChunk = 1ull << 24;  // samples per sort (bounds the temporaries)
+
+template <bool CENTERED>
+__global__ __launch_bounds__(kBlock) void k_draw_keys(SamplerView g, uint64_t seed, uint64_t first, uint64_t k,
+                                                      int kshift, uint32_t *__restrict__ keys)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += (uint64_t)gridDim.x * blockDim.x)
+        keys[i] = (uint32_t)(draw_bounded(seed, CENTERED ? 1u : 0u, first + i, g.R) >> kshift);
+}
+
+template <bool CENTERED>
+__global__ __launch_bounds__(kBlock) void k_sample_sorted(SamplerView g, uint64_t seed, uint64_t first, uint64_t k,
+                                                          const uint32_t *__restrict__ ids,
+                                                          unsigned long long *__restrict__ tally)
+{
+    uint32_t cnt[PM_NUM_TALLIES];
+#pragma unroll
+    for (int c = 0; c < PM_NUM_TALLIES; ++c) cnt[c] = 0;
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < k; j += (uint64_t)gridDim.x * blockDim.x)
+        tally_add(cnt, sample_class<CENTERED>(g, seed, first + ids[j]));
+    tally_flush(cnt, tally);
+}
+
+static pm_status launch_sorted(const pm_graph *g, const SamplerView &v, bool centered, uint64_t seed,
+                               uint64_t first, uint64_t k, uint64_t *tally, unsigned blocks, hipStream_t s)
+{
+    const int rbits = bits_for(v.R - 1);  // r < R
+    const int kshift = rbits > kDrawKeyBits ? rbits - kDrawKeyBits : 0;
+    const int kbits = rbits - kshift;
+    const uint64_t chunk = std::min<uint64_t>(k, kSortedChunk);
+    Temps tmp(s);
+    uint32_t *kin, *k0, *v0, *k1, *v1;
+    char *scr = nullptr;
+    PM_TRY(tmp.get(&kin, (size_t)chunk));
+    PM_TRY(tmp.get(&k0, (size_t)chunk));
+    PM_TRY(tmp.get(&v0, (size_t)chunk));
+    PM_TRY(tmp.get(&k1, (size_t)chunk));
+    PM_TRY(tmp.get(&v1, (size_t)chunk));
+    PM_TRY(tmp.get(&scr, radix_scratch_bytes((int64_t)chunk)));
+    for (uint64_t c0 = 0; c0 < k; c0 += chunk) {
+        const uint64_t kc = std::min(chunk, k - c0);
+        const unsigned kb = (unsigned)std::min<uint64_t>((kc + kBlock - 1) / kBlock, blocks);
+        {
+            ProfScope pd("draw_keys", s);
+            if (centered)
+                hipLaunchKernelGGL((k_draw_keys<true>), dim3(kb), dim3(kBlock), 0, s, v, seed, first + c0, kc, kshift,
+                                   kin);
+            else
+                hipLaunchKernelGGL((k_draw_keys<false>), dim3(kb), dim3(kBlock), 0, s, v, seed, first + c0, kc, kshift,
+                                   kin);
+            PM_HIP(hipGetLastError());
+        }
+        uint32_t *ks = nullptr, *ids = nullptr;
+        PM_TRY(radix_sort("draw_sort", kin, nullptr, k0, v0, k1, v1, (int64_t)kc, kbits, scr, s, &ks, &ids));
+        {
+            ProfScope pk(centered ? "sample_centered.sorted" : "sample_path.sorted", s);
+            if (centered)
+                hipLaunchKernelGGL((k_sample_sorted<true>), dim3(kb), dim3(kBlock), 0, s, v, seed, first + c0, kc, ids,
+                                   (unsigned long long *)tally);
+            else
+                hipLaunchKernelGGL((k_sample_sorted<false>), dim3(kb), dim3(kBlock), 0, s, v, seed, first + c0, kc,
+                                   ids, (unsigned long long *)tally);
+            PM_HIP(hipGetLastError());
+        }
+    }
+    return PM_OK;
+}
+
 static pm_status launch_sampler(const pm_graph *g, bool centered, uint64_t seed, uint64_t first, uint64_t k,
                                 uint64_t *tally, hipStream_t s)
 {
@@ -81,6 +165,8 @@ static pm_status launch_sampler(const pm_graph *g, bool centered, uint64_t seed,
     const uint64_t cap = (uint64_t)sampler_cu_count(g->device) * (uint64_t)g_blocks_per_cu.load();
     const unsigned blocks = (unsigned)std::max<uint64_t>(1, std::min(want, cap));
     ProfScope prof(centered ? "sample_centered" : "sample_path", s);
+    if (k >= kSortedMinK && v.R > 1 && g_draw_order.load())
+        return launch_sorted(g, v, centered, seed, first, k, tally, (unsigned)cap, s);
     switch (U * 2 + (centered ? 1 : 0)) {
     case 2: launch_k_sample<false, 1>(blocks, s, v, seed, first, k, tally); break;
     case 3: launch_k_sample<true, 1>(blocks, s, v, seed, first, k, tally); break;

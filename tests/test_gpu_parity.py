@@ -290,3 +290,29 @@ def test_cached_device_memory_reuse_across_streams():
         if it == 2:
             torch.cuda.synchronize()
             ps.release_cached_memory()
+
+
+def test_draw_order_does_not_change_tallies():
+    """Draw-ordered sampling (large k) gives the id-order tallies exactly:
+    against the oracle above the threshold, and on against off across
+    several sort chunks."""
+    _say("draw order")
+    off, col = synth.chung_lu(20000, 150000, 2.2, 800.0, 5)
+    og = oracle.Graph(off, col)
+    g = ps.Graph(*_dev(off, col))
+    k = (1 << 20) + 12345
+    try:
+        ps.set_draw_order(True)
+        a = g.count(k, k, seed=3, first_path=7, first_cent=2 ** 33)
+        assert a["tally_path"] == og.sample_path(3, k, 7).tolist()
+        assert a["tally_cent"] == og.sample_centered(3, k, 2 ** 33).tolist()
+        k2 = (1 << 24) * 2 + 777  # three sort chunks, the last one ragged
+        on = g.count(k2, k2, seed=9)
+        ps.set_draw_order(False)
+        b = g.count(k, k, seed=3, first_path=7, first_cent=2 ** 33)
+        off_ = g.count(k2, k2, seed=9)
+    finally:
+        ps.set_draw_order(True)
+    assert a["tally_path"] == b["tally_path"] and a["tally_cent"] == b["tally_cent"]
+    assert on["tally_path"] == off_["tally_path"] and on["tally_cent"] == off_["tally_cent"]
+    g.destroy()
