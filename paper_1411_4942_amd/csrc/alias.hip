@@ -27,6 +27,7 @@
 // sample is then decoded from (s, o) exactly as the main samplers decode it.
 #include "graph.hpp"
 #include "profile.hpp"
+#include "radix.hpp"
 #include "sampler.hpp"
 #include "scan.hpp"
 
@@ -307,6 +308,24 @@ struct DrawStream {
     }
 };
 
+// one alias-drawn sample (the stream's three draws, then the usual decode)
+template <bool CENTERED>
+__device__ __forceinline__ uint32_t alias_sample(const SamplerView &g, const AliasEntry *__restrict__ T, uint64_t N,
+                                                 uint64_t seed, uint64_t id)
+{
+    DrawStream st(seed, CENTERED ? 3u : 2u, id);
+    const uint64_t b = st.bounded(N);
+    const uint64_t x = st.bounded(g.R);
+    const uint4 *q = reinterpret_cast<const uint4 *>(T + b);
+    const uint4 e0 = q[0], e1 = q[1];
+    const uint64_t K = (uint64_t)e0.x | ((uint64_t)e0.y << 32);
+    const bool keep = x < K;
+    const uint32_t s = keep ? (uint32_t)b : e1.z;
+    const uint64_t ws = keep ? ((uint64_t)e0.z | ((uint64_t)e0.w << 32)) : ((uint64_t)e1.x | ((uint64_t)e1.y << 32));
+    const uint64_t o = st.bounded(ws);
+    return sample_decode<CENTERED>(g, s, o, ws);
+}
+
 template <bool CENTERED>
 __global__ __launch_bounds__(kBlock) void k_sample_alias(SamplerView g, const AliasEntry *__restrict__ T, uint64_t N,
                                                          uint64_t seed, uint64_t first, uint64_t k,
@@ -316,20 +335,73 @@ __global__ __launch_bounds__(kBlock) void k_sample_alias(SamplerView g, const Al
 #pragma unroll
     for (int c = 0; c < PM_NUM_TALLIES; ++c) cnt[c] = 0;
     const uint64_t nthreads = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += nthreads) {
-        DrawStream st(seed, CENTERED ? 3u : 2u, first + i);
-        const uint64_t b = st.bounded(N);
-        const uint64_t x = st.bounded(g.R);
-        const uint4 *q = reinterpret_cast<const uint4 *>(T + b);
-        const uint4 e0 = q[0], e1 = q[1];
-        const uint64_t K = (uint64_t)e0.x | ((uint64_t)e0.y << 32);
-        const bool keep = x < K;
-        const uint32_t s = keep ? (uint32_t)b : e1.z;
-        const uint64_t ws = keep ? ((uint64_t)e0.z | ((uint64_t)e0.w << 32)) : ((uint64_t)e1.x | ((uint64_t)e1.y << 32));
-        const uint64_t o = st.bounded(ws);
-        tally_add(cnt, sample_decode<CENTERED>(g, s, o, ws));
-    }
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += nthreads)
+        tally_add(cnt, alias_sample<CENTERED>(g, T, N, seed, first + i));
     tally_flush(cnt, tally);
+}
+
+// Draw order for the alias draw: the key is the top bits of the bucket b (the
+// stream's first draw), so neighbouring lanes read neighbouring table lines.
+template <bool CENTERED>
+__global__ __launch_bounds__(kBlock) void k_alias_keys(uint64_t N, uint64_t seed, uint64_t first, uint64_t k,
+                                                       int kshift, uint32_t *__restrict__ keys)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += (uint64_t)gridDim.x * blockDim.x) {
+        DrawStream st(seed, CENTERED ? 3u : 2u, first + i);
+        keys[i] = (uint32_t)(st.bounded(N) >> kshift);
+    }
+}
+
+template <bool CENTERED>
+__global__ __launch_bounds__(kBlock) void k_sample_alias_sorted(SamplerView g, const AliasEntry *__restrict__ T,
+                                                                uint64_t N, uint64_t seed, uint64_t first, uint64_t k,
+                                                                const uint32_t *__restrict__ ids,
+                                                                unsigned long long *__restrict__ tally)
+{
+    uint32_t cnt[PM_NUM_TALLIES];
+#pragma unroll
+    for (int c = 0; c < PM_NUM_TALLIES; ++c) cnt[c] = 0;
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < k; j += (uint64_t)gridDim.x * blockDim.x)
+        tally_add(cnt, alias_sample<CENTERED>(g, T, N, seed, first + ids[j]));
+    tally_flush(cnt, tally);
+}
+
+pm_status launch_alias_sorted(const SamplerView &v, const AliasEntry *T, uint64_t N, bool centered, uint64_t seed,
+                              uint64_t first, uint64_t k, uint64_t *tally, unsigned blocks, hipStream_t s)
+{
+    const int nbits = bits_for(N - 1);  // b < N
+    const int kshift = nbits > kDrawKeyBits ? nbits - kDrawKeyBits : 0;
+    const int kbits = nbits - kshift;
+    const uint64_t chunk = std::min<uint64_t>(k, kSortedChunk);
+    Temps tmp(s);
+    uint32_t *kin, *k0, *v0, *k1, *v1;
+    char *scr = nullptr;
+    PM_TRY(tmp.get(&kin, (size_t)chunk));
+    PM_TRY(tmp.get(&k0, (size_t)chunk));
+    PM_TRY(tmp.get(&v0, (size_t)chunk));
+    PM_TRY(tmp.get(&k1, (size_t)chunk));
+    PM_TRY(tmp.get(&v1, (size_t)chunk));
+    PM_TRY(tmp.get(&scr, radix_scratch_bytes((int64_t)chunk)));
+    for (uint64_t c0 = 0; c0 < k; c0 += chunk) {
+        const uint64_t kc = std::min(chunk, k - c0);
+        const unsigned kb = (unsigned)std::min<uint64_t>((kc + kBlock - 1) / kBlock, blocks);
+        if (centered)
+            hipLaunchKernelGGL((k_alias_keys<true>), dim3(kb), dim3(kBlock), 0, s, N, seed, first + c0, kc, kshift, kin);
+        else
+            hipLaunchKernelGGL((k_alias_keys<false>), dim3(kb), dim3(kBlock), 0, s, N, seed, first + c0, kc, kshift,
+                               kin);
+        PM_HIP(hipGetLastError());
+        uint32_t *ks = nullptr, *ids = nullptr;
+        PM_TRY(radix_sort("alias_draw_sort", kin, nullptr, k0, v0, k1, v1, (int64_t)kc, kbits, scr, s, &ks, &ids));
+        if (centered)
+            hipLaunchKernelGGL((k_sample_alias_sorted<true>), dim3(kb), dim3(kBlock), 0, s, v, T, N, seed, first + c0,
+                               kc, ids, (unsigned long long *)tally);
+        else
+            hipLaunchKernelGGL((k_sample_alias_sorted<false>), dim3(kb), dim3(kBlock), 0, s, v, T, N, seed, first + c0,
+                               kc, ids, (unsigned long long *)tally);
+        PM_HIP(hipGetLastError());
+    }
+    return PM_OK;
 }
 
 pm_status launch_alias(const pm_graph *g, bool centered, uint64_t seed, uint64_t first, uint64_t k,
@@ -341,13 +413,16 @@ pm_status launch_alias(const pm_graph *g, bool centered, uint64_t seed, uint64_t
     const uint64_t want = (k + kBlock - 1) / kBlock;
     const uint64_t cap = (uint64_t)sampler_cu_count(g->device) * 4u;
     const unsigned blocks = (unsigned)std::max<uint64_t>(1, std::min(want, cap));
+    const uint64_t N = (uint64_t)g->slots;
     ProfScope prof(centered ? "sample_centered_alias" : "sample_path_alias", s);
+    if (k >= kSortedMinK && N > 1 && draw_order_enabled())
+        return launch_alias_sorted(v, T, N, centered, seed, first, k, tally, (unsigned)cap, s);
     if (centered)
-        hipLaunchKernelGGL((k_sample_alias<true>), dim3(blocks), dim3(kBlock), 0, s, v, T, (uint64_t)g->slots, seed,
-                           first, k, (unsigned long long *)tally);
+        hipLaunchKernelGGL((k_sample_alias<true>), dim3(blocks), dim3(kBlock), 0, s, v, T, N, seed, first, k,
+                           (unsigned long long *)tally);
     else
-        hipLaunchKernelGGL((k_sample_alias<false>), dim3(blocks), dim3(kBlock), 0, s, v, T, (uint64_t)g->slots, seed,
-                           first, k, (unsigned long long *)tally);
+        hipLaunchKernelGGL((k_sample_alias<false>), dim3(blocks), dim3(kBlock), 0, s, v, T, N, seed, first, k,
+                           (unsigned long long *)tally);
     PM_HIP(hipGetLastError());
     return PM_OK;
 }

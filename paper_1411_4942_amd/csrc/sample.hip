@@ -39,6 +39,8 @@ static std::atomic<int> g_samples_per_lane{1};
 static std::atomic<int> g_blocks_per_cu{4};
 static std::atomic<int> g_draw_order{1};  // draw-ordered sampling for large k (pm_set_sampler_shape)
 
+bool draw_order_enabled() { return g_draw_order.load() != 0; }
+
 pm_status set_draw_order(int32_t enabled)
 {
     g_draw_order.store(enabled ? 1 : 0);
@@ -85,9 +87,6 @@ int sampler_cu_count(int dev)
 // guide entries, prefix lines, edge records and row-u data (r picks the
 // slot), so a sample touches fewer distinct random lines.  Each sample then
 // redraws its r from its id; tallies equal the unsorted kernel's exactly.
-constexpr int kDrawKeyBits = 24;
-constexpr uint64_t kSortedMinK = 1ull << 20;   // below this the sort costs more than it saves
-constexpr uint64_t kSortedChunk = 1ull << 24;  // samples per sort (bounds the temporaries)
 
 template <bool CENTERED>
 __global__ __launch_bounds__(kBlock) void k_draw_keys(SamplerView g, uint64_t seed, uint64_t first, uint64_t k,

@@ -135,6 +135,15 @@ __device__ __forceinline__ uint32_t sample_class(const SamplerView &g, uint64_t 
     return sample_decode<CENTERED>(g, s, r - below, CENTERED ? g.P[s] - p_prev : 0ull);
 }
 
+// Draw-ordered sampling (pm_count, pm_sample_async, pm_count_alias): for at
+// least kSortedMinK samples, ids are sorted in chunks of kSortedChunk by the
+// top kDrawKeyBits bits of their first draw before they run.
+constexpr int kDrawKeyBits = 24;
+constexpr uint64_t kSortedMinK = 1ull << 20;   // below this the sort costs more than it saves
+constexpr uint64_t kSortedChunk = 1ull << 24;  // samples per sort (bounds the temporaries)
+
+bool draw_order_enabled();
+
 __device__ __forceinline__ void tally_add(uint32_t (&cnt)[PM_NUM_TALLIES], uint32_t cls)
 {
 #pragma unroll

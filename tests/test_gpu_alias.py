@@ -139,3 +139,25 @@ def test_alias_full_size_agrees_with_main_draw():
         assert abs(a["est"][i] - m["est"][i]) <= half, (i, a["est"][i], m["est"][i], half)
     g.destroy()
     torch.cuda.empty_cache()
+
+
+def test_alias_draw_order_does_not_change_tallies():
+    """Draw-ordered alias sampling (ids sorted by their bucket) gives the
+    id-order tallies: against the oracle above the threshold, on against off."""
+    _say("alias draw order")
+    off, col = synth.chung_lu(20000, 150000, 2.2, 800.0, 5)
+    og = oracle.Graph(off, col)
+    g = ps.Graph(*_dev(off, col))
+    g.build_alias()
+    k = (1 << 20) + 4321
+    try:
+        ps.set_draw_order(True)
+        a = g.count_alias(k, k, seed=4, first_path=11, first_cent=2 ** 34)
+        ps.set_draw_order(False)
+        b = g.count_alias(k, k, seed=4, first_path=11, first_cent=2 ** 34)
+    finally:
+        ps.set_draw_order(True)
+    assert a["tally_path"] == b["tally_path"] and a["tally_cent"] == b["tally_cent"]
+    assert a["tally_path"] == og.sample_path_alias(4, k, 11).tolist()
+    assert a["tally_cent"] == og.sample_centered_alias(4, k, 2 ** 34).tolist()
+    g.destroy()
