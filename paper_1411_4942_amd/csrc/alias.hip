@@ -415,7 +415,7 @@ pm_status launch_alias(const pm_graph *g, bool centered, uint64_t seed, uint64_t
     const unsigned blocks = (unsigned)std::max<uint64_t>(1, std::min(want, cap));
     const uint64_t N = (uint64_t)g->slots;
     ProfScope prof(centered ? "sample_centered_alias" : "sample_path_alias", s);
-    if (k >= kSortedMinK && N > 1 && draw_order_enabled())
+    if (k >= draw_order_min() && N > 1 && draw_order_enabled())
         return launch_alias_sorted(v, T, N, centered, seed, first, k, tally, (unsigned)cap, s);
     if (centered)
         hipLaunchKernelGGL((k_sample_alias<true>), dim3(blocks), dim3(kBlock), 0, s, v, T, N, seed, first, k,

@@ -37,13 +37,16 @@ __global__ __launch_bounds__(kBlock) void k_sample(SamplerView g, uint64_t seed,
 // launch shape of the samplers (pm_set_sampler_shape)
 static std::atomic<int> g_samples_per_lane{1};
 static std::atomic<int> g_blocks_per_cu{4};
-static std::atomic<int> g_draw_order{1};  // draw-ordered sampling for large k (pm_set_sampler_shape)
+static std::atomic<int> g_draw_order{1};  // draw-ordered sampling for large k (pm_set_draw_order)
+static std::atomic<uint64_t> g_draw_min{kSortedMinDefault};
 
 bool draw_order_enabled() { return g_draw_order.load() != 0; }
+uint64_t draw_order_min() { return g_draw_min.load(); }
 
-pm_status set_draw_order(int32_t enabled)
+pm_status set_draw_order(int32_t enabled, uint64_t min_samples)
 {
     g_draw_order.store(enabled ? 1 : 0);
+    g_draw_min.store(min_samples ? min_samples : kSortedMinDefault);
     return PM_OK;
 }
 
@@ -164,7 +167,7 @@ static pm_status launch_sampler(const pm_graph *g, bool centered, uint64_t seed,
     const uint64_t cap = (uint64_t)sampler_cu_count(g->device) * (uint64_t)g_blocks_per_cu.load();
     const unsigned blocks = (unsigned)std::max<uint64_t>(1, std::min(want, cap));
     ProfScope prof(centered ? "sample_centered" : "sample_path", s);
-    if (k >= kSortedMinK && v.R > 1 && g_draw_order.load())
+    if (k >= draw_order_min() && v.R > 1 && draw_order_enabled())
         return launch_sorted(g, v, centered, seed, first, k, tally, (unsigned)cap, s);
     switch (U * 2 + (centered ? 1 : 0)) {
     case 2: launch_k_sample<false, 1>(blocks, s, v, seed, first, k, tally); break;

@@ -136,13 +136,16 @@ __device__ __forceinline__ uint32_t sample_class(const SamplerView &g, uint64_t 
 }
 
 // Draw-ordered sampling (pm_count, pm_sample_async, pm_count_alias): for at
-// least kSortedMinK samples, ids are sorted in chunks of kSortedChunk by the
-// top kDrawKeyBits bits of their first draw before they run.
+// least draw_order_min() samples of one sampler, ids are sorted in chunks of
+// kSortedChunk by the top kDrawKeyBits bits of their first draw before they
+// run.  Measured on MI355X the sort pays from about 4M samples, for graphs
+// from 1e6 to 2.4e8 slots alike (its fixed cost dominates below).
 constexpr int kDrawKeyBits = 24;
-constexpr uint64_t kSortedMinK = 1ull << 20;   // below this the sort costs more than it saves
+constexpr uint64_t kSortedMinDefault = 6ull << 20;
 constexpr uint64_t kSortedChunk = 1ull << 24;  // samples per sort (bounds the temporaries)
 
 bool draw_order_enabled();
+uint64_t draw_order_min();
 
 __device__ __forceinline__ void tally_add(uint32_t (&cnt)[PM_NUM_TALLIES], uint32_t cls)
 {

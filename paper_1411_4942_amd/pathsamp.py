@@ -132,7 +132,7 @@ _SIGNATURES = {
     "pm_device_copy": (ctypes.c_int32, [_P, _P, ctypes.c_uint64, _P]),
     "pm_device_gather": (ctypes.c_int32, [_P, ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint64, _P]),
     "pm_set_sampler_shape": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32]),
-    "pm_set_draw_order": (ctypes.c_int32, [ctypes.c_int32]),
+    "pm_set_draw_order": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_uint64]),
     "pm_release_cached_memory": (ctypes.c_int32, []),
     "pm_profile_enable": (ctypes.c_int32, [ctypes.c_int32]),
     "pm_profile_read": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
@@ -533,9 +533,10 @@ def samples_for_error(rel_err: float, delta: float, alpha: float) -> int:
     return int(k.value)
 
 
-def set_draw_order(enabled: bool):
-    """pm_set_draw_order: sort large sample batches by their draws first."""
-    _check(lib().pm_set_draw_order(1 if enabled else 0), "pm_set_draw_order")
+def set_draw_order(enabled: bool, min_samples: int = 0):
+    """pm_set_draw_order: sort sample batches of at least min_samples (0: the
+    default) by their draws first."""
+    _check(lib().pm_set_draw_order(1 if enabled else 0, min_samples), "pm_set_draw_order")
 
 
 def set_sampler_shape(samples_per_lane: int, blocks_per_cu: int):

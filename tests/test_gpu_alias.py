@@ -151,12 +151,12 @@ def test_alias_draw_order_does_not_change_tallies():
     g.build_alias()
     k = (1 << 20) + 4321
     try:
-        ps.set_draw_order(True)
+        ps.set_draw_order(True, 1 << 20)
         a = g.count_alias(k, k, seed=4, first_path=11, first_cent=2 ** 34)
         ps.set_draw_order(False)
         b = g.count_alias(k, k, seed=4, first_path=11, first_cent=2 ** 34)
     finally:
-        ps.set_draw_order(True)
+        ps.set_draw_order(True, 0)
     assert a["tally_path"] == b["tally_path"] and a["tally_cent"] == b["tally_cent"]
     assert a["tally_path"] == og.sample_path_alias(4, k, 11).tolist()
     assert a["tally_cent"] == og.sample_centered_alias(4, k, 2 ** 34).tolist()

@@ -302,7 +302,7 @@ def test_draw_order_does_not_change_tallies():
     g = ps.Graph(*_dev(off, col))
     k = (1 << 20) + 12345
     try:
-        ps.set_draw_order(True)
+        ps.set_draw_order(True, 1 << 20)
         a = g.count(k, k, seed=3, first_path=7, first_cent=2 ** 33)
         assert a["tally_path"] == og.sample_path(3, k, 7).tolist()
         assert a["tally_cent"] == og.sample_centered(3, k, 2 ** 33).tolist()
@@ -312,7 +312,7 @@ def test_draw_order_does_not_change_tallies():
         b = g.count(k, k, seed=3, first_path=7, first_cent=2 ** 33)
         off_ = g.count(k2, k2, seed=9)
     finally:
-        ps.set_draw_order(True)
+        ps.set_draw_order(True, 0)
     assert a["tally_path"] == b["tally_path"] and a["tally_cent"] == b["tally_cent"]
     assert on["tally_path"] == off_["tally_path"] and on["tally_cent"] == off_["tally_cent"]
     g.destroy()
