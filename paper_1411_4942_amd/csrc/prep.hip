@@ -592,9 +592,10 @@ __global__ __launch_bounds__(kBlock) void k_weights_reduce(const uint64_t *__res
         for (int i = 0; i < kWBatch; ++i) {
             const int64_t idx = wave_base + (int64_t)(h + i) * kWave + lane;
             const bool ok = idx < N;
-            e[i] = ok ? edge[idx] : 0ull;
-            r[i] = ok ? rev[idx] : 0u;
-            k2[i] = ok ? key2[idx] : 0u;
+            // read once here: keep them out of the cache the gathers use
+            e[i] = ok ? __builtin_nontemporal_load(edge + idx) : 0ull;
+            r[i] = ok ? __builtin_nontemporal_load(rev + idx) : 0u;
+            k2[i] = ok ? __builtin_nontemporal_load(key2 + idx) : 0u;
         }
         uint32_t ou[kWBatch], ou1[kWBatch], ov[kWBatch], ov1[kWBatch];
 #pragma unroll
@@ -622,8 +623,10 @@ __global__ __launch_bounds__(kBlock) void k_weights_reduce(const uint64_t *__res
             }
             const U64x2 incl = wave_inclusive(U64x2{tau, lam}, PairSumOp(), U64x2{0, 0});
             if (idx < N) {
-                p_tau[idx] = carry.a + incl.a;
-                p_lam[idx] = carry.b + incl.b;
+                // whole 512-byte rows per instruction, read again only by the
+                // guide pass and the samplers: stream them past the cache
+                __builtin_nontemporal_store(carry.a + incl.a, p_tau + idx);
+                __builtin_nontemporal_store(carry.b + incl.b, p_lam + idx);
             }
             carry = PairSumOp()(carry, shfl_idx_t(incl, kWave - 1));
         }
