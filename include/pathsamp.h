@@ -403,8 +403,9 @@ pm_status pm_samples_for_error(double rel_err, double delta, double alpha, uint6
 
 /* Launch shape of the two sampling kernels for this process: samples each
  * lane advances together (1, 2 or 4; more loads in flight per lane, more
- * registers) and resident blocks per compute unit (1..64).  Tallies do not
- * depend on the shape.  Default 1 and 4 (the fastest measured on MI355X). */
+ * registers; id-order launches only) and resident blocks per compute unit
+ * (1..64; also the grid of the draw-ordered launches).  Tallies do not depend
+ * on the shape.  Default 1 and 4 (the fastest measured on MI355X). */
 pm_status pm_set_sampler_shape(int32_t samples_per_lane, int32_t blocks_per_cu);
 
 /* Draw-ordered sampling in pm_count, pm_sample_async and pm_count_alias
