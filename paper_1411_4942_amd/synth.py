@@ -87,8 +87,13 @@ def path(n: int):
 
 
 def star(leaves: int):
-    """K_{1,leaves}, hub is vertex 0."""
-    return csr_from_edges(leaves + 1, np.zeros(leaves, np.int64), np.arange(1, leaves + 1))
+    """K_{1,leaves}, hub is vertex 0 (the CSR written out directly)."""
+    off = np.empty(leaves + 2, dtype=np.int64)
+    off[0] = 0
+    off[1:] = np.arange(leaves, 2 * leaves + 1, dtype=np.int64)
+    col = np.zeros(2 * leaves, dtype=np.int32)
+    col[:leaves] = np.arange(1, leaves + 1, dtype=np.int32)
+    return off, col
 
 
 def complete_bipartite(p: int, q: int):
