@@ -323,6 +323,55 @@ def alias_leg(off, col, k: int, stream, reps: int = 3) -> dict:
     }
 
 
+def accuracy_leg(ks=(2500, 5000, 10000, 20000, 35000), seeds: int = 50) -> dict:
+    """The paper's accuracy experiments (Section 6) on synthetic stand-ins:
+    exact counts from pm_exact_counts, then `seeds` runs per k (batched, Philox
+    seeds 1000 k + s): mean relative error of each motif's estimate, the
+    fraction of runs whose 99% bars hold the exact count, and at the largest k
+    the centered estimator's error against Algorithm 2's basic one."""
+    import numpy as np
+    import torch
+
+    from paper_1411_4942_amd import pathsamp as ps
+    from paper_1411_4942_amd import synth
+
+    graphs = [("Chung-Lu n=1e6, m=1e7, gamma 2.3, w_max 5000, seed 1",
+               lambda: synth.chung_lu_torch(1_000_000, 10_000_000, 2.3, 5000.0, 1, device="cuda")),
+              ("R-MAT scale 16 (0.57, 0.19, 0.19, 0.05), edge factor 16, seed 1",
+               lambda: synth.rmat_torch(16, 16.0, seed=1))]
+    out = []
+    for name, make in graphs:
+        off, col = make()
+        g = ps.Graph(off, col)
+        del off, col
+        C = g.exact()["C"]
+        per_k = []
+        for k in ks:
+            params = [ps.make_params(k, k, seed=1000 * k + s) for s in range(seeds)]
+            runs = ps.count_batch([g] * seeds, params)
+            per_k.append({
+                "k": k,
+                "mean_rel_err": [float(np.mean([abs(r["est"][i] - C[i]) / C[i] for r in runs])) if C[i] else None
+                                 for i in range(1, 7)],
+                "bar_coverage": [float(np.mean([r["lo"][i] - 1e-6 <= C[i] <= r["hi"][i] + 1e-6 for r in runs]))
+                                 for i in range(1, 7)],
+            })
+        last = runs
+        out.append({
+            "graph": name,
+            "exact_counts": C[1:],
+            "runs_per_k": seeds,
+            "by_k": per_k,
+            "centered_vs_basic_rel_err_k35000": [
+                (float(np.mean([abs(r["est"][i] - C[i]) / C[i] for r in last])),
+                 float(np.mean([abs(r["est_basic"][i] - C[i]) / C[i] for r in last]))) if C[i] else None
+                for i in (4, 5, 6)],
+        })
+        g.destroy()
+        torch.cuda.empty_cache()
+    return {"graphs": out, "delta": 0.01}
+
+
 def exact_leg(k: int = 2_000_000) -> dict:
     """Sampling against exact enumeration on Chung-Lu n = 1e6, m = 1e7
     (exponent 2.3, weight cap 5000, seed 1): times and the estimates' error."""
@@ -474,6 +523,7 @@ def main():
     ap.add_argument("--no-ingest", action="store_true")
     ap.add_argument("--no-exact", action="store_true")
     ap.add_argument("--no-alias", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--batch-graphs", type=int, default=256)
     ap.add_argument("--batch-k", type=int, default=200_000)
@@ -606,6 +656,12 @@ def main():
         out["alias"] = alias_leg(off, col, k, stream)
         log(f"[bench] alias: tables {out['alias']['table_build_ms']:.2f} ms, sampling "
             f"{out['alias']['alias_sampling_ms']:.2f} ms vs {out['alias']['main_sampling_ms']:.2f} ms")
+    if not args.no_accuracy:
+        log("[bench] accuracy leg ...")
+        out["accuracy"] = accuracy_leg()
+        for gr in out["accuracy"]["graphs"]:
+            log(f"[bench] accuracy {gr['graph'][:20]}: k=35000 mean rel err "
+                + ", ".join(f"{x:.3f}" if x is not None else "-" for x in gr["by_k"][-1]["mean_rel_err"]))
     if not args.no_exact:
         log("[bench] exact leg ...")
         out["exact"] = exact_leg()
