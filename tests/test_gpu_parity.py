@@ -208,6 +208,62 @@ def test_invalid_graphs_are_rejected(name, off, col, status):
     assert e.value.status == status
 
 
+def _run_starts(d):
+    """Input positions inside a row of degree d where the row kernel takes a
+    slot's predecessor from somewhere other than the lane below: the first
+    slots of items (lane 0) and of waves' runs, and the last slot.  Wave w
+    of a W-wave block owns slots [w per, (w + 1) per), per = ceil(d / 64W) 64,
+    item i of it the 64 slots from w per + 64 i."""
+    bounds = [16, 64, 256, 1024, 4096, 8192, 16384, 32768]
+    waves = [0, 1, 1, 1, 4, 8, 16, 16]  # lanes, then a wave or a block per row
+    W = next(w for b, w in zip(bounds, waves) if d <= b)
+    pos = {1, d - 1}
+    if W:
+        per = -(-d // (64 * W)) * 64
+        runs = [w * per for w in range(1, W) if w * per < d]
+        pos |= {64, 128} | set(runs[:1] + runs[-1:]) | {r + 64 for r in runs[-1:]}
+    return sorted(j for j in pos if 1 <= j < d)
+
+
+def test_row_checks_in_every_size_class():
+    """Planted input errors in rows of every size class are reported: an
+    unsorted pair and a repeated column at each place where the row kernel
+    gets a slot's predecessor from another item, wave or the run before, a
+    self-loop, an out-of-range and a negative column."""
+    degrees = [10, 50, 200, 700, 3000, 6000, 12000, 20000]
+    off, col = synth.hubs(degrees, 25000, 30000, 13)
+    n = len(off) - 1
+    g = ps.Graph(*_dev(off, col))  # the clean graph builds
+    g.destroy()
+    texts = {"order": "not strictly ascending", "loop": "self-loop", "range": "not a vertex id"}
+    for u, d in enumerate(degrees):
+        a = int(off[u])
+        plants = []
+        for j in _run_starts(d):
+            c = col.copy()
+            c[a + j - 1], c[a + j] = c[a + j], c[a + j - 1]
+            plants.append(("swap", j, c, "order"))
+            c = col.copy()
+            c[a + j] = c[a + j - 1]
+            plants.append(("repeat", j, c, "order"))
+        c = col.copy()
+        c[a + d // 2] = u
+        plants.append(("loop", d // 2, c, "loop"))
+        c = col.copy()
+        c[a + d - 1] = n + 3
+        plants.append(("range", d - 1, c, "range"))
+        c = col.copy()
+        c[a] = -3
+        plants.append(("negative", 0, c, "range"))
+        for kind, j, c, want in plants:
+            _say("row check", d, kind, j)
+            assert oracle.validate(off, c) != oracle.OK
+            with pytest.raises(ps.PathSampError) as e:
+                ps.Graph(*_dev(off, c))
+            assert e.value.status == ps.PM_EGRAPH, (d, kind, j)
+            assert texts[want] in str(e.value), (d, kind, j, str(e.value))
+
+
 def test_argument_errors():
     off, col = synth.complete(5)
     g = ps.Graph(*_dev(off, col))
