@@ -116,7 +116,9 @@ struct OffOut {
 // mapped to rank[c]; rows are sorted where they are built, by size class:
 //   degree <= 16          one lane per row, a sorting network in registers
 //   16 < degree <= 64     one wave per row, a sorting network across lanes
-//   64 < degree <= 16384  one block per row sized to the class (64, 64, 256,
+//   64 < degree <= 256    one wave per row, a sorting network on 2 (up to
+//                         128) or 4 keys per lane
+//   256 < degree <= 16384 one block per row sized to the class (64, 256,
 //                         512 or 1024 threads), stable LSD radix sort in LDS
 //   16384 < degree <= 32768  one block of 1024 per row, keys in registers
 //                         and one LDS exchange buffer (128 KB)
@@ -234,6 +236,88 @@ __global__ __launch_bounds__(kBlock) void k_rows_wave(const int64_t *__restrict_
             v = (up == low) ? (v < o ? v : o) : (v < o ? o : v);
         }
     if (lane < d) emit_slot(off_new[i] + lane, (uint32_t)i, v, col, edge, ladder1);
+    if (err) atomicOr(&st->err, err);
+}
+
+// One compare step of a bitonic network on 64 * ITEMS keys held as element
+// e = lane * ITEMS + j in k[j]: pairs (e, e ^ M), the lower element keeping
+// the smaller key.  M below ITEMS pairs registers of one lane; otherwise
+// lanes lane ^ (M / ITEMS) exchange register j ^ (M % ITEMS), and the lane
+// whose bit for M's top bit is clear holds the lower element.  M is a
+// compile-time constant after unrolling.
+template <int ITEMS>
+__device__ __forceinline__ void bitonic_step(uint32_t (&k)[ITEMS], int lane, int M)
+{
+    if (M < ITEMS) {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j)
+            if ((j ^ M) > j) cswap(k[j], k[j ^ M]);
+    } else {
+        const int ml = M / ITEMS, mj = M % ITEMS;
+        const int top = 1 << (31 - __builtin_clz((unsigned)ml));
+        const bool lower = (lane & top) == 0;
+        uint32_t o[ITEMS];
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) o[j] = __shfl_xor(k[j ^ mj], ml, kWave);
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) k[j] = lower ? (k[j] < o[j] ? k[j] : o[j]) : (k[j] < o[j] ? o[j] : k[j]);
+    }
+}
+
+// rows [r0, r1) with 64 < degree <= 64 * ITEMS, one wave each: bitonic
+// sorting network on 64 * ITEMS keys in registers (absent entries are
+// 0xFFFFFFFF and sort last), element e = lane * ITEMS + j so that the
+// frequent short strides stay inside a lane.  Each merge stage of size 2^p
+// opens with the mirror step (e against e ^ (2^p - 1)) and continues with
+// half-cleaners (e against e ^ 2^q for q = p - 2 .. 0).
+template <int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_rows_bitonic(const int64_t *__restrict__ off_in,
+                                                         const int32_t *__restrict__ col_in,
+                                                         const uint32_t *__restrict__ order,
+                                                         const int32_t *__restrict__ rank,
+                                                         const uint32_t *__restrict__ off_new, int64_t n, int64_t r0,
+                                                         int64_t r1, uint32_t *__restrict__ col,
+                                                         uint64_t *__restrict__ edge, uint32_t *__restrict__ ladder1,
+                                                         PrepStats *st)
+{
+    static_assert(ITEMS == 2 || ITEMS == 4, "two or four keys per lane");
+    constexpr int LOG_N = ITEMS == 2 ? 7 : 8;
+    const int64_t i = r0 + ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    if (i >= r1) return;  // whole waves leave together
+    const int lane = lane_id();
+    const int64_t u = order[i], a = off_in[u];
+    const int d = (int)(off_in[u + 1] - a);  // <= 64 * ITEMS by the class bounds
+    int32_t c[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int e = lane * ITEMS + j;
+        c[j] = e < d ? col_in[a + e] : 0;
+    }
+    const int32_t left = __shfl_up(c[ITEMS - 1], 1, kWave);  // element lane * ITEMS - 1
+    uint32_t err = 0, k[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int e = lane * ITEMS + j;
+        k[j] = 0xFFFFFFFFu;
+        if (e < d) {
+            const int64_t cv = c[j];
+            const int64_t prev = j > 0 ? (int64_t)c[j - 1] : (lane > 0 ? (int64_t)left : -1);
+            err |= slot_checks(cv, u, prev, n);
+            k[j] = (cv >= 0 && cv < n) ? (uint32_t)rank[cv] : 0u;
+        }
+    }
+#pragma unroll
+    for (int p = 1; p <= LOG_N; ++p) {
+        bitonic_step<ITEMS>(k, lane, (1 << p) - 1);
+#pragma unroll
+        for (int q = p - 2; q >= 0; --q) bitonic_step<ITEMS>(k, lane, 1 << q);
+    }
+    const int64_t dst = off_new[i];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int e = lane * ITEMS + j;
+        if (e < d) emit_slot(dst + e, (uint32_t)i, k[j], col, edge, ladder1);
+    }
     if (err) atomicOr(&st->err, err);
 }
 
@@ -518,11 +602,11 @@ __global__ __launch_bounds__(kBlock) void k_rows_tail_emit(const uint32_t *__res
 // first row of each size class (degrees ascend along the new order): cls[c]
 // = first row with degree > {0, 16, 64, 256, 1024, 4096, 8192, 16384,
 // 32768}[c]; cls[9] = the first slot of row cls[8]
-constexpr int kRowClasses = 9;
+constexpr int kRowClasses = 10;
 __global__ void k_row_classes(const uint32_t *__restrict__ deg, const uint32_t *__restrict__ off, int64_t n,
                               int64_t *cls)
 {
-    const uint32_t bound[kRowClasses] = {0u, 16u, 64u, 256u, 1024u, 4096u, 8192u, 16384u, 32768u};
+    const uint32_t bound[kRowClasses] = {0u, 16u, 64u, 128u, 256u, 1024u, 4096u, 8192u, 16384u, 32768u};
     const int c = threadIdx.x;
     if (c >= kRowClasses) return;
     int64_t lo = 0, hi = n;
@@ -1078,34 +1162,41 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
                                col_in, order, g->rank, g->off, n, cls[1], cls[2], g->col, g->edge, ladder1, st);
         }
         if (cls[3] > cls[2]) {
-            ProfScope pc("build_rows.b256", s);
-            hipLaunchKernelGGL((k_rows_block<64, 4>), dim3((unsigned)(cls[3] - cls[2])), dim3(64), 0, s, off_in,
-                               col_in, order, g->rank, g->off, n, cls[2], vbits, g->col, g->edge, ladder1, st);
+            ProfScope pc("build_rows.w128", s);
+            hipLaunchKernelGGL(k_rows_bitonic<2>, dim3((unsigned)((cls[3] - cls[2] + 3) / 4)), dim3(kBlock), 0, s,
+                               off_in, col_in, order, g->rank, g->off, n, cls[2], cls[3], g->col, g->edge, ladder1,
+                               st);
         }
         if (cls[4] > cls[3]) {
-            ProfScope pc("build_rows.b1024", s);
-            hipLaunchKernelGGL((k_rows_block<64, 16>), dim3((unsigned)(cls[4] - cls[3])), dim3(64), 0, s, off_in,
-                               col_in, order, g->rank, g->off, n, cls[3], vbits, g->col, g->edge, ladder1, st);
+            ProfScope pc("build_rows.w256", s);
+            hipLaunchKernelGGL(k_rows_bitonic<4>, dim3((unsigned)((cls[4] - cls[3] + 3) / 4)), dim3(kBlock), 0, s,
+                               off_in, col_in, order, g->rank, g->off, n, cls[3], cls[4], g->col, g->edge, ladder1,
+                               st);
         }
         if (cls[5] > cls[4]) {
-            ProfScope pc("build_rows.b4096", s);
-            hipLaunchKernelGGL((k_rows_block<256, 16>), dim3((unsigned)(cls[5] - cls[4])), dim3(256), 0, s, off_in,
+            ProfScope pc("build_rows.b1024", s);
+            hipLaunchKernelGGL((k_rows_block<64, 16>), dim3((unsigned)(cls[5] - cls[4])), dim3(64), 0, s, off_in,
                                col_in, order, g->rank, g->off, n, cls[4], vbits, g->col, g->edge, ladder1, st);
         }
         if (cls[6] > cls[5]) {
-            ProfScope pc("build_rows.b8192", s);
-            hipLaunchKernelGGL((k_rows_block<512, 16>), dim3((unsigned)(cls[6] - cls[5])), dim3(512), 0, s, off_in,
+            ProfScope pc("build_rows.b4096", s);
+            hipLaunchKernelGGL((k_rows_block<256, 16>), dim3((unsigned)(cls[6] - cls[5])), dim3(256), 0, s, off_in,
                                col_in, order, g->rank, g->off, n, cls[5], vbits, g->col, g->edge, ladder1, st);
         }
         if (cls[7] > cls[6]) {
-            ProfScope pc("build_rows.b16384", s);
-            hipLaunchKernelGGL((k_rows_block<1024, 16>), dim3((unsigned)(cls[7] - cls[6])), dim3(1024), 0, s, off_in,
+            ProfScope pc("build_rows.b8192", s);
+            hipLaunchKernelGGL((k_rows_block<512, 16>), dim3((unsigned)(cls[7] - cls[6])), dim3(512), 0, s, off_in,
                                col_in, order, g->rank, g->off, n, cls[6], vbits, g->col, g->edge, ladder1, st);
         }
         if (cls[8] > cls[7]) {
+            ProfScope pc("build_rows.b16384", s);
+            hipLaunchKernelGGL((k_rows_block<1024, 16>), dim3((unsigned)(cls[8] - cls[7])), dim3(1024), 0, s, off_in,
+                               col_in, order, g->rank, g->off, n, cls[7], vbits, g->col, g->edge, ladder1, st);
+        }
+        if (cls[9] > cls[8]) {
             ProfScope pc("build_rows.b32768", s);
-            hipLaunchKernelGGL((k_rows_block_reg<1024, 32>), dim3((unsigned)(cls[8] - cls[7])), dim3(1024), 0, s,
-                               off_in, col_in, order, g->rank, g->off, n, cls[7], vbits, g->col, g->edge, ladder1, st);
+            hipLaunchKernelGGL((k_rows_block_reg<1024, 32>), dim3((unsigned)(cls[9] - cls[8])), dim3(1024), 0, s,
+                               off_in, col_in, order, g->rank, g->off, n, cls[8], vbits, g->col, g->edge, ladder1, st);
         }
         PM_HIP(hipGetLastError());
         const int64_t T = slots - cls[kRowClasses];

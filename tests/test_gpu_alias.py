@@ -43,7 +43,7 @@ GRAPHS = [
     ("chunglu_3k", lambda: synth.chung_lu(3000, 20000, 2.2, 300.0, 3)),
     ("rmat_s12", lambda: synth.rmat(12, 16, seed=2)),
     ("er_tiles", lambda: synth.erdos_renyi(9000, 70000, 4)),
-    ("hub_classes", lambda: synth.hubs([16, 17, 64, 65, 256, 257, 1024, 1025, 4096, 4097, 8192, 8193, 16384,
+    ("hub_classes", lambda: synth.hubs([16, 17, 64, 65, 128, 129, 256, 257, 1024, 1025, 4096, 4097, 8192, 8193, 16384,
                                         16385, 32768, 32769, 70001], 100000, 150000, 9)),
 ]
 

@@ -54,7 +54,7 @@ def _graphs():
     gs.append(("er_tiles", synth.erdos_renyi(9000, 70000, 4)))  # > several scan/radix tiles, ragged tail
     # rows on both sides of every row-build size-class bound (16 .. 32768) and
     # above it (the global hub sort)
-    gs.append(("hub_classes", synth.hubs([16, 17, 64, 65, 256, 257, 1024, 1025, 4096, 4097, 8192, 8193, 16384,
+    gs.append(("hub_classes", synth.hubs([16, 17, 64, 65, 128, 129, 256, 257, 1024, 1025, 4096, 4097, 8192, 8193, 16384,
                                           16385, 32768, 32769, 70001], 100000, 150000, 9)))
     return gs
 
@@ -210,18 +210,19 @@ def test_invalid_graphs_are_rejected(name, off, col, status):
 
 def _run_starts(d):
     """Input positions inside a row of degree d where the row kernel takes a
-    slot's predecessor from somewhere other than the lane below: the first
-    slots of items (lane 0) and of waves' runs, and the last slot.  Wave w
-    of a W-wave block owns slots [w per, (w + 1) per), per = ceil(d / 64W) 64,
-    item i of it the 64 slots from w per + 64 i."""
-    bounds = [16, 64, 256, 1024, 4096, 8192, 16384, 32768]
-    waves = [0, 1, 1, 1, 4, 8, 16, 16]  # lanes, then a wave or a block per row
+    slot's predecessor from somewhere other than the register or lane just
+    below: up to 256, slot e is register e % I of lane e // I (I = 1, 2 or 4
+    keys per lane), so lane starts; above, wave w of a W-wave block owns
+    slots [w per, (w + 1) per), per = ceil(d / 64W) 64, item i of it the 64
+    slots from w per + 64 i, so item and run starts.  Plus the last slot."""
+    bounds = [16, 64, 128, 256, 1024, 4096, 8192, 16384, 32768]
+    waves = [0, 0, 0, 0, 1, 4, 8, 16, 16]  # lane and wave networks, then a block per row
     W = next(w for b, w in zip(bounds, waves) if d <= b)
-    pos = {1, d - 1}
+    pos = {1, 2, 3, 4, 5, 64, 128, d - 1}
     if W:
         per = -(-d // (64 * W)) * 64
         runs = [w * per for w in range(1, W) if w * per < d]
-        pos |= {64, 128} | set(runs[:1] + runs[-1:]) | {r + 64 for r in runs[-1:]}
+        pos |= set(runs[:1] + runs[-1:]) | {r + 64 for r in runs[-1:]}
     return sorted(j for j in pos if 1 <= j < d)
 
 
@@ -230,7 +231,7 @@ def test_row_checks_in_every_size_class():
     unsorted pair and a repeated column at each place where the row kernel
     gets a slot's predecessor from another item, wave or the run before, a
     self-loop, an out-of-range and a negative column."""
-    degrees = [10, 50, 200, 700, 3000, 6000, 12000, 20000]
+    degrees = [10, 50, 100, 200, 700, 3000, 6000, 12000, 20000]
     off, col = synth.hubs(degrees, 25000, 30000, 13)
     n = len(off) - 1
     g = ps.Graph(*_dev(off, col))  # the clean graph builds
