@@ -461,6 +461,15 @@ typedef struct {
 pm_status pm_profile_enable(int32_t on);
 pm_status pm_profile_read(pm_profile_entry *out, int32_t capacity, int32_t *count);
 
+/* Restrict the recording to the named scopes: `names` is a comma-separated
+ * list of kernel names as pm_profile_read reports them (e.g.
+ * "reverse_sort.scatter,sample_path"); null or "" records every scope again.
+ * The selection stays until the next call and does not clear the totals.
+ * Each recorded scope adds two event records between kernels on its stream,
+ * so timing a few scopes perturbs the timed work less than timing all.
+ * Always PM_OK. */
+pm_status pm_profile_select(const char *names);
+
 const char *pm_status_string(pm_status s);
 const char *pm_last_error(void);
 

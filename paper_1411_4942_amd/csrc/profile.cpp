@@ -5,6 +5,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -27,7 +28,9 @@ struct Totals {
 };
 
 std::atomic<bool> g_on{false};
+std::atomic<bool> g_all{true};  // no selection: every scope is recorded
 std::mutex g_mu;
+std::set<std::string> g_selected;
 std::vector<Pending> g_pending;
 std::map<std::string, Totals> g_totals;
 
@@ -53,6 +56,10 @@ bool profiling() { return g_on.load(std::memory_order_relaxed); }
 ProfScope::ProfScope(const char *name, hipStream_t s) : name_(name), s_(s)
 {
     if (!profiling()) return;
+    if (!g_all.load(std::memory_order_relaxed)) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (!g_selected.count(name_)) return;
+    }
     if (hipEventCreate(&a_) != hipSuccess || hipEventCreate(&b_) != hipSuccess) {
         a_ = b_ = nullptr;
         return;
@@ -78,6 +85,22 @@ pm_status pm_profile_enable(int32_t on)
     pm::resolve_locked();
     pm::g_totals.clear();
     pm::g_on.store(on != 0);
+    return PM_OK;
+}
+
+pm_status pm_profile_select(const char *names)
+{
+    std::lock_guard<std::mutex> lk(pm::g_mu);
+    pm::g_selected.clear();
+    const std::string all = names ? names : "";
+    size_t a = 0;
+    while (a <= all.size()) {
+        size_t b = all.find(',', a);
+        if (b == std::string::npos) b = all.size();
+        if (b > a) pm::g_selected.insert(all.substr(a, b - a));
+        a = b + 1;
+    }
+    pm::g_all.store(pm::g_selected.empty());
     return PM_OK;
 }
 

@@ -136,6 +136,7 @@ _SIGNATURES = {
     "pm_release_cached_memory": (ctypes.c_int32, []),
     "pm_profile_enable": (ctypes.c_int32, [ctypes.c_int32]),
     "pm_profile_read": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "pm_profile_select": (ctypes.c_int32, [ctypes.c_char_p]),
     "pm_batch_create": (ctypes.c_int32, [_P, _P, ctypes.c_int32, _P, _P, ctypes.POINTER(_P)]),
     "pm_batch_set_params": (ctypes.c_int32, [_P, _P]),
     "pm_batch_run": (ctypes.c_int32, [_P, _P, _P]),
@@ -574,6 +575,13 @@ def device_gather(table, count: int, seed: int = 1, stream=None):
 def profile_enable(on: bool = True):
     """Clear per-kernel totals and switch HIP-event timing on or off."""
     _check(lib().pm_profile_enable(1 if on else 0), "pm_profile_enable")
+
+
+def profile_select(names=None):
+    """Record only the named scopes (an iterable of kernel names as
+    profile_read reports them); None or empty records every scope."""
+    joined = ",".join(names) if names else ""
+    _check(lib().pm_profile_select(joined.encode()), "pm_profile_select")
 
 
 def profile_read() -> dict:

@@ -373,3 +373,28 @@ def test_draw_order_does_not_change_tallies():
     assert a["tally_path"] == b["tally_path"] and a["tally_cent"] == b["tally_cent"]
     assert on["tally_path"] == off_["tally_path"] and on["tally_cent"] == off_["tally_cent"]
     g.destroy()
+
+
+def test_profile_select_restricts_recording():
+    """With a selection only the named scopes are timed; with none, every
+    scope of a graph build and a count is."""
+    off, col = synth.chung_lu(3000, 20000, 2.2, 300.0, 3)
+    try:
+        ps.profile_select(["sample_path", "degrees"])
+        ps.profile_enable(True)
+        g = ps.Graph(*_dev(off, col))
+        g.count(5000, 5000, seed=1)
+        g.destroy()
+        got = ps.profile_read()
+        assert set(got) == {"sample_path", "degrees"}, got
+        assert got["sample_path"][0] == 1 and got["degrees"][0] == 1
+        ps.profile_select(None)
+        ps.profile_enable(True)  # clears the totals
+        g = ps.Graph(*_dev(off, col))
+        g.count(5000, 5000, seed=1)
+        g.destroy()
+        got = ps.profile_read()
+        assert {"sample_path", "sample_centered", "degrees", "build_rows", "reverse_sort.scatter"} <= set(got), got
+    finally:
+        ps.profile_enable(False)
+        ps.profile_select(None)
