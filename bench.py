@@ -535,8 +535,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build runs on single-GPU boxes "
-              "(the multi-GPU sharding is described, not built).", file=sys.stderr)
+        print("bench.py measures one GPU only: the multi-GPU sharding of the path is "
+              "designed, not built.", file=sys.stderr)
         sys.exit(2)
 
     import torch
