@@ -211,10 +211,11 @@ def test_invalid_graphs_are_rejected(name, off, col, status):
 def _run_starts(d):
     """Input positions inside a row of degree d where the row kernel takes a
     slot's predecessor from somewhere other than the register or lane just
-    below: up to 256, slot e is register e % I of lane e // I (I = 1, 2 or 4
-    keys per lane), so lane starts; above, wave w of a W-wave block owns
-    slots [w per, (w + 1) per), per = ceil(d / 64W) 64, item i of it the 64
-    slots from w per + 64 i, so item and run starts.  Plus the last slot."""
+    below.  Up to 16 one lane holds the whole row; up to 256 slot e is
+    register e % I of lane e // I (I = 1, 2 or 4 keys per lane), so lane
+    starts; above, wave w of a W-wave block owns slots [w per, (w + 1) per),
+    per = ceil(d / 64W) 64, item i of it the 64 slots from w per + 64 i, so
+    item and run starts.  Plus the last slot."""
     bounds = [16, 64, 128, 256, 1024, 4096, 8192, 16384, 32768]
     waves = [0, 0, 0, 0, 1, 4, 8, 16, 16]  # lane and wave networks, then a block per row
     W = next(w for b, w in zip(bounds, waves) if d <= b)
