@@ -435,10 +435,10 @@ __device__ uint32_t *block_radix_lds(uint32_t *a, uint32_t *b, int nk, int bits,
 
 // The same sort with the keys held in registers between passes (key[i] is
 // item i as above) and one LDS buffer for the exchange: twice the capacity in
-// the same LDS.  No ranks are kept: after the counts become digit offsets,
-// the scatter ranks every key again on top of them, which yields its output
-// position directly.  buf holds THREADS * ITEMS words; the sorted keys end
-// in its first nk (it must hold the input keys when bits == 0).
+// the same LDS.  Each key's rank among its wave's keys of the same digit is
+// kept in a register from the counting step to the scatter.  buf holds
+// THREADS * ITEMS words; the sorted keys end in its first nk (it must hold
+// the input keys when bits == 0).
 template <int THREADS, int ITEMS>
 __device__ __forceinline__ void block_radix_reg(uint32_t (&key)[ITEMS], uint32_t *buf, int nk, int bits,
                                                 uint32_t *s_cnt, uint32_t *s_tot)
@@ -451,26 +451,26 @@ __device__ __forceinline__ void block_radix_reg(uint32_t (&key)[ITEMS], uint32_t
         const uint32_t mask = (bits - shift >= 8) ? 0xFFu : ((1u << (bits - shift)) - 1u);
         for (int j = t; j < W * 256; j += THREADS) s_cnt[j] = 0;
         __syncthreads();
+        uint32_t rank[ITEMS];
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
-            if (i * kWave >= per) break;  // wave-uniform
             const int idx = w * per + i * kWave + lane;
             const bool ok = idx < nk;
-            (void)wave_digit_rank(ok ? (key[i] >> shift) & mask : 0u, ok, lt_mask, s_cnt + w * 256);
+            // an opaque copy: the ballots of later items would otherwise be
+            // computed ahead and held in registers
+            uint32_t k = key[i];
+            asm volatile("" : "+v"(k));
+            // every item ranks (absent ones count nothing), so that each
+            // register of rank is written on every path
+            rank[i] = i * kWave < per ? wave_digit_rank(ok ? (k >> shift) & mask : 0u, ok, lt_mask, s_cnt + w * 256)
+                                      : 0u;
         }
         __syncthreads();
         block_digit_offsets<THREADS>(s_cnt, s_tot);
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
-            if (i * kWave >= per) break;
             const int idx = w * per + i * kWave + lane;
-            const bool ok = idx < nk;
-            // an opaque copy: the compiler would otherwise keep the counting
-            // loop's masks of all ITEMS keys alive to reuse them here
-            uint32_t k = key[i];
-            asm volatile("" : "+v"(k));
-            const uint32_t pos = wave_digit_rank(ok ? (k >> shift) & mask : 0u, ok, lt_mask, s_cnt + w * 256);
-            if (ok) buf[pos] = k;
+            if (i * kWave < per && idx < nk) buf[s_cnt[w * 256 + ((key[i] >> shift) & mask)] + rank[i]] = key[i];
         }
         __syncthreads();
         if (shift + 8 >= bits) break;  // the result stays in buf
