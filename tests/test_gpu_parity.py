@@ -56,6 +56,10 @@ def _graphs():
     # above it (the global hub sort)
     gs.append(("hub_classes", synth.hubs([16, 17, 64, 65, 128, 129, 256, 257, 1024, 1025, 4096, 4097, 8192, 8193, 16384,
                                           16385, 32768, 32769, 70001], 100000, 150000, 9)))
+    # rows of every length from 1 to 300: each padding of the lane, wave and
+    # register networks (classes up to 16, 64, 128 and 256) and the first
+    # block sizes above them
+    gs.append(("every_small_degree", synth.hubs(list(range(1, 301)), 3000, 4000, 17)))
     return gs
 
 
