@@ -41,13 +41,6 @@ def test_library_exports_every_declared_symbol():
     assert not [n for n in _declared_functions() if n not in ps._SIGNATURES]
 
 
-def test_status_strings():
-    L = ps.lib()
-    assert L.pm_status_string(ps.PM_OK) == b"PM_OK"
-    assert L.pm_status_string(ps.PM_EGRAPH) == b"PM_EGRAPH"
-    assert L.pm_status_string(ps.PM_EOVERFLOW) == b"PM_EOVERFLOW"
-
-
 def _random_case(rng):
     k_path = int(rng.integers(1, 10 ** int(rng.integers(1, 8))))
     k_cent = int(rng.integers(1, 10 ** int(rng.integers(1, 8))))
@@ -120,3 +113,14 @@ def test_samples_for_error():
             assert 0.8 * approx < k < 1.2 * approx
     with pytest.raises(ps.PathSampError):
         ps.samples_for_error(0.0, 0.01, 0.5)
+
+
+def test_status_strings():
+    """Every status code has its name; unknown codes say so (no device call)."""
+    L = ps.lib()
+    names = {ps.PM_OK: b"PM_OK", ps.PM_EINVAL: b"PM_EINVAL", ps.PM_EGRAPH: b"PM_EGRAPH",
+             ps.PM_EOVERFLOW: b"PM_EOVERFLOW", ps.PM_ENOMEM: b"PM_ENOMEM", ps.PM_EDEVICE: b"PM_EDEVICE",
+             ps.PM_EBUSY: b"PM_EBUSY", ps.PM_ECANCELED: b"PM_ECANCELED"}
+    for code, name in names.items():
+        assert L.pm_status_string(code) == name
+    assert L.pm_status_string(-99) == b"PM_UNKNOWN"
