@@ -123,7 +123,8 @@ struct OffOut {
 //   16384 < degree <= 32768  one block of 1024 per row, keys in registers
 //                         and one LDS exchange buffer (128 KB)
 //   degree > 32768        (the few hub rows, all at the end of the order)
-//                         placed unsorted, then two global radix sorts
+//                         chunks of 32768 sorted as the class above, then
+//                         merged within each row
 // Each class writes col, edge = row | col << 32, and ladder level 1 (every
 // 32nd column) at the row's final slots, and checks the input row (column
 // range, self-loop, strictly ascending).
@@ -556,52 +557,207 @@ __global__ __launch_bounds__(THREADS) void k_rows_block_reg(const int64_t *__res
     if (err) atomicOr(&st->err, err);
 }
 
-// hub rows [r0, n), slot-parallel (their degrees run to the hundreds of
-// thousands): tail slot q = off_new[r0] + q finds its row by binary search
-// over the hub rows' offsets, then places (key = new column, value = row - r0)
-__global__ __launch_bounds__(kBlock) void k_rows_tail_place(const int64_t *__restrict__ off_in,
-                                                            const int32_t *__restrict__ col_in,
-                                                            const uint32_t *__restrict__ order,
-                                                            const int32_t *__restrict__ rank,
-                                                            const uint32_t *__restrict__ off_new, int64_t n,
-                                                            int64_t r0, int64_t T, uint32_t *__restrict__ key,
-                                                            uint32_t *__restrict__ val, PrepStats *st)
+// Hub rows [r0, n) (degree > 32768: a few rows of up to hundreds of
+// thousands of slots).  Hub-local position q stands for slot off_new[r0] + q.
+// Each row is cut into chunks of kHubChunk slots; one block sorts a chunk
+// with the keys in registers (as the largest block class), then rounds of
+// pairwise merges, the run length doubling each round, leave one sorted run
+// per row, which the round that finishes it writes to the row's slots.
+constexpr int kHubChunk = 32768;                // 1024 threads x 32 keys
+constexpr int kMergeTile = 2048;                // merged slots per block and round
+constexpr int kMergePer = kMergeTile / kBlock;  // per thread
+
+// hstart[h] = off_new[r0 + h] - off_new[r0] for h in [0, H] (H = n - r0 hub
+// rows) and cstart[h] = the chunks of hub rows before h (cstart[H] = all of
+// them); one block
+__global__ __launch_bounds__(kBlock) void k_hub_layout(const uint32_t *__restrict__ off_new, int64_t r0, int64_t H,
+                                                       uint32_t *__restrict__ hstart, uint32_t *__restrict__ cstart)
 {
-    const int64_t p0 = off_new[r0];
-    uint32_t err = 0;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < T; q += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t p = p0 + q;
-        int64_t lo = r0, hi = n;  // last row i in [r0, n) with off_new[i] <= p
-        while (hi - lo > 1) {
-            const int64_t mid = (lo + hi) >> 1;
-            if (off_new[mid] <= p)
-                lo = mid;
-            else
-                hi = mid;
+    __shared__ uint32_t s_sum[kBlock];
+    const int t = threadIdx.x;
+    const int64_t per = (H + kBlock - 1) / kBlock;
+    const int64_t h0 = t * per < H ? t * per : H, h1 = h0 + per < H ? h0 + per : H;
+    const uint32_t p0 = off_new[r0];
+    uint32_t local = 0;
+    for (int64_t h = h0; h < h1; ++h)
+        local += (off_new[r0 + h + 1] - off_new[r0 + h] + kHubChunk - 1) / kHubChunk;
+    s_sum[t] = local;
+    __syncthreads();
+    if (t == 0) {  // exclusive scan of the 256 thread sums
+        uint32_t run = 0;
+        for (int i = 0; i < kBlock; ++i) {
+            const uint32_t x = s_sum[i];
+            s_sum[i] = run;
+            run += x;
         }
-        const int64_t i = lo, u = order[i], j = p - off_new[i], a = off_in[u];
-        const int64_t c = col_in[a + j];
-        const int64_t prev = j > 0 ? (int64_t)col_in[a + j - 1] : -1;
-        err |= slot_checks(c, u, prev, n);
-        key[q] = (c >= 0 && c < n) ? (uint32_t)rank[c] : 0u;
-        val[q] = (uint32_t)(i - r0);
     }
+    __syncthreads();
+    uint32_t run = s_sum[t];
+    for (int64_t h = h0; h < h1; ++h) {
+        hstart[h] = off_new[r0 + h] - p0;
+        cstart[h] = run;
+        run += (off_new[r0 + h + 1] - off_new[r0 + h] + kHubChunk - 1) / kHubChunk;
+    }
+    if (t == kBlock - 1) {  // the last thread's range ends at H
+        hstart[H] = off_new[r0 + H] - p0;
+        cstart[H] = run;
+    }
+}
+
+// last h in [0, H) with start[h] <= x (start[0] = 0 <= x)
+__device__ __forceinline__ int64_t hub_of(const uint32_t *__restrict__ start, int64_t H, uint64_t x)
+{
+    int64_t lo = 0, hi = H;
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (start[mid] <= x)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// chunk blockIdx.x of the hub rows sorted into out (hub-local positions);
+// the grid is an upper bound on the chunk count, blocks beyond it leave
+template <int THREADS, int ITEMS>
+__global__ __launch_bounds__(THREADS) void k_hub_chunks(const int64_t *__restrict__ off_in,
+                                                        const int32_t *__restrict__ col_in,
+                                                        const uint32_t *__restrict__ order,
+                                                        const int32_t *__restrict__ rank,
+                                                        const uint32_t *__restrict__ hstart,
+                                                        const uint32_t *__restrict__ cstart, int64_t n, int64_t r0,
+                                                        int64_t H, int bits, uint32_t *__restrict__ out, PrepStats *st)
+{
+    constexpr int CAP = THREADS * ITEMS;
+    static_assert(CAP == kHubChunk, "one chunk per block");
+    __shared__ uint32_t s_buf[CAP];
+    __shared__ uint32_t s_cnt[(THREADS / kWave) * 256];
+    __shared__ uint32_t s_tot[256];
+    const uint32_t b = blockIdx.x;
+    if (b >= cstart[H]) return;  // the whole block
+    const int64_t h = hub_of(cstart, H, b), i = r0 + h, u = order[i], a = off_in[u];
+    const int64_t d = off_in[u + 1] - a, c0 = (int64_t)(b - cstart[h]) * CAP;
+    const int nk = (int)(d - c0 < CAP ? d - c0 : CAP);
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    uint32_t err = 0;
+    for (int j = threadIdx.x; j < nk; j += THREADS) {
+        const int64_t jj = c0 + j;
+        const int64_t c = col_in[a + jj];
+        const int64_t prev = jj > 0 ? (int64_t)col_in[a + jj - 1] : -1;  // across chunk edges too
+        err |= slot_checks(c, u, prev, n);
+        s_buf[j] = (c >= 0 && c < n) ? (uint32_t)rank[c] : 0u;
+    }
+    __syncthreads();
+    uint32_t key[ITEMS];
+    // unconditional reads, as in block_radix_reg; a hub row means n > 32768,
+    // so bits >= 16 and the sort makes passes
+    const int per = keys_per_wave<THREADS>(nk);
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) key[it] = s_buf[w * per + it * kWave + lane];
+    // the first pass writes s_buf only after its own barriers
+    block_radix_reg<THREADS, ITEMS>(key, s_buf, nk, bits, s_cnt, s_tot);
+    const int64_t q0 = hstart[h] + c0;
+    for (int j = threadIdx.x; j < nk; j += THREADS) out[q0 + j] = s_buf[j];
     if (err) atomicOr(&st->err, err);
 }
 
-// the sorted hub rows (rows relative to r0, columns) to their final slots
-__global__ __launch_bounds__(kBlock) void k_rows_tail_emit(const uint32_t *__restrict__ row_rel,
-                                                           const uint32_t *__restrict__ cols_sorted, int64_t T,
-                                                           int64_t r0, int64_t p0, uint32_t *__restrict__ col,
-                                                           uint64_t *__restrict__ edge, uint32_t *__restrict__ ladder1)
+// One merge round over the hub rows still in several runs (degree > L; the
+// hub rows ascend by degree, so they form a suffix).  In each such row the
+// sorted runs [s, s + L) and [s + L, s + 2L) (s = the row's start plus a
+// multiple of 2L, both cut at the row's end) become one sorted run; a run
+// without a partner is carried over.  A row of degree <= 2L is finished by
+// this round and goes straight to its final slots (col, edge, ladder);
+// longer rows go to out for the next round.  Block b writes positions
+// [qA + b kMergeTile, qA + (b + 1) kMergeTile) of [qA, T), qA the first
+// active row's start, piece by piece where the tile crosses a pair's end:
+// merge-path splits of the piece's first and last output, both inputs
+// staged in LDS, kMergePer outputs per thread from its own split merged
+// into LDS, then written out coalesced.  Ties
+// take the first run (rows hold distinct keys unless the input fails its
+// checks).  The grid covers [0, T); blocks past the end leave.
+__global__ __launch_bounds__(kBlock) void k_hub_merge(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
+                                                      int64_t T, const uint32_t *__restrict__ hstart, int64_t H,
+                                                      int64_t L, int64_t r0, int64_t p0, uint32_t *__restrict__ col,
+                                                      uint64_t *__restrict__ edge, uint32_t *__restrict__ ladder1)
 {
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < T; q += (int64_t)gridDim.x * blockDim.x)
-        emit_slot(p0 + q, (uint32_t)(r0 + row_rel[q]), cols_sorted[q], col, edge, ladder1);
+    __shared__ uint32_t s_a[kMergeTile], s_b[kMergeTile], s_out[kMergeTile];
+    __shared__ int64_t s_split[2];
+    const int t = threadIdx.x;
+    // the first hub row of degree > L (H when none)
+    int64_t lo0 = 0, hi0 = H;
+    while (lo0 < hi0) {
+        const int64_t mid = (lo0 + hi0) >> 1;
+        if ((int64_t)(hstart[mid + 1] - hstart[mid]) > L)
+            hi0 = mid;
+        else
+            lo0 = mid + 1;
+    }
+    int64_t q = (int64_t)hstart[lo0] + (int64_t)blockIdx.x * kMergeTile;
+    if (q >= T) return;  // the whole block
+    const int64_t tile_end = q + kMergeTile < T ? q + kMergeTile : T;
+    while (q < tile_end) {  // block-uniform
+        const int64_t h = hub_of(hstart, H, (uint64_t)q);
+        const int64_t rs = hstart[h], re = hstart[h + 1];
+        const int64_t ps = rs + (q - rs) / (2 * L) * (2 * L);
+        const int64_t am = ps + L < re ? ps + L : re, pe = ps + 2 * L < re ? ps + 2 * L : re;
+        const int64_t la = am - ps, lb = pe - am;
+        const int64_t seg_end = tile_end < pe ? tile_end : pe;  // > q: ps <= q < pe
+        const bool last = re - rs <= 2 * L;
+        const uint32_t *A = in + ps, *B = in + am;
+        if (t < 2) {
+            // outputs [0, k) of the pair take A[0, i) and B[0, k - i): the
+            // first i with A[i] > B[k - 1 - i]
+            const int64_t k = (t ? seg_end : q) - ps;
+            int64_t lo = k - lb > 0 ? k - lb : 0, hi = k < la ? k : la;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (A[mid] <= B[k - 1 - mid])
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            s_split[t] = lo;
+        }
+        __syncthreads();
+        const int64_t i0 = s_split[0], i1 = s_split[1];
+        const int64_t j0 = (q - ps) - i0, j1 = (seg_end - ps) - i1;
+        const int na = (int)(i1 - i0), nb = (int)(j1 - j0);  // na + nb = seg_end - q <= kMergeTile
+        for (int x = t; x < na; x += kBlock) s_a[x] = A[i0 + x];
+        for (int x = t; x < nb; x += kBlock) s_b[x] = B[j0 + x];
+        __syncthreads();
+        const int o0 = t * kMergePer, n_out = na + nb;
+        if (o0 < n_out) {
+            int lo = o0 - nb > 0 ? o0 - nb : 0, hi = o0 < na ? o0 : na;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (s_a[mid] <= s_b[o0 - 1 - mid])
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            int ia = lo, ib = o0 - lo;
+            const int o1 = o0 + kMergePer < n_out ? o0 + kMergePer : n_out;
+            for (int o = o0; o < o1; ++o) {
+                const bool take_a = ib >= nb || (ia < na && s_a[ia] <= s_b[ib]);
+                s_out[o] = take_a ? s_a[ia++] : s_b[ib++];
+            }
+        }
+        __syncthreads();
+        for (int o = t; o < n_out; o += kBlock) {
+            if (last)
+                emit_slot(p0 + q + o, (uint32_t)(r0 + h), s_out[o], col, edge, ladder1);
+            else
+                out[q + o] = s_out[o];
+        }
+        __syncthreads();  // s_a, s_b, s_out and s_split are refilled for the next piece
+        q = seg_end;
+    }
 }
 
 // first row of each size class (degrees ascend along the new order): cls[c]
-// = first row with degree > {0, 16, 64, 256, 1024, 4096, 8192, 16384,
-// 32768}[c]; cls[9] = the first slot of row cls[8]
+// = first row with degree > {0, 16, 64, 128, 256, 1024, 4096, 8192, 16384,
+// 32768}[c]; cls[10] = the first slot of row cls[9]
 constexpr int kRowClasses = 10;
 __global__ void k_row_classes(const uint32_t *__restrict__ deg, const uint32_t *__restrict__ off, int64_t n,
                               int64_t *cls)
@@ -1201,27 +1357,28 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
         PM_HIP(hipGetLastError());
         const int64_t T = slots - cls[kRowClasses];
         if (T > 0) {
-            // hub rows: placed unsorted, then stably by column and by row
-            uint32_t *tk0, *tv0, *tk1, *tv1, *tk2, *tv2;
-            PM_TRY(tmp.get(&tk0, (size_t)T));
-            PM_TRY(tmp.get(&tv0, (size_t)T));
-            PM_TRY(tmp.get(&tk1, (size_t)T));
-            PM_TRY(tmp.get(&tv1, (size_t)T));
-            PM_TRY(tmp.get(&tk2, (size_t)T));
-            PM_TRY(tmp.get(&tv2, (size_t)T));
-            const int64_t rt = cls[kRowClasses - 1];
+            // hub rows: chunks sorted in blocks, then merged within each row
+            const int64_t rt = cls[kRowClasses - 1], H = n - rt;
+            uint32_t *run0, *run1, *hstart, *cstart;
+            PM_TRY(tmp.get(&run0, (size_t)T));
+            PM_TRY(tmp.get(&run1, (size_t)T));
+            PM_TRY(tmp.get(&hstart, (size_t)H + 1));
+            PM_TRY(tmp.get(&cstart, (size_t)H + 1));
             ProfScope pt("build_rows.hubs", s);
-            hipLaunchKernelGGL(k_rows_tail_place, dim3(grid_for(T, kBlock, 1 << 22)), dim3(kBlock), 0, s, off_in,
-                               col_in, order, g->rank, g->off, n, rt, T, tk0, tv0, st);
+            hipLaunchKernelGGL(k_hub_layout, dim3(1), dim3(kBlock), 0, s, g->off, rt, H, hstart, cstart);
+            // each row has at most d / kHubChunk + 1 chunks
+            const int64_t chunk_bound = T / kHubChunk + H;
+            hipLaunchKernelGGL((k_hub_chunks<1024, 32>), dim3((unsigned)chunk_bound), dim3(1024), 0, s, off_in,
+                               col_in, order, g->rank, hstart, cstart, n, rt, H, vbits, run0, st);
             PM_HIP(hipGetLastError());
-            uint32_t *kc, *vr;
-            PM_TRY(radix_sort("hub_sort.col", tk0, tv0, tk1, tv1, tk2, tv2, T, vbits, rscr, s, &kc, &vr));
-            uint32_t *ok_ = (kc == tk1) ? tk2 : tk1, *ov_ = (vr == tv1) ? tv2 : tv1;
-            uint32_t *rr, *cc;
-            PM_TRY(radix_sort("hub_sort.row", vr, kc, ok_, ov_, tk0, tv0, T, bits_for((uint64_t)(n - rt - 1)), rscr,
-                              s, &rr, &cc));
-            hipLaunchKernelGGL(k_rows_tail_emit, dim3(grid_for(T, kBlock, 1 << 22)), dim3(kBlock), 0, s, rr, cc, T,
-                               rt, cls[kRowClasses], g->col, g->edge, ladder1);
+            // every hub row is longer than one chunk, so it takes at least one
+            // round, and the round with L < degree <= 2L finishes it
+            uint32_t *src = run0, *dst = run1;
+            for (int64_t L = kHubChunk; L < (int64_t)g->dmax; L *= 2) {
+                hipLaunchKernelGGL(k_hub_merge, dim3((unsigned)((T + kMergeTile - 1) / kMergeTile)), dim3(kBlock), 0,
+                                   s, src, dst, T, hstart, H, L, rt, cls[kRowClasses], g->col, g->edge, ladder1);
+                std::swap(src, dst);
+            }
             PM_HIP(hipGetLastError());
         }
     }

@@ -219,11 +219,14 @@ def _run_starts(d):
     register e % I of lane e // I (I = 1, 2 or 4 keys per lane), so lane
     starts; above, wave w of a W-wave block owns slots [w per, (w + 1) per),
     per = ceil(d / 64W) 64, item i of it the 64 slots from w per + 64 i, so
-    item and run starts.  Plus the last slot."""
+    item and run starts.  Above 32768 the row is sorted in chunks of 32768
+    slots, so chunk starts.  Plus the last slot."""
     bounds = [16, 64, 128, 256, 1024, 4096, 8192, 16384, 32768]
     waves = [0, 0, 0, 0, 1, 4, 8, 16, 16]  # lane and wave networks, then a block per row
-    W = next(w for b, w in zip(bounds, waves) if d <= b)
     pos = {1, 2, 3, 4, 5, 64, 128, d - 1}
+    if d > 32768:
+        return sorted(pos | set(range(32768, d, 32768)) | {32769})
+    W = next(w for b, w in zip(bounds, waves) if d <= b)
     if W:
         per = -(-d // (64 * W)) * 64
         runs = [w * per for w in range(1, W) if w * per < d]
@@ -236,8 +239,8 @@ def test_row_checks_in_every_size_class():
     unsorted pair and a repeated column at each place where the row kernel
     gets a slot's predecessor from another item, wave or the run before, a
     self-loop, an out-of-range and a negative column."""
-    degrees = [10, 50, 100, 200, 700, 3000, 6000, 12000, 20000]
-    off, col = synth.hubs(degrees, 25000, 30000, 13)
+    degrees = [10, 50, 100, 200, 700, 3000, 6000, 12000, 20000, 40000]
+    off, col = synth.hubs(degrees, 45000, 30000, 13)
     n = len(off) - 1
     g = ps.Graph(*_dev(off, col))  # the clean graph builds
     g.destroy()
