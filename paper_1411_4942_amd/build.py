@@ -8,7 +8,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpathsamp.so")
-SOURCES = ["alloc.cpp", "capi.cpp", "finalize.cpp", "profile.cpp", "prep.hip", "sample.hip", "batch.hip", "server.cpp", "ingest.hip", "exact.hip", "alias.hip"]
+SOURCES = ["alloc.cpp", "capi.cpp", "finalize.cpp", "profile.cpp", "streams.cpp", "prep.hip", "sample.hip", "batch.hip", "server.cpp", "ingest.hip", "exact.hip", "alias.hip"]
 ARCH = "gfx950"
 
 

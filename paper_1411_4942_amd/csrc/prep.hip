@@ -12,6 +12,7 @@
 #include "graph.hpp"
 #include "profile.hpp"
 #include "radix.hpp"
+#include "streams.hpp"
 
 #include <algorithm>
 #include <vector>
@@ -1344,43 +1345,54 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
             hipLaunchKernelGGL((k_rows_block<512, 16>), dim3((unsigned)(cls[7] - cls[6])), dim3(512), 0, s, off_in,
                                col_in, order, g->rank, g->off, n, cls[6], vbits, g->col, g->edge, ladder1, st);
         }
-        if (cls[8] > cls[7]) {
-            ProfScope pc("build_rows.b16384", s);
-            hipLaunchKernelGGL((k_rows_block<1024, 16>), dim3((unsigned)(cls[8] - cls[7])), dim3(1024), 0, s, off_in,
-                               col_in, order, g->rank, g->off, n, cls[7], vbits, g->col, g->edge, ladder1, st);
-        }
-        if (cls[9] > cls[8]) {
-            ProfScope pc("build_rows.b32768", s);
-            hipLaunchKernelGGL((k_rows_block_reg<1024, 32>), dim3((unsigned)(cls[9] - cls[8])), dim3(1024), 0, s,
-                               off_in, col_in, order, g->rank, g->off, n, cls[8], vbits, g->col, g->edge, ladder1, st);
-        }
         PM_HIP(hipGetLastError());
+        // the rows above 8192 (one block of 1024 per row or chunk) run on two
+        // side streams, forked from s after everything above and joined back
         const int64_t T = slots - cls[kRowClasses];
+        const int64_t rt = cls[kRowClasses - 1], H = n - rt;
+        uint32_t *run0 = nullptr, *run1 = nullptr, *hstart = nullptr, *cstart = nullptr;
         if (T > 0) {
-            // hub rows: chunks sorted in blocks, then merged within each row
-            const int64_t rt = cls[kRowClasses - 1], H = n - rt;
-            uint32_t *run0, *run1, *hstart, *cstart;
             PM_TRY(tmp.get(&run0, (size_t)T));
             PM_TRY(tmp.get(&run1, (size_t)T));
             PM_TRY(tmp.get(&hstart, (size_t)H + 1));
             PM_TRY(tmp.get(&cstart, (size_t)H + 1));
-            ProfScope pt("build_rows.hubs", s);
-            hipLaunchKernelGGL(k_hub_layout, dim3(1), dim3(kBlock), 0, s, g->off, rt, H, hstart, cstart);
+        }
+        hipStream_t side[2];
+        PM_HIP(side_streams(side));
+        Fork fork(s, side, 2);
+        PM_HIP(fork.status);
+        if (cls[8] > cls[7]) {
+            ProfScope pc("build_rows.b16384", side[1]);
+            hipLaunchKernelGGL((k_rows_block<1024, 16>), dim3((unsigned)(cls[8] - cls[7])), dim3(1024), 0, side[1],
+                               off_in, col_in, order, g->rank, g->off, n, cls[7], vbits, g->col, g->edge, ladder1, st);
+        }
+        if (cls[9] > cls[8]) {
+            ProfScope pc("build_rows.b32768", side[1]);
+            hipLaunchKernelGGL((k_rows_block_reg<1024, 32>), dim3((unsigned)(cls[9] - cls[8])), dim3(1024), 0,
+                               side[1], off_in, col_in, order, g->rank, g->off, n, cls[8], vbits, g->col, g->edge,
+                               ladder1, st);
+        }
+        if (T > 0) {
+            // hub rows: chunks sorted in blocks, then merged within each row
+            ProfScope pt("build_rows.hubs", side[0]);
+            hipLaunchKernelGGL(k_hub_layout, dim3(1), dim3(kBlock), 0, side[0], g->off, rt, H, hstart, cstart);
             // each row has at most d / kHubChunk + 1 chunks
             const int64_t chunk_bound = T / kHubChunk + H;
-            hipLaunchKernelGGL((k_hub_chunks<1024, 32>), dim3((unsigned)chunk_bound), dim3(1024), 0, s, off_in,
+            hipLaunchKernelGGL((k_hub_chunks<1024, 32>), dim3((unsigned)chunk_bound), dim3(1024), 0, side[0], off_in,
                                col_in, order, g->rank, hstart, cstart, n, rt, H, vbits, run0, st);
-            PM_HIP(hipGetLastError());
             // every hub row is longer than one chunk, so it takes at least one
             // round, and the round with L < degree <= 2L finishes it
             uint32_t *src = run0, *dst = run1;
             for (int64_t L = kHubChunk; L < (int64_t)g->dmax; L *= 2) {
                 hipLaunchKernelGGL(k_hub_merge, dim3((unsigned)((T + kMergeTile - 1) / kMergeTile)), dim3(kBlock), 0,
-                                   s, src, dst, T, hstart, H, L, rt, cls[kRowClasses], g->col, g->edge, ladder1);
+                                   side[0], src, dst, T, hstart, H, L, rt, cls[kRowClasses], g->col, g->edge,
+                                   ladder1);
                 std::swap(src, dst);
             }
-            PM_HIP(hipGetLastError());
         }
+        const hipError_t launched = hipGetLastError();
+        PM_HIP(fork.join());  // before anything can return: the temporaries are released on s
+        PM_HIP(launched);
     }
     tmp.release(vk0);
     tmp.release(vv0);
