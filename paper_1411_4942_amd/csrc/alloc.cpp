@@ -1,15 +1,20 @@
 // Device memory for the library: a caching allocator.
 //
-// A freed block goes to a per-device free list together with an event
-// recorded on the stream that freed it; a later allocation of a similar size
-// takes the block and makes its own stream wait for that event (a device-side
-// wait), so reuse across streams stays ordered.  New blocks come from
-// hipMalloc; when that runs out of memory the free lists are released and the
+// A freed block goes to a per-device free list with the stream that freed it
+// and an event recorded there (one event for a whole batch of frees).  A
+// later allocation of a similar size takes the block.  On the same stream
+// the stream order already puts every new use after the old ones, so no wait
+// is queued.  On another stream the new stream waits for the event (a
+// device-side wait), so reuse across streams stays ordered.  Each event
+// record or wait is a packet the GPU processes between kernels, which is why
+// both are kept to what ordering needs.  New blocks come from hipMalloc;
+// when that runs out of memory the free lists are released and the
 // allocation retried.  pm_release_cached_memory() returns every cached block.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -22,10 +27,20 @@ void set_error(const std::string &msg);
 
 namespace {
 
+// an event shared by the blocks of one batch of frees, destroyed with the last
+struct SharedEvent {
+    hipEvent_t ev = nullptr;
+    ~SharedEvent()
+    {
+        if (ev) (void)hipEventDestroy(ev);
+    }
+};
+
 struct FreeBlock {
     void *ptr;
     size_t bytes;
-    hipEvent_t ready;  // recorded on the freeing stream (null: already idle)
+    hipStream_t stream;                 // the freeing stream
+    std::shared_ptr<SharedEvent> ready; // recorded on it (null: already idle)
 };
 
 struct DeviceCache {
@@ -52,10 +67,7 @@ void release_all_locked(int dev)
 {
     DeviceCache &c = g_cache[dev];
     for (auto &kv : c.free_blocks) {
-        if (kv.second.ready) {
-            (void)hipEventSynchronize(kv.second.ready);
-            (void)hipEventDestroy(kv.second.ready);
-        }
+        if (kv.second.ready) (void)hipEventSynchronize(kv.second.ready->ev);
         (void)hipFree(kv.second.ptr);
     }
     c.free_blocks.clear();
@@ -82,10 +94,10 @@ pm_status dev_alloc(void **p, size_t bytes, hipStream_t s)
         FreeBlock b = it->second;
         c.free_blocks.erase(it);
         c.cached_bytes -= b.bytes;
-        if (b.ready) {
-            e = hipStreamWaitEvent(s, b.ready, 0);
-            (void)hipEventDestroy(b.ready);
+        if (b.ready && b.stream != s) {
+            e = hipStreamWaitEvent(s, b.ready->ev, 0);
             if (e != hipSuccess) {
+                (void)hipEventSynchronize(b.ready->ev);
                 (void)hipFree(b.ptr);
                 set_error(std::string("dev_alloc: hipStreamWaitEvent: ") + hipGetErrorString(e));
                 return PM_EDEVICE;
@@ -112,27 +124,38 @@ pm_status dev_alloc(void **p, size_t bytes, hipStream_t s)
     return PM_OK;
 }
 
-void dev_free(void *p, hipStream_t s)
+void dev_free_batch(void *const *ps, size_t count, hipStream_t s)
 {
-    if (!p) return;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return;
     std::lock_guard<std::mutex> lk(g_mu);
     DeviceCache &c = g_cache[dev];
-    auto it = c.live.find(p);
-    if (it == c.live.end()) return;  // not ours (or freed on another device)
-    FreeBlock b{p, it->second, nullptr};
-    c.live.erase(it);
-    if (hipEventCreateWithFlags(&b.ready, hipEventDisableTiming) != hipSuccess ||
-        hipEventRecord(b.ready, s) != hipSuccess) {
-        // cannot mark the point of release: wait for the stream instead
-        if (b.ready) (void)hipEventDestroy(b.ready);
-        b.ready = nullptr;
-        (void)hipStreamSynchronize(s);
+    std::shared_ptr<SharedEvent> ready;  // one event for the batch, made at its first block of ours
+    bool waited = false;
+    for (size_t i = 0; i < count; ++i) {
+        void *p = ps[i];
+        if (!p) continue;
+        auto it = c.live.find(p);
+        if (it == c.live.end()) continue;  // not ours (or freed on another device)
+        if (!ready && !waited) {
+            auto ev = std::make_shared<SharedEvent>();
+            if (hipEventCreateWithFlags(&ev->ev, hipEventDisableTiming) == hipSuccess &&
+                hipEventRecord(ev->ev, s) == hipSuccess) {
+                ready = ev;
+            } else {
+                // cannot mark the point of release: wait for the stream instead
+                (void)hipStreamSynchronize(s);
+                waited = true;
+            }
+        }
+        FreeBlock b{p, it->second, s, ready};
+        c.live.erase(it);
+        c.free_blocks.emplace(b.bytes, b);
+        c.cached_bytes += b.bytes;
     }
-    c.free_blocks.emplace(b.bytes, b);
-    c.cached_bytes += b.bytes;
 }
+
+void dev_free(void *p, hipStream_t s) { dev_free_batch(&p, 1, s); }
 
 }  // namespace pm
 

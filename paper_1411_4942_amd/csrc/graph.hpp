@@ -96,6 +96,8 @@ inline SamplerView view_of(const pm_graph *g, bool centered)
 // device memory through the stream-ordered allocator
 pm_status dev_alloc(void **p, size_t bytes, hipStream_t s);
 void dev_free(void *p, hipStream_t s);
+// frees every non-null block of ps with one stream-ordered release point
+void dev_free_batch(void *const *ps, size_t count, hipStream_t s);
 
 // Scoped temporaries: every block still held is freed (stream-ordered) when
 // the owner goes out of scope; keep() hands a block over to its new owner.
@@ -103,10 +105,7 @@ struct Temps {
     hipStream_t s;
     std::vector<void *> ptrs;
     explicit Temps(hipStream_t st) : s(st) {}
-    ~Temps()
-    {
-        for (void *p : ptrs) dev_free(p, s);
-    }
+    ~Temps() { dev_free_batch(ptrs.data(), ptrs.size(), s); }
     template <typename T>
     pm_status get(T **p, size_t count)
     {

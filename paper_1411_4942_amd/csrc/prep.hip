@@ -1124,20 +1124,10 @@ const char *err_text(uint32_t e)
 void graph_free(pm_graph *g, hipStream_t s)
 {
     if (!g) return;
-    dev_free(g->off, s);
-    dev_free(g->col, s);
-    dev_free(g->edge, s);
-    dev_free(g->ladder, s);
-    dev_free(g->deg, s);
-    dev_free(g->rank, s);
-    dev_free(g->p_tau, s);
-    dev_free(g->p_lam, s);
-    dev_free(g->seg_tau, s);
-    dev_free(g->seg_lam, s);
-    dev_free(g->guide_tau, s);
-    dev_free(g->guide_lam, s);
-    dev_free(g->alias_tau, s);
-    dev_free(g->alias_lam, s);
+    void *const arrays[] = {g->off,     g->col,     g->edge,      g->ladder,    g->deg,       g->rank,
+                            g->p_tau,   g->p_lam,   g->seg_tau,   g->seg_lam,   g->guide_tau, g->guide_lam,
+                            g->alias_tau, g->alias_lam};
+    dev_free_batch(arrays, sizeof(arrays) / sizeof(arrays[0]), s);
     delete g;
 }
 
