@@ -969,6 +969,10 @@ __global__ __launch_bounds__(kBlock) void k_guide_fill(const uint64_t *__restric
                                                        uint32_t *__restrict__ long_lam, uint32_t long_cap,
                                                        PrepStats *st)
 {
+    // an asymmetric input (found by the weights kernel) leaves the weights
+    // inconsistent, so their bucket ranges could overlap without bound; the
+    // build fails anyway, so the guide is not filled
+    if (st->err & ERR_ASYM) return;
     const int w = threadIdx.x / kWave;
     const int lane = lane_id();
     const int64_t wave_base = (int64_t)blockIdx.x * (kBlock * kWItems) + (int64_t)w * (kWave * kWItems);
@@ -1086,8 +1090,9 @@ __global__ __launch_bounds__(kBlock) void k_guide_long(const uint64_t *__restric
                                                        const uint64_t *__restrict__ seg, const uint32_t *shift_p,
                                                        uint32_t *__restrict__ guide,
                                                        const uint32_t *__restrict__ long_list,
-                                                       const uint32_t *nlong, uint32_t cap)
+                                                       const uint32_t *nlong, uint32_t cap, const uint32_t *err)
 {
+    if (*err & (ERR_ASYM | ERR_GUIDE)) return;  // inconsistent weights: the build fails
     const uint32_t shift = *shift_p;
     const uint64_t mask = (shift == 0) ? 0ull : ((1ull << shift) - 1ull);
     const uint32_t cnt = *nlong < cap ? *nlong : cap;  // listed runs were checked against nb
@@ -1457,9 +1462,9 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
         }
         const unsigned gl = (unsigned)std::min<uint64_t>(long_cap, 2048);
         hipLaunchKernelGGL(k_guide_long, dim3(gl), dim3(kBlock), 0, s, g->p_tau, g->seg_tau, &st->shift_tau,
-                           g->guide_tau, long_tau, &st->nlong_tau, (uint32_t)long_cap);
+                           g->guide_tau, long_tau, &st->nlong_tau, (uint32_t)long_cap, &st->err);
         hipLaunchKernelGGL(k_guide_long, dim3(gl), dim3(kBlock), 0, s, g->p_lam, g->seg_lam, &st->shift_lam,
-                           g->guide_lam, long_lam, &st->nlong_lam, (uint32_t)long_cap);
+                           g->guide_lam, long_lam, &st->nlong_lam, (uint32_t)long_cap, &st->err);
         PM_HIP(hipGetLastError());
     }
     if (n > 0) {

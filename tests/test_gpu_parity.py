@@ -406,3 +406,26 @@ def test_profile_select_restricts_recording():
     finally:
         ps.profile_enable(False)
         ps.profile_select(None)
+
+
+def test_large_asymmetric_graph_is_rejected():
+    """A directed random graph (rows sorted, no loops, no repeats, but not
+    symmetric) spanning many tiles and prefix segments: the build reports the
+    asymmetry; the inconsistent weights it leaves fill no guide table."""
+    rng = np.random.default_rng(21)
+    n, m = 50_000, 400_000
+    u = rng.integers(0, n, size=m)
+    v = rng.integers(0, n, size=m)
+    keep = u != v
+    key = np.unique(u[keep].astype(np.int64) * n + v[keep])
+    src, dst = key // n, key % n
+    off = np.zeros(n + 1, np.int64)
+    np.add.at(off, src + 1, 1)
+    off = np.cumsum(off)
+    col = dst.astype(np.int32)
+    _say("large asymmetric", len(col))
+    assert oracle.validate(off, col) != oracle.OK
+    with pytest.raises(ps.PathSampError) as e:
+        ps.Graph(*_dev(off, col))
+    assert e.value.status == ps.PM_EGRAPH
+    assert "not symmetric" in str(e.value)
