@@ -115,7 +115,7 @@ struct OffOut {
 // Relabelled rows built sorted (Section 4's order: ids are ranks, rows
 // ascending).  New row i is input row u = order[i] with every column c
 // mapped to rank[c]; rows are sorted where they are built, by size class:
-//   degree <= 16          one lane per row, a sorting network in registers
+//   degree <= 16          16 lanes per row, a sorting network across them
 //   16 < degree <= 64     one wave per row, a sorting network across lanes
 //   64 < degree <= 256    one wave per row, a sorting network on 2 (up to
 //                         128) or 4 keys per lane
@@ -130,8 +130,6 @@ struct OffOut {
 // 32nd column) at the row's final slots, and checks the input row (column
 // range, self-loop, strictly ascending).
 // ---------------------------------------------------------------------------
-
-constexpr int kLaneRowMax = 16;
 
 // the checks of one input slot p (row u, previous column prev or -1)
 __device__ __forceinline__ uint32_t slot_checks(int64_t c, int64_t u, int64_t prev, int64_t n)
@@ -158,86 +156,49 @@ __device__ __forceinline__ void cswap(uint32_t &a, uint32_t &b)
     b = hi;
 }
 
-// rows [r0, r1) with degree <= 16, one lane each: bitonic network on 16
-// registers (absent entries are 0xFFFFFFFF and sort last)
-__global__ __launch_bounds__(kBlock) void k_rows_lane(const int64_t *__restrict__ off_in,
-                                                      const int32_t *__restrict__ col_in,
-                                                      const uint32_t *__restrict__ order,
-                                                      const int32_t *__restrict__ rank,
-                                                      const uint32_t *__restrict__ off_new, int64_t n, int64_t r0,
-                                                      int64_t r1, uint32_t *__restrict__ col,
-                                                      uint64_t *__restrict__ edge, uint32_t *__restrict__ ladder1,
-                                                      PrepStats *st)
+// rows [r0, r1) with degree <= W, a group of W lanes each (W = 16: four rows
+// per wave; W = 64: one): slot j of a row is lane j of its group, so loads
+// and stores coalesce; a bitonic network across the group's lanes (absent
+// entries are 0xFFFFFFFF and sort last).  A slot's predecessor for the order
+// check comes from the lane below.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_rows_group(const int64_t *__restrict__ off_in,
+                                                       const int32_t *__restrict__ col_in,
+                                                       const uint32_t *__restrict__ order,
+                                                       const int32_t *__restrict__ rank,
+                                                       const uint32_t *__restrict__ off_new, int64_t n, int64_t r0,
+                                                       int64_t r1, uint32_t *__restrict__ col,
+                                                       uint64_t *__restrict__ edge, uint32_t *__restrict__ ladder1,
+                                                       PrepStats *st)
 {
-    const int64_t i = r0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t err = 0;
-    if (i < r1) {
-        const int64_t u = order[i], a = off_in[u], d = off_in[u + 1] - a;
-        uint32_t k[kLaneRowMax];
-        int64_t prev = -1;
-#pragma unroll
-        for (int j = 0; j < kLaneRowMax; ++j) {
-            k[j] = 0xFFFFFFFFu;
-            if (j < d) {
-                const int64_t c = col_in[a + j];
-                err |= slot_checks(c, u, prev, n);
-                prev = c;
-                k[j] = (c >= 0 && c < n) ? (uint32_t)rank[c] : 0u;
-            }
-        }
-#pragma unroll
-        for (int size = 2; size <= kLaneRowMax; size <<= 1)
-#pragma unroll
-            for (int stride = size >> 1; stride > 0; stride >>= 1)
-#pragma unroll
-                for (int j = 0; j < kLaneRowMax; ++j) {
-                    const int l = j ^ stride;
-                    if (l > j) {
-                        if ((j & size) == 0)
-                            cswap(k[j], k[l]);
-                        else
-                            cswap(k[l], k[j]);
-                    }
-                }
-        const int64_t dst = off_new[i];
-#pragma unroll
-        for (int j = 0; j < kLaneRowMax; ++j)
-            if (j < d) emit_slot(dst + j, (uint32_t)i, k[j], col, edge, ladder1);
+    static_assert(W == 16 || W == 64, "a quarter wave or a wave per row");
+    const int64_t i = r0 + ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / W;
+    if (W == kWave && i >= r1) return;  // whole waves leave together
+    const int j = lane_id() & (W - 1);
+    const bool row = i < r1;  // W = 16: the last wave may hold fewer rows
+    int64_t u = 0, a = 0, d = 0;
+    if (row) {
+        u = order[i];
+        a = off_in[u];
+        d = off_in[u + 1] - a;
     }
-    if (err) atomicOr(&st->err, err);
-}
-
-// rows [r0, r1) with 16 < degree <= 64, one wave each: bitonic network
-// across the 64 lanes (absent entries are 0xFFFFFFFF and sort last)
-__global__ __launch_bounds__(kBlock) void k_rows_wave(const int64_t *__restrict__ off_in,
-                                                      const int32_t *__restrict__ col_in,
-                                                      const uint32_t *__restrict__ order,
-                                                      const int32_t *__restrict__ rank,
-                                                      const uint32_t *__restrict__ off_new, int64_t n, int64_t r0,
-                                                      int64_t r1, uint32_t *__restrict__ col,
-                                                      uint64_t *__restrict__ edge, uint32_t *__restrict__ ladder1,
-                                                      PrepStats *st)
-{
-    const int64_t i = r0 + ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    if (i >= r1) return;  // whole waves leave together
-    const int lane = lane_id();
-    const int64_t u = order[i], a = off_in[u], d = off_in[u + 1] - a;
+    const bool ok = row && j < d;
+    const int32_t c = ok ? col_in[a + j] : 0;
+    const int32_t below = __shfl_up(c, 1, W);  // every lane takes part
     uint32_t err = 0, v = 0xFFFFFFFFu;
-    if (lane < d) {
-        const int64_t c = col_in[a + lane];
-        const int64_t prev = lane > 0 ? (int64_t)col_in[a + lane - 1] : -1;
-        err = slot_checks(c, u, prev, n);
+    if (ok) {
+        err = slot_checks(c, u, j > 0 ? (int64_t)below : -1, n);
         v = (c >= 0 && c < n) ? (uint32_t)rank[c] : 0u;
     }
 #pragma unroll
-    for (int size = 2; size <= kWave; size <<= 1)
+    for (int size = 2; size <= W; size <<= 1)
 #pragma unroll
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            const uint32_t o = __shfl_xor(v, stride, kWave);
-            const bool up = (lane & size) == 0, low = (lane & stride) == 0;
+            const uint32_t o = __shfl_xor(v, stride, W);
+            const bool up = (j & size) == 0, low = (j & stride) == 0;
             v = (up == low) ? (v < o ? v : o) : (v < o ? o : v);
         }
-    if (lane < d) emit_slot(off_new[i] + lane, (uint32_t)i, v, col, edge, ladder1);
+    if (ok) emit_slot(off_new[i] + j, (uint32_t)i, v, col, edge, ladder1);
     if (err) atomicOr(&st->err, err);
 }
 
@@ -1304,14 +1265,15 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
         ProfScope prof("build_rows", s);
         if (cls[1] > cls[0]) {
             ProfScope pc("build_rows.lane", s);
-            hipLaunchKernelGGL(k_rows_lane, dim3((unsigned)((cls[1] - cls[0] + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                               s, off_in, col_in, order, g->rank, g->off, n, cls[0], cls[1], g->col, g->edge, ladder1,
+            hipLaunchKernelGGL(k_rows_group<16>, dim3((unsigned)((cls[1] - cls[0] + 15) / 16)), dim3(kBlock), 0, s,
+                               off_in, col_in, order, g->rank, g->off, n, cls[0], cls[1], g->col, g->edge, ladder1,
                                st);
         }
         if (cls[2] > cls[1]) {
             ProfScope pc("build_rows.wave", s);
-            hipLaunchKernelGGL(k_rows_wave, dim3((unsigned)((cls[2] - cls[1] + 3) / 4)), dim3(kBlock), 0, s, off_in,
-                               col_in, order, g->rank, g->off, n, cls[1], cls[2], g->col, g->edge, ladder1, st);
+            hipLaunchKernelGGL(k_rows_group<64>, dim3((unsigned)((cls[2] - cls[1] + 3) / 4)), dim3(kBlock), 0, s,
+                               off_in, col_in, order, g->rank, g->off, n, cls[1], cls[2], g->col, g->edge, ladder1,
+                               st);
         }
         if (cls[3] > cls[2]) {
             ProfScope pc("build_rows.w128", s);
