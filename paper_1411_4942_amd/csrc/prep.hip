@@ -1433,11 +1433,11 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
         hipLaunchKernelGGL(k_n1, dim3(grid_for(n, kBlock, 1024)), dim3(kBlock), 0, s, g->deg, n, st);
         PM_HIP(hipGetLastError());
     }
-    uint64_t R[2] = {0, 0};
-    PM_HIP(hipMemcpyAsync(&R[0], g->seg_tau + nseg, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-    PM_HIP(hipMemcpyAsync(&R[1], g->seg_lam + nseg, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     PM_HIP(hipMemcpyAsync(&hst, st, sizeof(hst), hipMemcpyDeviceToHost, s));
     PM_HIP(hipStreamSynchronize(s));
+    // the scan writes its totals with the last segment offsets (seg[nseg]);
+    // both stay 0 for an empty graph
+    const uint64_t R[2] = {hst.totals.a, hst.totals.b};
     if (hst.err & ERR_ASYM) {
         set_error(err_text(hst.err));
         return PM_EGRAPH;
