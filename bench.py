@@ -54,6 +54,17 @@ def load_traffic():
     return t if t.get("source_hash") == source_hash() else None
 
 
+def rev_pass_bytes(n: int) -> float:
+    """Algorithmic bytes per element of one reverse-sort scatter launch,
+    averaged over its passes (8-bit digits over the bits of n - 1)."""
+    bits = max(int(n - 1).bit_length(), 1)
+    passes = (bits + 7) // 8
+    if passes == 1:
+        return 8.0  # key read, value written
+    per = [12.0] + [16.0] * (passes - 2) + [12.0]
+    return sum(per) / passes
+
+
 def roofline_for(name, kern, alg_entry, traffic, copy_gbs=None):
     alg_bytes, symbol = alg_entry
     achieved = alg_bytes / (kern["avg_ms"] * 1e-3) / 1e9
@@ -578,14 +589,17 @@ def main():
         # the sampling kernels over draw-ordered ids
         "sample_path.sorted": (BYTES_PER_SAMPLE * k, "pm::k_sample_sorted<false>"),
         "sample_centered.sorted": (BYTES_PER_SAMPLE * k, "pm::k_sample_sorted<true>"),
-        # one pass: read key + value, write key + value
-        "reverse_sort.scatter": (16 * slots, "pm::radix_scatter"),
+        # per launch, averaged over the passes: the first reads no value (the
+        # payload is the position: key 4 read, key 4 + value 4 written), the
+        # middle ones read and write key + value (16), the last writes no key
+        # (key 4 + value 4 read, value 4 written)
+        "reverse_sort.scatter": (rev_pass_bytes(info["n"]) * slots, "pm::radix_scatter"),
         "reverse_sort.histogram": (4 * slots, "pm::radix_histogram"),
         # per slot: input column 4, its rank 4, column 4 and edge 8 written
         # (a scope over several kernels: reported, never the dominant kernel)
         "build_rows": (20 * slots, "pm::k_rows_block"),
-        # per slot: edge 8 + rev 4 + key2 4, both rows' 32-bit offset pairs 16, both segment prefixes written 16
-        "weights.reduce": (48 * slots, "pm::k_weights_reduce"),
+        # per slot: edge 8 + rev 4, both rows' 32-bit offset pairs 16, both segment prefixes written 16
+        "weights.reduce": (44 * slots, "pm::k_weights_reduce"),
         # per slot: both segment prefixes read 16, guide entries 2 (2m/4 buckets of 4 bytes per table)
         "weights.guide": (18 * slots, "pm::k_guide_fill"),
     }

@@ -773,7 +773,6 @@ static_assert((int64_t)kWave * kWItems == kPrefixSeg, "one wave per prefix segme
 
 __global__ __launch_bounds__(kBlock) void k_weights_reduce(const uint64_t *__restrict__ edge,
                                                            const uint32_t *__restrict__ rev,
-                                                           const uint32_t *__restrict__ key2,
                                                            const uint32_t *__restrict__ off, int64_t N,
                                                            uint64_t *__restrict__ p_tau,
                                                            uint64_t *__restrict__ p_lam, U64x2 *__restrict__ seg_sums,
@@ -789,7 +788,7 @@ __global__ __launch_bounds__(kBlock) void k_weights_reduce(const uint64_t *__res
 #pragma unroll
     for (int h = 0; h < kWItems; h += kWBatch) {
         uint64_t e[kWBatch];
-        uint32_t r[kWBatch], k2[kWBatch];
+        uint32_t r[kWBatch];
 #pragma unroll
         for (int i = 0; i < kWBatch; ++i) {
             const int64_t idx = wave_base + (int64_t)(h + i) * kWave + lane;
@@ -797,7 +796,6 @@ __global__ __launch_bounds__(kBlock) void k_weights_reduce(const uint64_t *__res
             // read once here: keep them out of the cache the gathers use
             e[i] = ok ? __builtin_nontemporal_load(edge + idx) : 0ull;
             r[i] = ok ? __builtin_nontemporal_load(rev + idx) : 0u;
-            k2[i] = ok ? __builtin_nontemporal_load(key2 + idx) : 0u;
         }
         uint32_t ou[kWBatch], ou1[kWBatch], ov[kWBatch], ov1[kWBatch];
 #pragma unroll
@@ -813,10 +811,13 @@ __global__ __launch_bounds__(kBlock) void k_weights_reduce(const uint64_t *__res
             const int64_t idx = wave_base + (int64_t)(h + i) * kWave + lane;
             uint64_t tau = 0, lam = 0;
             if (idx < N) {
-                const uint32_t u = (uint32_t)e[i];
                 const int64_t rr = r[i];
-                if (k2[i] != u) err |= ERR_ASYM;                                    // symmetry, half 1
-                if (rr < (int64_t)ov[i] || rr >= (int64_t)ov1[i]) err |= ERR_ASYM;  // half 2
+                // symmetry: slot rev[i] (the i-th slot ordered by column) lies
+                // in row v.  Over all slots that makes every in-degree equal
+                // its out-degree (rev is a bijection), so the slots of column
+                // u fill exactly row u's positions, and slot rev[i] of row v
+                // has column u: it is the reverse (v, u) of slot i.
+                if (rr < (int64_t)ov[i] || rr >= (int64_t)ov1[i]) err |= ERR_ASYM;
                 const int64_t du = (int64_t)ou1[i] - ou[i], dv = (int64_t)ov1[i] - ov[i];
                 tau = (uint64_t)(du - 1) * (uint64_t)(dv - 1);
                 const uint64_t luv = (uint64_t)(du - 1 - (idx - (int64_t)ou[i]));
@@ -1375,9 +1376,10 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
     PM_TRY(tmp.get(&v2a, ss));
 
     // reverse slots and the symmetry check: the slots' columns sorted stably,
-    // with each slot's own position as payload
-    uint32_t *key2, *rev;
-    PM_TRY(radix_sort("reverse_sort", g->col, nullptr, kb, vfree, ka, v2a, slots, vbits, rscr, s, &key2, &rev));
+    // with each slot's own position as payload (only the payload is kept)
+    uint32_t *keys_unused, *rev;
+    PM_TRY(radix_sort("reverse_sort", g->col, nullptr, kb, vfree, ka, v2a, slots, vbits, rscr, s, &keys_unused, &rev,
+                      nullptr, nullptr, false));
 
     // weights, their prefixes and the guide tables of the edge draws (nothing
     // below indexes memory through the weights until the checks are read back)
@@ -1407,7 +1409,7 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
         const int64_t tiles = (slots + (int64_t)kBlock * kWItems - 1) / ((int64_t)kBlock * kWItems);
         {
             ProfScope pr("weights.reduce", s);
-            hipLaunchKernelGGL(k_weights_reduce, dim3((unsigned)tiles), dim3(kBlock), 0, s, g->edge, rev, key2, g->off,
+            hipLaunchKernelGGL(k_weights_reduce, dim3((unsigned)tiles), dim3(kBlock), 0, s, g->edge, rev, g->off,
                                slots, g->p_tau, g->p_lam, sums, st);
             PM_HIP(hipGetLastError());
         }

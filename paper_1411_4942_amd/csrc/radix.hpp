@@ -99,8 +99,9 @@ static __global__ __launch_bounds__(kRadixThreads) void radix_histogram(const ui
 }
 
 // vals_in may be null: the payload is then the element's input position.
-// keys_out may be null when pair_out is given: then pair_out[dst] =
-// key | val << 32 replaces the key array (vals_out is always written).
+// keys_out may be null: with pair_out given, pair_out[dst] = key | val << 32
+// replaces the key array; without, the keys are not written (vals_out is
+// always written).
 // sample_out, when given, receives every 32nd value: sample_out[dst / 32].
 static __global__ __launch_bounds__(kRadixThreads) void radix_scatter(const uint32_t *__restrict__ keys_in,
                                                         const uint32_t *__restrict__ vals_in, int64_t N, int shift,
@@ -208,7 +209,7 @@ static __global__ __launch_bounds__(kRadixThreads) void radix_scatter(const uint
             const uint32_t vv = s_val[p];
             if (pair_out)
                 pair_out[dst] = (uint64_t)k | ((uint64_t)vv << 32);
-            else
+            else if (keys_out)
                 keys_out[dst] = k;
             vals_out[dst] = vv;
             if (sample_out && (dst & 31u) == 0) sample_out[dst >> 5] = vv;
@@ -349,7 +350,8 @@ inline size_t radix_scratch_bytes(int64_t N)
 // (k0, v0) and (k1, v1).  On return *out_k / *out_v point at the result.
 // With pair_out, the last pass writes key | val << 32 there instead of the
 // keys (*out_k is then null); with sample_out it also writes every 32nd
-// value.  N < 2^32.
+// value.  With keys_wanted false the last pass writes no keys (*out_k is
+// then null).  N < 2^32.
 static __global__ void radix_pair_copy(const uint32_t *__restrict__ k, const uint32_t *__restrict__ v, int64_t N,
                                 uint64_t *__restrict__ pair, uint32_t *__restrict__ sample, uint32_t *__restrict__ vcopy)
 {
@@ -364,7 +366,7 @@ static __global__ void radix_pair_copy(const uint32_t *__restrict__ k, const uin
 inline pm_status radix_sort(const char *name, const uint32_t *in_k, const uint32_t *in_v, uint32_t *k0, uint32_t *v0,
                             uint32_t *k1, uint32_t *v1, int64_t N, int bits, void *scratch, hipStream_t s,
                             uint32_t **out_k, uint32_t **out_v, uint64_t *pair_out = nullptr,
-                            uint32_t *sample_out = nullptr)
+                            uint32_t *sample_out = nullptr, bool keys_wanted = true)
 {
     const std::string n_hist = std::string(name) + ".histogram", n_scan = std::string(name) + ".count_scan",
                       n_scat = std::string(name) + ".scatter";
@@ -411,8 +413,9 @@ inline pm_status radix_sort(const char *name, const uint32_t *in_k, const uint32
             uint64_t *po = (last && pair_out) ? pair_out : nullptr;
             uint32_t *so = last ? sample_out : nullptr;
             ProfScope prof(n_scat.c_str(), s);
+            uint32_t *kw = (po || (last && !keys_wanted)) ? nullptr : ko;
             hipLaunchKernelGGL(radix_scatter, dim3((unsigned)tiles), dim3(kRadixThreads), 0, s, ki, vi, N, shift, mask,
-                               offs, tiles, po ? nullptr : ko, vo, po, so);
+                               offs, tiles, kw, vo, po, so);
             PM_HIP(hipGetLastError());
         }
         *out_k = ko;
@@ -422,7 +425,7 @@ inline pm_status radix_sort(const char *name, const uint32_t *in_k, const uint32
         ko = (ko == k0) ? k1 : k0;
         vo = (vo == v0) ? v1 : v0;
     }
-    if (pair_out) *out_k = nullptr;
+    if (pair_out || !keys_wanted) *out_k = nullptr;
     return PM_OK;
 }
 
