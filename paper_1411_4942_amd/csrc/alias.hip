@@ -392,7 +392,8 @@ pm_status launch_alias_sorted(const SamplerView &v, const AliasEntry *T, uint64_
                                kin);
         PM_HIP(hipGetLastError());
         uint32_t *ks = nullptr, *ids = nullptr;
-        PM_TRY(radix_sort("alias_draw_sort", kin, nullptr, k0, v0, k1, v1, (int64_t)kc, kbits, scr, s, &ks, &ids));
+        PM_TRY(radix_sort("alias_draw_sort", kin, nullptr, k0, v0, k1, v1, (int64_t)kc, kbits, scr, s, &ks, &ids,
+                          nullptr, nullptr, false));  // only the ids are used
         if (centered)
             hipLaunchKernelGGL((k_sample_alias_sorted<true>), dim3(kb), dim3(kBlock), 0, s, v, T, N, seed, first + c0,
                                kc, ids, (unsigned long long *)tally);

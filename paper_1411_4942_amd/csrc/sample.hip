@@ -142,7 +142,8 @@ static pm_status launch_sorted(const pm_graph *g, const SamplerView &v, bool cen
             PM_HIP(hipGetLastError());
         }
         uint32_t *ks = nullptr, *ids = nullptr;
-        PM_TRY(radix_sort("draw_sort", kin, nullptr, k0, v0, k1, v1, (int64_t)kc, kbits, scr, s, &ks, &ids));
+        PM_TRY(radix_sort("draw_sort", kin, nullptr, k0, v0, k1, v1, (int64_t)kc, kbits, scr, s, &ks, &ids,
+                          nullptr, nullptr, false));  // only the ids are used
         {
             ProfScope pk(centered ? "sample_centered.sorted" : "sample_path.sorted", s);
             if (centered)
