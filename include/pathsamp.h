@@ -128,14 +128,29 @@ pm_status pm_count_motifs(const pm_csr_view *csr, uint64_t k, uint64_t seed, pm_
  * is immutable after creation: concurrent pm_count calls on it are safe. */
 pm_status pm_graph_create(const pm_csr_view *csr, uint32_t flags, void *stream, pm_graph **out);
 
+/* Sizes and totals of a prepared graph (the survey's pm_graph_info, named
+ * _get here because the struct already takes that name): n, m, the largest
+ * degree, isolated vertices, W (Section 3: 3-paths plus three times the
+ * triangles, the total of tau over one orientation of each edge), Lambda
+ * (Section 4: the total of lambda over one orientation), N_1 (Algorithm 2:
+ * the sum over vertices of C(d_v, 3)) and the handle's resident device bytes.
+ * Host call, no device work.  Errors: PM_EINVAL (null argument). */
 pm_status pm_graph_info_get(const pm_graph *g, pm_graph_info *out);
 
-/* Copy the prepared arrays to host buffers (any pointer may be NULL):
- * off[n+1] and col[2m] of the relabelled graph, rank[n] (input id ->
- * relabelled id), p_tau[2m] and p_lam[2m] (inclusive prefix sums over slots). */
+/* Copy the prepared arrays to caller-owned host buffers (any pointer may be
+ * NULL): off[n+1] and col[2m] of the graph relabelled in the degree order of
+ * Section 4 (rows ascending), rank[n] (input id -> relabelled id), p_tau[2m]
+ * (inclusive prefix of tau, Section 3 / Algorithm 1 step 1) and p_lam[2m]
+ * (inclusive prefix of lambda, Section 4 / Algorithm 3 step 1), both global
+ * over the slots.  Synchronises `stream` before returning.  Errors:
+ * PM_EINVAL (null graph), PM_ENOMEM, PM_EDEVICE. */
 pm_status pm_graph_export(const pm_graph *g, int64_t *off, int32_t *col, int32_t *rank, uint64_t *p_tau,
                           uint64_t *p_lam, void *stream);
 
+/* Release a prepared graph (the arrays pm_graph_create built for Sections 3
+ * and 4).  Waits for all work on the graph's device first (samplers still
+ * running on any stream, pm_sample_async included), so the memory is never
+ * handed out while a kernel reads it.  Errors: PM_EINVAL (null), PM_EDEVICE. */
 pm_status pm_graph_destroy(pm_graph *g);
 
 /* Run both samplers on a prepared graph and finalize on the host.  A sampler

@@ -104,8 +104,15 @@ pm_status pm_graph_destroy(pm_graph *g)
             pm::set_error("null graph");
             return PM_EINVAL;
         }
+        // samplers may still read the graph on a caller's stream
+        // (pm_sample_async): wait for the whole device before freeing
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) {
+            pm::set_error(std::string("pm_graph_destroy: ") + hipGetErrorString(e));
+            return PM_EDEVICE;
+        }
         pm::graph_free(g, nullptr);
-        hipError_t e = hipStreamSynchronize(nullptr);
+        e = hipStreamSynchronize(nullptr);
         if (e != hipSuccess) {
             pm::set_error(std::string("pm_graph_destroy: ") + hipGetErrorString(e));
             return PM_EDEVICE;
@@ -167,8 +174,15 @@ pm_status pm_count_motifs(const pm_csr_view *csr, uint64_t k, uint64_t seed, pm_
         p.seed = seed;
         p.delta = 0.01;
         st = pm::count_on_graph(g, &p, out, nullptr);
+        // samplers may still read the graph on a caller's stream
+        // (pm_sample_async): wait for the whole device before freeing
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) {
+            pm::set_error(std::string("pm_graph_destroy: ") + hipGetErrorString(e));
+            return PM_EDEVICE;
+        }
         pm::graph_free(g, nullptr);
-        hipError_t e = hipStreamSynchronize(nullptr);
+        e = hipStreamSynchronize(nullptr);
         if (st == PM_OK && e != hipSuccess) {
             pm::set_error(std::string("pm_count_motifs: ") + hipGetErrorString(e));
             return PM_EDEVICE;
