@@ -1,12 +1,15 @@
 #!/usr/bin/env python3
-"""Benchmark: the whole 3-path sampling hot path on one MI355X.
+"""Benchmark: the sampling stage of 3-path sampling on one MI355X.
 
-One step = prepare the graph from its device-resident CSR (validation,
-degree-order relabel, tau/lambda prefix sums, N_1, guide tables), run both
-samplers with k samples each, and finalize estimates with 99% error bars.
-Workload: R-MAT scale 22 (a, b, c, d) = (0.57, 0.19, 0.19, 0.05), symmetrised
-and deduplicated (about 1.2e8 undirected edges), k = 1e7 samples per sampler,
-Philox seed 1.  value = samples per step (2k) / step time.
+Workload: R-MAT scale 22 (a, b, c, d) = (0.57, 0.19, 0.19, 0.05),
+symmetrised and deduplicated (about 1.2e8 undirected edges), k = 1e7 samples
+per sampler, Philox seed 1.  The graph is prepared once (validation,
+degree-order relabel, tau/lambda prefix sums, N_1, guide tables) and stays
+resident, as in serving.  One timed step = pm_count on the prepared graph:
+both samplers (per-sample randomness, edge draw, neighbour picks, adjacency
+tests, tallies) and the host finalize with 99% error bars.
+value = samples per step (2k) / step time.  Preparation and the whole job
+(prepare + count + release) are measured separately and reported beside it.
 
 Prints one JSON line.  --gpus above 1 is not supported (one GPU per box).
 """
@@ -68,17 +71,21 @@ def rev_pass_bytes(n: int) -> float:
 def roofline_for(name, kern, alg_entry, traffic, copy_gbs=None):
     alg_bytes, symbol = alg_entry
     achieved = alg_bytes / (kern["avg_ms"] * 1e-3) / 1e9
-    tr = None
+    tr = hit = None
     if traffic:
-        cands = [v for key, v in traffic["kernels"].items() if key.startswith(symbol)]
+        cands = [v for key, v in traffic["kernels"].items() if key.startswith(symbol + "@")]
         if cands:
             best = max(cands, key=lambda v: v["fetch_bytes"])
             tr = best["fetch_bytes"] + best["write_bytes"]
+            if best.get("tcc_hit") is not None and best.get("tcc_miss"):
+                hit = best["tcc_hit"] / (best["tcc_hit"] + best["tcc_miss"])
     return {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": tr, "algorithmic_bytes": alg_bytes,
             "measured_copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs if copy_gbs else None,
-            "avg_launch_ms": kern["avg_ms"],
-            "traffic_over_algorithmic": (tr / alg_bytes) if tr else None}
+            "avg_launch_ms": kern["avg_ms"], "launches_timed": kern.get("launches"),
+            "traffic_over_algorithmic": (tr / alg_bytes) if tr else None,
+            "traffic_gbs": (tr / (kern["avg_ms"] * 1e-3) / 1e9) if tr else None,
+            "tcc_hit_rate": hit}
 
 
 COPY_BYTES = 1 << 30
@@ -140,32 +147,53 @@ def make_graph(scale: int, edge_factor: float, seed: int):
     return off, col
 
 
-def cpu_baseline(scale: int, edge_factor: float, k: int, seed: int) -> dict:
-    """The oracle (single thread) on a bounded sample of the workload: an
-    R-MAT graph of the same family at a smaller scale, k scaled by the same
-    factor as the edges, whole job (prep + both samplers)."""
-    import oracle
-    from paper_1411_4942_amd import synth
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
 
-    # drawn on the device (fast), handed to the oracle as host arrays; only
-    # the oracle's own work is timed
-    off_d, col_d = synth.rmat_torch(scale, edge_factor, seed=seed, device="cuda")
-    off, col = off_d.cpu().numpy(), col_d.cpu().numpy()
-    del off_d, col_d
-    t0 = time.perf_counter()
-    g = oracle.Graph(off, col)
-    t1 = time.perf_counter()
-    g.sample_path(1, k)
-    g.sample_centered(1, k)
-    t2 = time.perf_counter()
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(off, col, k_sample: int, seed: int, gpu_tallies) -> dict:
+    """The oracle (single thread, the calling thread pinned to one core) on the
+    benchmark's own CSR: its preparation timed once, then each sampler over
+    the first k_sample ids (a bounded sample of the k ids a step draws),
+    whose tallies must equal the GPU's over the same ids."""
+    import oracle
+
+    core = sorted(os.sched_getaffinity(0))[0]
+    saved = os.sched_getaffinity(0)
+    os.sched_setaffinity(0, {core})  # this thread only (Linux): the oracle runs in it
+    try:
+        t0 = time.perf_counter()
+        g = oracle.Graph(off, col)
+        t1 = time.perf_counter()
+        tp = g.sample_path(seed, k_sample).tolist()
+        t2 = time.perf_counter()
+        tc = g.sample_centered(seed, k_sample).tolist()
+        t3 = time.perf_counter()
+    finally:
+        os.sched_setaffinity(0, saved)
     return {
-        "value": 2 * k / (t2 - t0),
+        "value": 2 * k_sample / (t3 - t1),
         "unit": "samples/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"R-MAT scale {scale} (same a,b,c,d and edge factor {edge_factor}, 2m={off[-1]}), "
-                  f"k={k} per sampler, prep {t1 - t0:.2f}s + sampling {t2 - t1:.2f}s, single thread",
-        "sampling_only_samples_per_s": 2 * k / (t2 - t1),
+        "sample": f"the benchmark graph itself (R-MAT scale 22, 2m={int(off[-1])}), oracle preparation once, "
+                  f"then ids [0, {k_sample}) of each sampler (of the {{k}} per step), Philox seed {seed}, "
+                  f"one thread pinned to core {core}",
+        "cpu_model": cpu_model(),
+        "nproc": os.cpu_count(),
+        "prep_s": t1 - t0,
+        "path_samples_per_s": k_sample / (t2 - t1),
+        "centered_samples_per_s": k_sample / (t3 - t2),
+        "bit_exact_vs_gpu": tp == gpu_tallies[0] and tc == gpu_tallies[1],
     }
 
 
@@ -519,16 +547,29 @@ def served_leg(count: int, n_sat: int, n_open: int, loads, rel_err: float, delta
     return out
 
 
+# The paper's own figure for context (Table 3, Section 6): orkut, 2.24e8
+# edges, k = 200K per sampler, 16.24 s end to end including reading the edge
+# list, C code on a 2 x 2.4 GHz Xeon with 6 cores.  Not the same metric.
+PAPER_CONTEXT = {
+    "source": "Table 3 and Section 6: 3-path sampling time, end to end including reading the edge list",
+    "graph": "orkut (SNAP), 3.07e6 vertices, 2.24e8 edges",
+    "k_per_sampler": 200_000,
+    "seconds": 16.24,
+    "machine": "2 x 2.4 GHz Intel Xeon, 6 cores, 64 GB (C implementation)",
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--scale", type=int, default=22)
     ap.add_argument("--edge-factor", type=float, default=31.0)
     ap.add_argument("--k", type=int, default=10_000_000)
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--cpu-scale", type=int, default=20)
+    ap.add_argument("--whole-steps", type=int, default=5)
+    ap.add_argument("--cpu-k", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-ingest", action="store_true")
@@ -560,62 +601,45 @@ def main():
     stream = torch.cuda.current_stream()
     k = args.k
 
+    # the prepared graph stays resident; a step samples it
+    g = ps.Graph(off, col, stream=stream)
+    info = g.info()
+    slots = 2 * info["m"]
+
     def step():
-        g = ps.Graph(off, col, stream=stream)
-        res = g.count(k, k, seed=1, stream=stream)
-        info = g.info()
-        g.destroy()
-        return res, info
+        return g.count(k, k, seed=1, stream=stream)
 
     for i in range(args.warmup):
         t0 = time.perf_counter()
-        res, info = step()
-        log(f"[bench] warmup {i}: {1e3 * (time.perf_counter() - t0):.1f} ms")
+        res = step()
+        log(f"[bench] warmup {i}: {1e3 * (time.perf_counter() - t0):.2f} ms")
 
-    # the per-kernel breakdown: separate steps with every scope timed
+    # per-kernel breakdown of a step: separate steps with every scope timed
     ps.profile_enable(True)
     for i in range(2):
-        res, info = step()
+        step()
     torch.cuda.synchronize()
     kernels = {name: {"launches": n, "avg_ms": ms / n, "ms_per_step": ms / 2}
                for name, (n, ms) in ps.profile_read().items()}
     ps.profile_enable(False)
-    slots = 2 * info["m"]
-    # algorithmic bytes per launch of the kernels the roofline can name
-    alg = {
-        # both samplers whole (draw keys, draw sort, sampling: several kernels)
-        "sample_path": (BYTES_PER_SAMPLE * k, "pm::k_sample"),
-        "sample_centered": (BYTES_PER_SAMPLE * k, "pm::k_sample"),
-        # the sampling kernels over draw-ordered ids
+    samp = "sample_path.sorted" if "sample_path.sorted" in kernels else "sample_path"
+    cent = "sample_centered.sorted" if "sample_centered.sorted" in kernels else "sample_centered"
+    alg_samp = {
+        # the sampling kernels: algorithmic bytes per sample x samples per launch
         "sample_path.sorted": (BYTES_PER_SAMPLE * k, "pm::k_sample_sorted<false>"),
         "sample_centered.sorted": (BYTES_PER_SAMPLE * k, "pm::k_sample_sorted<true>"),
-        # per launch, averaged over the passes: the first reads no value (the
-        # payload is the position: key 4 read, key 4 + value 4 written), the
-        # middle ones read and write key + value (16), the last writes no key
-        # (key 4 + value 4 read, value 4 written)
-        "reverse_sort.scatter": (rev_pass_bytes(info["n"]) * slots, "pm::radix_scatter"),
-        "reverse_sort.histogram": (4 * slots, "pm::radix_histogram"),
-        # per slot: input column 4, its rank 4, column 4 and edge 8 written
-        # (a scope over several kernels: reported, never the dominant kernel)
-        "build_rows": (20 * slots, "pm::k_rows_block"),
-        # per slot: edge 8 + rev 4, both rows' 32-bit offset pairs 16, both segment prefixes written 16
-        "weights.reduce": (44 * slots, "pm::k_weights_reduce"),
-        # per slot: both segment prefixes read 16, guide entries 2 (2m/4 buckets of 4 bytes per table)
-        "weights.guide": (18 * slots, "pm::k_guide_fill"),
+        "sample_path": (BYTES_PER_SAMPLE * k, "pm::k_sample<false, 1>"),
+        "sample_centered": (BYTES_PER_SAMPLE * k, "pm::k_sample<true, 1>"),
     }
-    multi = {"build_rows", "sample_path", "sample_centered"}  # scopes spanning several kernels
-    cand = {n: v for n, v in kernels.items() if n in alg and n not in multi}
-    dom_name = max(cand, key=lambda n: cand[n]["ms_per_step"])
-    samp = "sample_path.sorted" if "sample_path.sorted" in kernels else "sample_path"
 
-    # the timed region: events only around the two kernels the roofline
-    # lines report (every timed scope adds two event records between kernels)
-    ps.profile_select([dom_name, samp])
+    # the timed region: K steps; HIP events only around the 3-path sampling
+    # kernel (the step's dominant kernel) on the stream it runs on
+    ps.profile_select([samp])
     ps.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        res, info = step()
+        res = step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     live = {name: {"launches": n, "avg_ms": ms / n, "ms_per_step": ms / args.steps}
@@ -624,23 +648,67 @@ def main():
     ps.profile_select(None)
     ms_per_step = 1e3 * (t1 - t0) / args.steps
     value = 2 * k / ((t1 - t0) / args.steps)
-    log(f"[bench] {args.steps} steps: {ms_per_step:.2f} ms/step")
+    log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step, {value:.4e} samples/s")
+
+    # the whole job per graph: prepare + count + release (the preparation
+    # kernels' breakdown from the same steps)
+    def whole():
+        h = ps.Graph(off, col, stream=stream)
+        r = h.count(k, k, seed=1, stream=stream)
+        h.destroy()
+        return r
+
+    whole()
+    ps.profile_enable(True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for _ in range(args.whole_steps):
+        rw = whole()
+    torch.cuda.synchronize()
+    w1 = time.perf_counter()
+    prep_kernels = {name: {"launches": n, "avg_ms": ms / n, "ms_per_step": ms / args.whole_steps}
+                    for name, (n, ms) in ps.profile_read().items()}
+    ps.profile_enable(False)
+    assert rw["tally_path"] == res["tally_path"] and rw["tally_cent"] == res["tally_cent"]
+    whole_ms = 1e3 * (w1 - w0) / args.whole_steps
+    log(f"[bench] whole job: {whole_ms:.2f} ms/step (prepare {prep_kernels['prep_total']['avg_ms']:.2f} ms)")
+
     copy_gbs = measure_copy(stream)
     gather_per_s = measure_gather(stream)
-
     traffic = load_traffic()
-    roofline = roofline_for(dom_name, live[dom_name], alg[dom_name], traffic, copy_gbs)
-    roofline_sampler = roofline_for(samp, live[samp], alg[samp], traffic, copy_gbs)
-    roofline_all = {n: {"achieved_gbs": alg[n][0] / (kernels[n]["avg_ms"] * 1e-3) / 1e9,
-                        "frac": alg[n][0] / (kernels[n]["avg_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                        "ms_per_step": kernels[n]["ms_per_step"]} for n in alg if n in kernels}
-    # line-granular view: fetched lines per sample against the random-load ceiling
-    roofline_sampler["random_loads_per_s_ceiling"] = gather_per_s
-    if roofline_sampler["traffic"]:
-        lines = roofline_sampler["traffic"] / 128.0 / k
-        roofline_sampler["lines_per_sample"] = lines
-        roofline_sampler["lines_per_s"] = lines * k / (live[samp]["avg_ms"] * 1e-3)
-        roofline_sampler["frac_of_random_ceiling"] = roofline_sampler["lines_per_s"] / gather_per_s
+    roofline = roofline_for(samp, live[samp], alg_samp[samp], traffic, copy_gbs)
+    # line-granular view: fetched 128-byte lines per sample against the
+    # measured random-load ceiling (one line per independent random load)
+    roofline["random_loads_per_s_ceiling"] = gather_per_s
+    if roofline["traffic"]:
+        lines = roofline["traffic"] / 128.0 / k
+        roofline["lines_per_sample"] = lines
+        roofline["lines_per_s"] = lines * k / (live[samp]["avg_ms"] * 1e-3)
+        roofline["frac_of_random_ceiling"] = roofline["lines_per_s"] / gather_per_s
+    roofline_cent = roofline_for(cent, kernels[cent], alg_samp[cent], traffic, copy_gbs)
+
+    prep_alg = {
+        # per launch, averaged over the passes: the first reads no value (the
+        # payload is the position: key 4 read, key 4 + value 4 written), the
+        # middle ones read and write key + value (16), the last writes no key
+        # (key 4 + value 4 read, value 4 written)
+        "reverse_sort.scatter": (rev_pass_bytes(info["n"]) * slots, "pm::radix_scatter"),
+        "reverse_sort.histogram": (4 * slots, "pm::radix_histogram"),
+        # per slot: input column 4, its rank 4, column 4 and edge 8 written
+        "build_rows": (20 * slots, "pm::k_rows_block"),
+        # per slot: edge 8 + rev 4, both rows' 32-bit offset pairs 16, both segment prefixes written 16
+        "weights.reduce": (44 * slots, "pm::k_weights_reduce"),
+        # per slot: both segment prefixes read 16, guide entries 2 (2m/4 buckets of 4 bytes per table)
+        "weights.guide": (18 * slots, "pm::k_guide_fill"),
+    }
+    multi = {"build_rows"}  # a scope over several kernels: reported, never the dominant kernel
+    cand = {n: v for n, v in prep_kernels.items() if n in prep_alg and n not in multi}
+    prep_dom = max(cand, key=lambda n: cand[n]["ms_per_step"])
+    roofline_prep = roofline_for(prep_dom, prep_kernels[prep_dom], prep_alg[prep_dom], traffic, copy_gbs)
+    roofline_prep_all = {n: {"achieved_gbs": prep_alg[n][0] / (prep_kernels[n]["avg_ms"] * 1e-3) / 1e9,
+                             "frac": prep_alg[n][0] / (prep_kernels[n]["avg_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                             "ms_per_step": prep_kernels[n]["ms_per_step"]}
+                         for n in prep_alg if n in prep_kernels}
     samp_ms = [kernels[n]["avg_ms"] for n in ("sample_path", "sample_centered") if n in kernels]
 
     out = {
@@ -658,21 +726,49 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"R-MAT scale {args.scale} (0.57,0.19,0.19,0.05), edge factor {args.edge_factor}, "
-                        f"symmetrised+dedup; k={k} 3-path + {k} centered samples, Philox seed 1",
+                        f"symmetrised+dedup, prepared once and resident; step = pm_count: k={k} 3-path + {k} "
+                        f"centered samples (Philox seed 1) + host finalize",
             "n": info["n"], "m": info["m"], "dmax": info["dmax"], "isolated": info["isolated"],
             "W": info["W"], "Lambda": info["Lambda"], "N1": info["N1"],
             "samples_per_step": 2 * k,
             "parallelism": "single GPU",
         },
         "roofline": roofline,
-        "roofline_sampler": roofline_sampler,
-        "roofline_by_kernel": roofline_all,
-        # every scope, from two profiled steps outside the timed region
+        "roofline_centered": roofline_cent,
+        "roofline_prep": roofline_prep,
+        "roofline_prep_by_kernel": roofline_prep_all,
+        "prep_ms": prep_kernels["prep_total"]["avg_ms"],
+        "whole_job": {"what": "pm_graph_create from the device-resident CSR (all checks) + pm_count + "
+                              "pm_graph_destroy, per step",
+                      "ms_per_step": whole_ms, "samples_per_s": 2 * k / (whole_ms * 1e-3),
+                      "steps": args.whole_steps},
+        # every scope of a step, from two profiled steps outside the timed region
         "kernels": kernels,
-        "sampling_samples_per_s": 2 * k / (sum(samp_ms) * 1e-3),
+        "prep_kernels": prep_kernels,
+        "sampling_kernels_samples_per_s": 2 * k / (sum(samp_ms) * 1e-3),
         "estimates": res["est"][1:],
         "rel_bar_halfwidth": [((h - l) / 2 / e if e else None) for e, l, h in zip(res["est"][1:], res["lo"][1:], res["hi"][1:])],
+        "paper_context": dict(PAPER_CONTEXT),
     }
+    # the paper's end-to-end figure next to ours at its k (prepare + 2 x 200K samples)
+    kp = PAPER_CONTEXT["k_per_sampler"]
+    h = ps.Graph(off, col, stream=stream)
+    h.count(kp, kp, seed=1, stream=stream)
+    h.destroy()
+    torch.cuda.synchronize()
+    c0 = time.perf_counter()
+    h = ps.Graph(off, col, stream=stream)
+    h.count(kp, kp, seed=1, stream=stream)
+    h.destroy()
+    torch.cuda.synchronize()
+    out["paper_context"]["this_gpu_prepare_plus_200k_per_sampler_ms"] = 1e3 * (time.perf_counter() - c0)
+    out["paper_context"]["this_gpu_graph"] = f"R-MAT scale {args.scale}, {info['m']} edges, CSR already in HBM"
+
+    gpu_cpu_tallies = None
+    if not args.no_cpu_baseline:
+        r_small = g.count(args.cpu_k, args.cpu_k, seed=1, stream=stream)
+        gpu_cpu_tallies = (r_small["tally_path"], r_small["tally_cent"])
+    g.destroy()
     if not args.no_ingest:
         log("[bench] ingest leg ...")
         out["ingest"] = ingest_leg(args.scale, args.edge_factor, args.seed, k, res)
@@ -701,9 +797,15 @@ def main():
                                    [float(x) for x in args.served_loads.split(",")], 0.01, 0.01,
                                    int(args.served_kmax), plain_check=min(8, args.served_sat))
     if not args.no_cpu_baseline:
-        log("[bench] cpu baseline (oracle) ...")
-        kc = max(1, int(k * (2 ** args.cpu_scale) / (2 ** args.scale)))
-        out["cpu_baseline"] = cpu_baseline(args.cpu_scale, args.edge_factor, kc, args.seed)
+        log("[bench] cpu baseline (oracle on the benchmark graph) ...")
+        off_h, col_h = off.cpu().numpy(), col.cpu().numpy()
+        del off, col
+        torch.cuda.empty_cache()
+        cb = cpu_baseline(off_h, col_h, args.cpu_k, 1, gpu_cpu_tallies)
+        cb["sample"] = cb["sample"].replace("{k}", str(k))
+        out["cpu_baseline"] = cb
+        log(f"[bench] cpu baseline: prep {cb['prep_s']:.1f} s, {cb['value']:.3e} samples/s, "
+            f"bit-exact vs GPU: {cb['bit_exact_vs_gpu']}")
     print(json.dumps(out), flush=True)
 
 
