@@ -73,7 +73,7 @@ int or_exact_brute(int64_t n, const int64_t *off, const int32_t *col, uint64_t C
 
 /* ---- formula counter ----------------------------------------------------- */
 
-static const int64_t *g_ex_off;
+static _Thread_local const int64_t *g_ex_off; /* per thread, like the relabel sort */
 
 static int cmp_deg_id(const void *pa, const void *pb)
 {

@@ -171,7 +171,8 @@ int or_validate(int64_t n, const int64_t *off, const int32_t *col)
 /* canonical relabel into the degree order of Section 4                     */
 /* ------------------------------------------------------------------------ */
 
-static const int64_t *g_sort_off; /* the oracle is single-threaded */
+/* per thread: tests prepare several oracle graphs on host threads at once */
+static _Thread_local const int64_t *g_sort_off;
 
 static int cmp_degree_then_id(const void *pa, const void *pb)
 {
