@@ -433,6 +433,21 @@ pm_status pm_set_sampler_shape(int32_t samples_per_lane, int32_t blocks_per_cu);
  * do not change: enabled = 0 gives the same results in id order. */
 pm_status pm_set_draw_order(int32_t enabled, uint64_t min_samples);
 
+/* How pm_count and pm_sample_async run the adjacency tests of Algorithms 2
+ * and 4 ("determine the subgraph induced by" the sampled path) in this
+ * process: PM_SEARCH_LANE (0) searches each sample's row in its own lane
+ * through the row search index (one 128-byte line per level, read as eight
+ * 16-byte loads per lane); PM_SEARCH_WAVE (1) lets the 64 lanes of a wave
+ * read each query's line together (two queries per coalesced load, a ballot
+ * counts the entries at most the key).  Both give the same answers, so
+ * tallies do not change.  Default PM_SEARCH_LANE: on MI355X the per-lane
+ * search measured about three times faster (the cooperative rounds spend
+ * their time in cross-lane instructions).  The batched, served and alias
+ * paths always search per lane.  Errors: PM_EINVAL for another mode. */
+#define PM_SEARCH_LANE 0
+#define PM_SEARCH_WAVE 1
+pm_status pm_set_search_mode(int32_t mode);
+
 /* Device memory: the library keeps freed blocks for reuse (each tagged with
  * an event on the stream that released it).  This returns every cached block
  * of the current device to the runtime (after those events complete).  Blocks

@@ -38,6 +38,7 @@ void dev_free(void *p, hipStream_t s);
 pm_status count_on_graph(const pm_graph *g, const pm_params *p, pm_result *out, hipStream_t s);
 pm_status set_sampler_shape(int32_t samples_per_lane, int32_t blocks_per_cu);
 pm_status set_draw_order(int32_t enabled, uint64_t min_samples);
+pm_status set_search_mode(int32_t mode);
 pm_status batch_create(const pm_graph *const *graphs, const pm_params *params, int32_t count, const pm_tune *tune,
                        hipStream_t user_stream, pm_batch **out);
 pm_status batch_set_params(pm_batch *b, const pm_params *params);
@@ -281,6 +282,11 @@ pm_status pm_set_sampler_shape(int32_t samples_per_lane, int32_t blocks_per_cu)
 pm_status pm_set_draw_order(int32_t enabled, uint64_t min_samples)
 {
     PM_GUARD(return pm::set_draw_order(enabled, min_samples);)
+}
+
+pm_status pm_set_search_mode(int32_t mode)
+{
+    PM_GUARD(return pm::set_search_mode(mode);)
 }
 
 pm_status pm_batch_create(const pm_graph *const *graphs, const pm_params *params, int32_t count, const pm_tune *tune,

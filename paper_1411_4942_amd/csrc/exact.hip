@@ -94,15 +94,15 @@ __global__ __launch_bounds__(kBlock) void k_split(const uint32_t *__restrict__ o
 // checked against N+(w).
 __global__ __launch_bounds__(kBlock) void k_triangles(const uint32_t *__restrict__ off,
                                                       const uint32_t *__restrict__ col,
-                                                      const uint64_t *__restrict__ edge,
+                                                      const SlotRec *__restrict__ rec,
                                                       const uint32_t *__restrict__ split, int64_t slots,
                                                       uint32_t *__restrict__ t_e, ExactAcc *acc)
 {
     unsigned long long tri = 0, k4 = 0;
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < slots;
          s += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t e = edge[s];
-        const uint32_t u = (uint32_t)e, v = (uint32_t)(e >> 32);
+        const SlotRec e = rec[s];
+        const uint32_t u = e.row, v = e.col;
         if (v <= u) continue;
         const int64_t a0 = s + 1, a1 = off[u + 1];
         const int64_t b0 = off[v] + split[v], b1 = off[v + 1];
@@ -152,18 +152,18 @@ __global__ __launch_bounds__(kBlock) void k_triangles(const uint32_t *__restrict
 
 // Sums over forward slots: 2 N_3 = sum t_e (d_u + d_v - 4), N_5 = sum C(t_e, 2)
 __global__ __launch_bounds__(kBlock) void k_edge_sums(const uint32_t *__restrict__ off,
-                                                      const uint64_t *__restrict__ edge,
+                                                      const SlotRec *__restrict__ rec,
                                                       const uint32_t *__restrict__ t_e, int64_t slots,
                                                       ExactAcc *acc)
 {
     unsigned __int128 n3 = 0, n5 = 0;
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < slots;
          s += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t e = edge[s];
-        const uint32_t u = (uint32_t)e, v = (uint32_t)(e >> 32);
+        const SlotRec e = rec[s];
+        const uint32_t u = e.row, v = e.col;
         const uint64_t t = t_e[s];
         if (v <= u || t == 0) continue;
-        const uint64_t du = (uint64_t)(off[u + 1] - off[u]), dv = (uint64_t)(off[v + 1] - off[v]);
+        const uint64_t du = (uint64_t)(off[u + 1] - off[u]), dv = e.cdeg;
         n3 += (unsigned __int128)t * (du + dv - 4);  // t > 0 means both degrees >= 2
         n5 += (unsigned __int128)(t * (t - 1) / 2);
     }
@@ -245,9 +245,9 @@ pm_status exact_counts(const pm_graph *g, pm_exact *out, hipStream_t s)
         {
             ProfScope prof("exact.triangles", s);
             hipLaunchKernelGGL(k_triangles, dim3(grid_for(slots, kBlock, 1 << 16)), dim3(kBlock), 0, s, g->off,
-                               g->col, g->edge, split, slots, t_e, acc);
+                               g->col, g->rec, split, slots, t_e, acc);
         }
-        hipLaunchKernelGGL(k_edge_sums, dim3(grid_for(slots, kBlock, 4096)), dim3(kBlock), 0, s, g->off, g->edge,
+        hipLaunchKernelGGL(k_edge_sums, dim3(grid_for(slots, kBlock, 4096)), dim3(kBlock), 0, s, g->off, g->rec,
                            t_e, slots, acc);
         PM_HIP(hipGetLastError());
         tmp.release(t_e);

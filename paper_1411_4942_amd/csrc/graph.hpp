@@ -7,17 +7,33 @@
 #include "common.hpp"
 #include "ladder.hpp"
 
+namespace pm {
+
+// What the samplers read about one slot s = (u, v) of the relabelled CSR, in
+// one 16-byte load: its column v with v's row offset and degree, and its own
+// row u.  A neighbour pick reads the record of the picked slot, so the picked
+// vertex arrives with the bounds of its row (no separate offset gathers).
+struct SlotRec {
+    uint32_t col;   // v
+    uint32_t coff;  // off[v]
+    uint32_t cdeg;  // d_v
+    uint32_t row;   // u
+};
+static_assert(sizeof(SlotRec) == 16, "slot record is 16 bytes");
+
+}  // namespace pm
+
 // Relabelled graph: vertex ids are positions in the degree order of Section 4
 // (degree, then input id), so "u before v" is integer u < v and every row is
-// sorted in that order.  Slot s is position s of the CSR; edge[s] holds its
-// row in the low and its column in the high 32 bits (one load for both).
+// sorted in that order.  Slot s is position s of the CSR; rec[s] is its
+// sampler record.
 struct pm_graph {
     int device = 0;
     int64_t n = 0;
     int64_t slots = 0;            // 2m
     uint32_t *off = nullptr;      // [n+1] (every slot index is below 2^32)
     uint32_t *col = nullptr;      // [slots]
-    uint64_t *edge = nullptr;     // [slots] row | col << 32
+    pm::SlotRec *rec = nullptr;   // [slots] column, its row offset and degree, row
     uint32_t *deg = nullptr;      // [n]
     int32_t *rank = nullptr;      // [n] input id -> relabelled id
     uint64_t *p_tau = nullptr;    // [slots] inclusive prefix of tau inside each kPrefixSeg-slot segment
@@ -68,7 +84,7 @@ struct SamplerView {
     const uint32_t *off;
     const uint32_t *col;
     Ladder ladder;
-    const uint64_t *edge;    // row | col << 32 per slot
+    const SlotRec *rec;      // per-slot records
     const uint64_t *P;       // inclusive prefix of the sampler's weights, per segment
     const uint64_t *Pseg;    // prefix before each segment
     const uint32_t *guide;   // guide[j] = first slot with P > j << shift
@@ -84,7 +100,7 @@ inline SamplerView view_of(const pm_graph *g, bool centered)
     v.ladder.top = g->ladder_top;
     v.ladder.lvl[0] = g->col;
     for (int l = 1; l < kLadderMax; ++l) v.ladder.lvl[l] = l <= g->ladder_top ? g->ladder + g->ladder_off[l] : nullptr;
-    v.edge = g->edge;
+    v.rec = g->rec;
     v.P = centered ? g->p_lam : g->p_tau;
     v.Pseg = centered ? g->seg_lam : g->seg_tau;
     v.guide = centered ? g->guide_lam : g->guide_tau;

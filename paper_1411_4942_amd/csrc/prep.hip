@@ -775,7 +775,8 @@ __global__ __launch_bounds__(kBlock) void k_weights_reduce(const uint64_t *__res
                                                            const uint32_t *__restrict__ rev,
                                                            const uint32_t *__restrict__ off, int64_t N,
                                                            uint64_t *__restrict__ p_tau,
-                                                           uint64_t *__restrict__ p_lam, U64x2 *__restrict__ seg_sums,
+                                                           uint64_t *__restrict__ p_lam,
+                                                           SlotRec *__restrict__ rec, U64x2 *__restrict__ seg_sums,
                                                            PrepStats *st)
 {
     const int w = threadIdx.x / kWave;
@@ -826,6 +827,11 @@ __global__ __launch_bounds__(kBlock) void k_weights_reduce(const uint64_t *__res
             }
             const U64x2 incl = wave_inclusive(U64x2{tau, lam}, PairSumOp(), U64x2{0, 0});
             if (idx < N) {
+                // the slot's sampler record: column, its row bounds, row
+                const uint32_t u = (uint32_t)e[i], v = (uint32_t)(e[i] >> 32);
+                typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+                const u32x4 r4 = {v, ov[i], ov1[i] - ov[i], u};
+                __builtin_nontemporal_store(r4, reinterpret_cast<u32x4 *>(rec) + idx);
                 // whole 512-byte rows per instruction, read again only by the
                 // guide pass and the samplers: stream them past the cache
                 __builtin_nontemporal_store(carry.a + incl.a, p_tau + idx);
@@ -1091,7 +1097,7 @@ const char *err_text(uint32_t e)
 void graph_free(pm_graph *g, hipStream_t s)
 {
     if (!g) return;
-    void *const arrays[] = {g->off,     g->col,     g->edge,      g->ladder,    g->deg,       g->rank,
+    void *const arrays[] = {g->off,     g->col,     g->rec,       g->ladder,    g->deg,       g->rank,
                             g->p_tau,   g->p_lam,   g->seg_tau,   g->seg_lam,   g->guide_tau, g->guide_lam,
                             g->alias_tau, g->alias_lam};
     dev_free_batch(arrays, sizeof(arrays) / sizeof(arrays[0]), s);
@@ -1108,7 +1114,7 @@ uint64_t graph_bytes_for(int64_t n, int64_t slots)
     uint64_t total = 0;
     for (int l = 1; l <= top; ++l) total += (ladder_count(slots, l) + 31) / 32 * 32;
     if (top > 0) b += 4 * (total + 32);
-    b += 12 * ss + 16 * ss;
+    b += 20 * ss + 16 * ss;  // col and slot records; both prefix arrays
     b += 2 * 8 * ((uint64_t)prefix_segments(slots) + 1);
     b += 2 * 4 * (guide_target(slots) + 1);
     return b;
@@ -1233,8 +1239,12 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
     // the column array is padded to whole 128-byte lines (ladder level 0)
     const int64_t ssp = (ss + 31) / 32 * 32 + 32;
     PM_TRY(dev_alloc((void **)&g->col, sizeof(uint32_t) * ssp, s));
-    PM_TRY(dev_alloc((void **)&g->edge, sizeof(uint64_t) * ss, s));
-    g->bytes += (sizeof(uint32_t) + sizeof(uint64_t)) * ss;
+    // (row, column) of every slot for the weights pass; the samplers read
+    // the slot records it writes
+    uint64_t *edge = nullptr;
+    PM_TRY(tmp.get(&edge, (size_t)ss));
+    PM_TRY(dev_alloc((void **)&g->rec, sizeof(SlotRec) * ss, s));
+    g->bytes += (sizeof(uint32_t) + sizeof(SlotRec)) * ss;
 
     // ladder levels 1..top, count(l) = ceil(slots / 32^l); top is the smallest
     // level whose single line covers every slot (32^(top+1) >= slots)
@@ -1267,41 +1277,41 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
         if (cls[1] > cls[0]) {
             ProfScope pc("build_rows.lane", s);
             hipLaunchKernelGGL(k_rows_group<16>, dim3((unsigned)((cls[1] - cls[0] + 15) / 16)), dim3(kBlock), 0, s,
-                               off_in, col_in, order, g->rank, g->off, n, cls[0], cls[1], g->col, g->edge, ladder1,
+                               off_in, col_in, order, g->rank, g->off, n, cls[0], cls[1], g->col, edge, ladder1,
                                st);
         }
         if (cls[2] > cls[1]) {
             ProfScope pc("build_rows.wave", s);
             hipLaunchKernelGGL(k_rows_group<64>, dim3((unsigned)((cls[2] - cls[1] + 3) / 4)), dim3(kBlock), 0, s,
-                               off_in, col_in, order, g->rank, g->off, n, cls[1], cls[2], g->col, g->edge, ladder1,
+                               off_in, col_in, order, g->rank, g->off, n, cls[1], cls[2], g->col, edge, ladder1,
                                st);
         }
         if (cls[3] > cls[2]) {
             ProfScope pc("build_rows.w128", s);
             hipLaunchKernelGGL(k_rows_bitonic<2>, dim3((unsigned)((cls[3] - cls[2] + 3) / 4)), dim3(kBlock), 0, s,
-                               off_in, col_in, order, g->rank, g->off, n, cls[2], cls[3], g->col, g->edge, ladder1,
+                               off_in, col_in, order, g->rank, g->off, n, cls[2], cls[3], g->col, edge, ladder1,
                                st);
         }
         if (cls[4] > cls[3]) {
             ProfScope pc("build_rows.w256", s);
             hipLaunchKernelGGL(k_rows_bitonic<4>, dim3((unsigned)((cls[4] - cls[3] + 3) / 4)), dim3(kBlock), 0, s,
-                               off_in, col_in, order, g->rank, g->off, n, cls[3], cls[4], g->col, g->edge, ladder1,
+                               off_in, col_in, order, g->rank, g->off, n, cls[3], cls[4], g->col, edge, ladder1,
                                st);
         }
         if (cls[5] > cls[4]) {
             ProfScope pc("build_rows.b1024", s);
             hipLaunchKernelGGL((k_rows_block<64, 16>), dim3((unsigned)(cls[5] - cls[4])), dim3(64), 0, s, off_in,
-                               col_in, order, g->rank, g->off, n, cls[4], vbits, g->col, g->edge, ladder1, st);
+                               col_in, order, g->rank, g->off, n, cls[4], vbits, g->col, edge, ladder1, st);
         }
         if (cls[6] > cls[5]) {
             ProfScope pc("build_rows.b4096", s);
             hipLaunchKernelGGL((k_rows_block<256, 16>), dim3((unsigned)(cls[6] - cls[5])), dim3(256), 0, s, off_in,
-                               col_in, order, g->rank, g->off, n, cls[5], vbits, g->col, g->edge, ladder1, st);
+                               col_in, order, g->rank, g->off, n, cls[5], vbits, g->col, edge, ladder1, st);
         }
         if (cls[7] > cls[6]) {
             ProfScope pc("build_rows.b8192", s);
             hipLaunchKernelGGL((k_rows_block<512, 16>), dim3((unsigned)(cls[7] - cls[6])), dim3(512), 0, s, off_in,
-                               col_in, order, g->rank, g->off, n, cls[6], vbits, g->col, g->edge, ladder1, st);
+                               col_in, order, g->rank, g->off, n, cls[6], vbits, g->col, edge, ladder1, st);
         }
         PM_HIP(hipGetLastError());
         // the rows above 8192 (one block of 1024 per row or chunk) run on two
@@ -1322,12 +1332,12 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
         if (cls[8] > cls[7]) {
             ProfScope pc("build_rows.b16384", side[1]);
             hipLaunchKernelGGL((k_rows_block<1024, 16>), dim3((unsigned)(cls[8] - cls[7])), dim3(1024), 0, side[1],
-                               off_in, col_in, order, g->rank, g->off, n, cls[7], vbits, g->col, g->edge, ladder1, st);
+                               off_in, col_in, order, g->rank, g->off, n, cls[7], vbits, g->col, edge, ladder1, st);
         }
         if (cls[9] > cls[8]) {
             ProfScope pc("build_rows.b32768", side[1]);
             hipLaunchKernelGGL((k_rows_block_reg<1024, 32>), dim3((unsigned)(cls[9] - cls[8])), dim3(1024), 0,
-                               side[1], off_in, col_in, order, g->rank, g->off, n, cls[8], vbits, g->col, g->edge,
+                               side[1], off_in, col_in, order, g->rank, g->off, n, cls[8], vbits, g->col, edge,
                                ladder1, st);
         }
         if (T > 0) {
@@ -1343,7 +1353,7 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
             uint32_t *src = run0, *dst = run1;
             for (int64_t L = kHubChunk; L < (int64_t)g->dmax; L *= 2) {
                 hipLaunchKernelGGL(k_hub_merge, dim3((unsigned)((T + kMergeTile - 1) / kMergeTile)), dim3(kBlock), 0,
-                                   side[0], src, dst, T, hstart, H, L, rt, cls[kRowClasses], g->col, g->edge,
+                                   side[0], src, dst, T, hstart, H, L, rt, cls[kRowClasses], g->col, edge,
                                    ladder1);
                 std::swap(src, dst);
             }
@@ -1409,8 +1419,8 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
         const int64_t tiles = (slots + (int64_t)kBlock * kWItems - 1) / ((int64_t)kBlock * kWItems);
         {
             ProfScope pr("weights.reduce", s);
-            hipLaunchKernelGGL(k_weights_reduce, dim3((unsigned)tiles), dim3(kBlock), 0, s, g->edge, rev, g->off,
-                               slots, g->p_tau, g->p_lam, sums, st);
+            hipLaunchKernelGGL(k_weights_reduce, dim3((unsigned)tiles), dim3(kBlock), 0, s, edge, rev, g->off,
+                               slots, g->p_tau, g->p_lam, g->rec, sums, st);
             PM_HIP(hipGetLastError());
         }
         PM_TRY((scan_launch<U64x2, 16>(SegIn{sums}, SegOut{g->seg_tau, g->seg_lam, nseg, &st->totals}, nseg,

@@ -34,11 +34,37 @@ __global__ __launch_bounds__(kBlock) void k_sample(SamplerView g, uint64_t seed,
     tally_flush(cnt, tally);
 }
 
+// The same samples with the adjacency tests done by the wave together
+// (ladder_contains_wave): the loop steps whole waves over the ids (over
+// ids[j] when SORTED), so every lane stays in it until the wave's last
+// round; lanes past k carry no sample.
+template <bool CENTERED, bool SORTED>
+__global__ __launch_bounds__(kBlock) void k_sample_wave(SamplerView g, uint64_t seed, uint64_t first, uint64_t k,
+                                                        const uint32_t *__restrict__ ids,
+                                                        unsigned long long *__restrict__ tally)
+{
+    uint32_t cnt[PM_NUM_TALLIES];
+#pragma unroll
+    for (int c = 0; c < PM_NUM_TALLIES; ++c) cnt[c] = 0;
+    const uint64_t lane = (uint64_t)lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = (uint64_t)gridDim.x * blockDim.x / kWave;
+    for (uint64_t base = wave * kWave; base < k; base += nwaves * kWave) {  // wave-uniform
+        const uint64_t j = base + lane;
+        const bool act = j < k;
+        const uint64_t id = first + (act ? (SORTED ? (uint64_t)ids[j] : j) : 0ull);
+        const uint32_t cls = sample_class_wave<CENTERED>(g, seed, id, act);
+        if (act) tally_add(cnt, cls);
+    }
+    tally_flush(cnt, tally);
+}
+
 // launch shape of the samplers (pm_set_sampler_shape)
 static std::atomic<int> g_samples_per_lane{1};
 static std::atomic<int> g_blocks_per_cu{4};
 static std::atomic<int> g_draw_order{1};  // draw-ordered sampling for large k (pm_set_draw_order)
 static std::atomic<uint64_t> g_draw_min{kSortedMinDefault};
+static std::atomic<int> g_search_mode{PM_SEARCH_LANE};  // adjacency tests (pm_set_search_mode)
 
 bool draw_order_enabled() { return g_draw_order.load() != 0; }
 uint64_t draw_order_min() { return g_draw_min.load(); }
@@ -47,6 +73,16 @@ pm_status set_draw_order(int32_t enabled, uint64_t min_samples)
 {
     g_draw_order.store(enabled ? 1 : 0);
     g_draw_min.store(min_samples ? min_samples : kSortedMinDefault);
+    return PM_OK;
+}
+
+pm_status set_search_mode(int32_t mode)
+{
+    if (mode != PM_SEARCH_LANE && mode != PM_SEARCH_WAVE) {
+        set_error("search mode: PM_SEARCH_LANE (0) or PM_SEARCH_WAVE (1)");
+        return PM_EINVAL;
+    }
+    g_search_mode.store(mode);
     return PM_OK;
 }
 
@@ -146,7 +182,14 @@ static pm_status launch_sorted(const pm_graph *g, const SamplerView &v, bool cen
                           nullptr, nullptr, false));  // only the ids are used
         {
             ProfScope pk(centered ? "sample_centered.sorted" : "sample_path.sorted", s);
-            if (centered)
+            if (g_search_mode.load() == PM_SEARCH_WAVE) {
+                if (centered)
+                    hipLaunchKernelGGL((k_sample_wave<true, true>), dim3(kb), dim3(kBlock), 0, s, v, seed, first + c0,
+                                       kc, ids, (unsigned long long *)tally);
+                else
+                    hipLaunchKernelGGL((k_sample_wave<false, true>), dim3(kb), dim3(kBlock), 0, s, v, seed,
+                                       first + c0, kc, ids, (unsigned long long *)tally);
+            } else if (centered)
                 hipLaunchKernelGGL((k_sample_sorted<true>), dim3(kb), dim3(kBlock), 0, s, v, seed, first + c0, kc, ids,
                                    (unsigned long long *)tally);
             else
@@ -170,6 +213,18 @@ static pm_status launch_sampler(const pm_graph *g, bool centered, uint64_t seed,
     ProfScope prof(centered ? "sample_centered" : "sample_path", s);
     if (k >= draw_order_min() && v.R > 1 && draw_order_enabled())
         return launch_sorted(g, v, centered, seed, first, k, tally, (unsigned)cap, s);
+    if (g_search_mode.load() == PM_SEARCH_WAVE) {
+        const uint64_t wants = (k + kBlock - 1) / kBlock;
+        const unsigned wb = (unsigned)std::max<uint64_t>(1, std::min(wants, cap));
+        if (centered)
+            hipLaunchKernelGGL((k_sample_wave<true, false>), dim3(wb), dim3(kBlock), 0, s, v, seed, first, k, nullptr,
+                               (unsigned long long *)tally);
+        else
+            hipLaunchKernelGGL((k_sample_wave<false, false>), dim3(wb), dim3(kBlock), 0, s, v, seed, first, k,
+                               nullptr, (unsigned long long *)tally);
+        PM_HIP(hipGetLastError());
+        return PM_OK;
+    }
     switch (U * 2 + (centered ? 1 : 0)) {
     case 2: launch_k_sample<false, 1>(blocks, s, v, seed, first, k, tally); break;
     case 3: launch_k_sample<true, 1>(blocks, s, v, seed, first, k, tally); break;

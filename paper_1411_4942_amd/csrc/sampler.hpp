@@ -9,50 +9,54 @@
 #pragma once
 
 #include "graph.hpp"
+#include "ladder_wave.hpp"
 
 namespace pm {
 
-// Bounds of the row to search for the pair (known, other): the row of the
-// smaller id; the offsets are loaded only when that row is not already in
-// registers.
-struct RowSearch {
-    uint32_t lo, hi, key;
+// The adjacency tests a sample still needs after its picks: three row
+// windows [lo, hi) with the key to look for, each the row of the pair's
+// smaller id (after the relabel the shorter or equal row).  3-path: x =
+// [u'~v], y = [u~v'], z = [u'~v']; centered: the same three, z first.
+struct SampleTests {
+    uint32_t lo[3], hi[3], key[3];
 };
 
-__device__ __forceinline__ RowSearch row_search(const uint32_t *__restrict__ off, uint32_t known, uint32_t klo,
-                                                uint32_t khi, uint32_t other)
+constexpr uint32_t kUndecided = 0xFFu;
+
+__device__ __forceinline__ void test_window(SampleTests &t, int i, uint32_t a, uint32_t alo, uint32_t ad, uint32_t b,
+                                            uint32_t blo, uint32_t bd)
 {
-    if (known < other) return RowSearch{klo, khi, other};
-    return RowSearch{(uint32_t)off[other], (uint32_t)off[other + 1], known};
+    const bool lo_a = a < b;
+    t.lo[i] = lo_a ? alo : blo;
+    t.hi[i] = t.lo[i] + (lo_a ? ad : bd);
+    t.key[i] = lo_a ? b : a;
 }
 
-__device__ __forceinline__ RowSearch row_search2(const uint32_t *__restrict__ off, uint32_t a, uint32_t b)
-{
-    const uint32_t x = a < b ? a : b;
-    return RowSearch{(uint32_t)off[x], (uint32_t)off[x + 1], a < b ? b : a};
-}
-
-// Tally index of the sample at slot s with offset o in [0, w_s) inside the
-// slot's weight w_s (Algorithms 1 and 3 from the picked edge on, classified
-// as in Algorithms 2 and 4).  w_s is read by the centered sampler only.
+// Algorithms 1 and 3 from the picked slot s on: the neighbour picks from the
+// offset o in [0, w_s) inside the slot's weight w_s (read by the centered
+// sampler only), and the adjacency tests that classify the sample as in
+// Algorithms 2 and 4.  Returns PM_TALLY_TRI when the picks coincide (the
+// triangle outcome), else kUndecided with the tests filled.  Every record
+// carries its column's row bounds, so each test knows its row without
+// another load.
 template <bool CENTERED>
-__device__ __forceinline__ uint32_t sample_decode(const SamplerView &g, uint32_t s, uint64_t o, uint64_t ws)
+__device__ __forceinline__ uint32_t sample_picks(const SamplerView &g, uint32_t s, uint64_t o, uint64_t ws,
+                                                 SampleTests &t)
 {
-    const uint64_t e = g.edge[s];
-    const uint32_t u = (uint32_t)e, v = (uint32_t)(e >> 32);
+    const SlotRec e = g.rec[s];
+    const uint32_t u = e.row, v = e.col, ov = e.coff, dv = e.cdeg;
     const uint32_t ou = (uint32_t)g.off[u], du = (uint32_t)g.off[u + 1] - ou;
-    const uint32_t ov = (uint32_t)g.off[v], dv = (uint32_t)g.off[v + 1] - ov;
     const uint32_t pos_v = s - ou;  // position of v in row u
 
-    uint32_t up, vp;
+    SlotRec pu, pv;  // the picked slots: u' = pu.col, v' = pv.col
     if (!CENTERED) {
         // o in [0, (d_u-1)(d_v-1)): u' is the a-th of N(u)\{v} (v's own
         // position stands for the row's last entry), v' the b-th of N(v)\{u}
         uint64_t a, b;
         divmod_small(o, dv - 1, a, b);
-        up = g.col[ou + ((uint32_t)a == pos_v ? du - 1 : (uint32_t)a)];
-        vp = g.col[ov + (uint32_t)b];
-        if (vp == u) vp = g.col[ov + dv - 1];
+        pu = g.rec[ou + ((uint32_t)a == pos_v ? du - 1 : (uint32_t)a)];
+        pv = g.rec[ov + (uint32_t)b];
+        if (pv.col == u) pv = g.rec[ov + dv - 1];
     } else {
         // o in [0, L_uv L_vu): u' among the L_uv neighbours of u after v, v'
         // among the L_vu neighbours of v after u (row suffixes)
@@ -60,30 +64,46 @@ __device__ __forceinline__ uint32_t sample_decode(const SamplerView &g, uint32_t
         uint64_t lvu, rem, a, b;
         divmod_small(ws, luv, lvu, rem);
         divmod_small(o, (uint32_t)lvu, a, b);
-        up = g.col[s + 1 + (uint32_t)a];
-        vp = g.col[ov + (dv - (uint32_t)lvu) + (uint32_t)b];
+        pu = g.rec[s + 1 + (uint32_t)a];
+        pv = g.rec[ov + (dv - (uint32_t)lvu) + (uint32_t)b];
     }
+    const uint32_t up = pu.col, vp = pv.col;
     if (up == vp) return PM_TALLY_TRI;
+    // centered: v < u' and u < v' by construction, so x and y search the
+    // rows of v and u
+    test_window(t, 0, up, pu.coff, pu.cdeg, v, ov, dv);
+    test_window(t, 1, u, ou, du, vp, pv.coff, pv.cdeg);
+    test_window(t, 2, up, pu.coff, pu.cdeg, vp, pv.coff, pv.cdeg);
+    return kUndecided;
+}
 
+// 3-path classification (Algorithm 2) from x = [u'~v], y = [u~v'],
+// z = [u'~v']: 3 edges: 3-path; 4: 4-cycle with the closing edge z, else
+// tailed triangle; 5: chordal-4-cycle; 6: 4-clique.
+__device__ __forceinline__ uint32_t classify_path(uint32_t x, uint32_t y, uint32_t z)
+{
+    const uint32_t edges = x + y + z;
+    return edges == 0 ? 2u : edges == 1 ? (z ? 4u : 3u) : edges == 2 ? 5u : 6u;
+}
+
+// Tally index of the sample at slot s (per-lane searches through the ladder).
+// Centered (Algorithm 4): centered iff u'~v' (Definition 4.1); then the
+// chords u'~v and u~v' give 4-cycle, chordal-4-cycle or 4-clique.
+template <bool CENTERED>
+__device__ __forceinline__ uint32_t sample_decode(const SamplerView &g, uint32_t s, uint64_t o, uint64_t ws)
+{
+    SampleTests t;
+    const uint32_t pre = sample_picks<CENTERED>(g, s, o, ws, t);
+    if (pre != kUndecided) return pre;
     if (!CENTERED) {
-        // x = [u'~v], y = [u~v'], z = [u'~v']
-        const RowSearch sx = row_search(g.off, v, ov, ov + dv, up);
-        const RowSearch sy = row_search(g.off, u, ou, ou + du, vp);
-        const RowSearch sz = row_search2(g.off, up, vp);
-        const uint32_t x = ladder_contains(g.ladder, sx.lo, sx.hi, sx.key);
-        const uint32_t y = ladder_contains(g.ladder, sy.lo, sy.hi, sy.key);
-        const uint32_t z = ladder_contains(g.ladder, sz.lo, sz.hi, sz.key);
-        const uint32_t edges = x + y + z;
-        // 3 edges: 3-path; 4: 4-cycle with the closing edge, else tailed
-        // triangle; 5: chordal-4-cycle; 6: 4-clique
-        return edges == 0 ? 2u : edges == 1 ? (z ? 4u : 3u) : edges == 2 ? 5u : 6u;
+        const uint32_t x = ladder_contains(g.ladder, t.lo[0], t.hi[0], t.key[0]) ? 1u : 0u;
+        const uint32_t y = ladder_contains(g.ladder, t.lo[1], t.hi[1], t.key[1]) ? 1u : 0u;
+        const uint32_t z = ladder_contains(g.ladder, t.lo[2], t.hi[2], t.key[2]) ? 1u : 0u;
+        return classify_path(x, y, z);
     } else {
-        // centered iff u'~v' (Definition 4.1); then the chords u'~v and u~v',
-        // searched in the rows of v and u (v < u' and u < v')
-        const RowSearch sz = row_search2(g.off, up, vp);
-        if (!ladder_contains(g.ladder, sz.lo, sz.hi, sz.key)) return PM_TALLY_OPEN;
-        const uint32_t x = ladder_contains(g.ladder, ov, ov + dv, up);
-        const uint32_t y = ladder_contains(g.ladder, ou, ou + du, vp);
+        if (!ladder_contains(g.ladder, t.lo[2], t.hi[2], t.key[2])) return PM_TALLY_OPEN;
+        const uint32_t x = ladder_contains(g.ladder, t.lo[0], t.hi[0], t.key[0]) ? 1u : 0u;
+        const uint32_t y = ladder_contains(g.ladder, t.lo[1], t.hi[1], t.key[1]) ? 1u : 0u;
         return 4u + x + y;
     }
 }
@@ -94,17 +114,20 @@ __device__ __forceinline__ uint64_t prefix_at(const SamplerView &g, uint32_t i)
     return g.P[i] + g.Pseg[i >> kPrefixSegShift];
 }
 
-// Tally index of sample `id` (R > 0; positions below 2^32): r exact uniform
-// in [0, R), its slot from the guide table and a short binary search.
+// The edge draw of sample `id` (R > 0; positions below 2^32): r exact
+// uniform in [0, R), its slot s = min{s : P[s] > r} from the guide table and
+// a short binary search, the offset o = r - P[s-1] inside the slot's weight,
+// and (centered only) that weight w_s.
 template <bool CENTERED>
-__device__ __forceinline__ uint32_t sample_class(const SamplerView &g, uint64_t seed, uint64_t id)
+__device__ __forceinline__ uint32_t sample_slot(const SamplerView &g, uint64_t seed, uint64_t id, uint64_t &o,
+                                                uint64_t &ws)
 {
     const uint64_t r = draw_bounded(seed, CENTERED ? 1u : 0u, id, g.R);
 
-    // edge draw: s = min{s : P[s] > r}, window from the guide table.  Inside
-    // one prefix segment the search compares the stored (segment) prefixes
-    // with r less the segment's offset: one offset load instead of one per
-    // probe (a window nearly always lies in one segment).
+    // window from the guide table.  Inside one prefix segment the search
+    // compares the stored (segment) prefixes with r less the segment's
+    // offset: one offset load instead of one per probe (a window nearly
+    // always lies in one segment).
     const uint64_t j = r >> g.shift;
     uint32_t lo = g.guide[j], hi = g.guide[j + 1];
     const uint32_t sg = lo >> kPrefixSegShift;
@@ -132,7 +155,48 @@ __device__ __forceinline__ uint32_t sample_class(const SamplerView &g, uint64_t 
     const bool first = (s & (kPrefixSeg - 1)) == 0;
     const uint64_t p_prev = first ? 0ull : g.P[s - 1];
     const uint64_t below = ((s >> kPrefixSegShift) == sg ? off_sg : g.Pseg[s >> kPrefixSegShift]) + p_prev;
-    return sample_decode<CENTERED>(g, s, r - below, CENTERED ? g.P[s] - p_prev : 0ull);
+    o = r - below;
+    ws = CENTERED ? g.P[s] - p_prev : 0ull;
+    return s;
+}
+
+// Tally index of sample `id` (R > 0), per-lane searches.
+template <bool CENTERED>
+__device__ __forceinline__ uint32_t sample_class(const SamplerView &g, uint64_t seed, uint64_t id)
+{
+    uint64_t o, ws;
+    const uint32_t s = sample_slot<CENTERED>(g, seed, id, o, ws);
+    return sample_decode<CENTERED>(g, s, o, ws);
+}
+
+// Tally index of the sample in this lane (`active`) with the adjacency tests
+// done by the wave together (ladder_contains_wave): every lane of the wave
+// must call it, lanes without a sample pass active = false (the result is
+// then meaningless).
+template <bool CENTERED>
+__device__ __forceinline__ uint32_t sample_class_wave(const SamplerView &g, uint64_t seed, uint64_t id, bool active)
+{
+    SampleTests t;
+    uint32_t cls = kUndecided;
+    if (active) {
+        uint64_t o, ws;
+        const uint32_t s = sample_slot<CENTERED>(g, seed, id, o, ws);
+        cls = sample_picks<CENTERED>(g, s, o, ws, t);
+    }
+    const bool need = active && cls == kUndecided;
+    if (!CENTERED) {
+        const uint32_t x = ladder_contains_wave(g.ladder, need, t.lo[0], t.hi[0], t.key[0]) ? 1u : 0u;
+        const uint32_t y = ladder_contains_wave(g.ladder, need, t.lo[1], t.hi[1], t.key[1]) ? 1u : 0u;
+        const uint32_t z = ladder_contains_wave(g.ladder, need, t.lo[2], t.hi[2], t.key[2]) ? 1u : 0u;
+        if (need) cls = classify_path(x, y, z);
+    } else {
+        const bool z = ladder_contains_wave(g.ladder, need, t.lo[2], t.hi[2], t.key[2]);
+        const bool chords = need && z;
+        const uint32_t x = ladder_contains_wave(g.ladder, chords, t.lo[0], t.hi[0], t.key[0]) ? 1u : 0u;
+        const uint32_t y = ladder_contains_wave(g.ladder, chords, t.lo[1], t.hi[1], t.key[1]) ? 1u : 0u;
+        if (need) cls = z ? 4u + x + y : (uint32_t)PM_TALLY_OPEN;
+    }
+    return cls;
 }
 
 // Draw-ordered sampling (pm_count, pm_sample_async, pm_count_alias): for at

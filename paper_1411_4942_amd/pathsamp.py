@@ -133,6 +133,7 @@ _SIGNATURES = {
     "pm_device_gather": (ctypes.c_int32, [_P, ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint64, _P]),
     "pm_set_sampler_shape": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32]),
     "pm_set_draw_order": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_uint64]),
+    "pm_set_search_mode": (ctypes.c_int32, [ctypes.c_int32]),
     "pm_release_cached_memory": (ctypes.c_int32, []),
     "pm_profile_enable": (ctypes.c_int32, [ctypes.c_int32]),
     "pm_profile_read": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
@@ -538,6 +539,14 @@ def set_draw_order(enabled: bool, min_samples: int = 0):
     """pm_set_draw_order: sort sample batches of at least min_samples (0: the
     default) by their draws first."""
     _check(lib().pm_set_draw_order(1 if enabled else 0, min_samples), "pm_set_draw_order")
+
+
+SEARCH_LANE, SEARCH_WAVE = 0, 1
+
+
+def set_search_mode(mode: int):
+    """pm_set_search_mode: adjacency tests per lane (0) or by the whole wave (1)."""
+    _check(lib().pm_set_search_mode(mode), "pm_set_search_mode")
 
 
 def set_sampler_shape(samples_per_lane: int, blocks_per_cu: int):
