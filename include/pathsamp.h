@@ -435,17 +435,21 @@ pm_status pm_set_draw_order(int32_t enabled, uint64_t min_samples);
 
 /* How pm_count and pm_sample_async run the adjacency tests of Algorithms 2
  * and 4 ("determine the subgraph induced by" the sampled path) in this
- * process: PM_SEARCH_LANE (0) searches each sample's row in its own lane
- * through the row search index (one 128-byte line per level, read as eight
- * 16-byte loads per lane); PM_SEARCH_WAVE (1) lets the 64 lanes of a wave
- * read each query's line together (two queries per coalesced load, a ballot
- * counts the entries at most the key).  Both give the same answers, so
- * tallies do not change.  Default PM_SEARCH_LANE: on MI355X the per-lane
- * search measured about three times faster (the cooperative rounds spend
- * their time in cross-lane instructions).  The batched, served and alias
- * paths always search per lane.  Errors: PM_EINVAL for another mode. */
+ * process.  The paper keeps adjacency in hash tables (Theorem 3.5); here:
+ * PM_SEARCH_HASH (2, the default) probes a per-row hash of the row's columns
+ * (open addressing at load 1/2, built with the graph): one aligned 16-byte
+ * read nearly always decides.  PM_SEARCH_LANE (0) searches the sorted row in
+ * each sample's own lane through the row search index (one 128-byte line per
+ * level, read as eight 16-byte loads per lane).  PM_SEARCH_WAVE (1) lets the
+ * 64 lanes of a wave read each query's index line together (two queries per
+ * coalesced load, a ballot counts the entries at most the key); on MI355X it
+ * measured about three times slower than PM_SEARCH_LANE (its rounds spend
+ * their time in cross-lane instructions).  All give the same answers, so
+ * tallies do not change.  The batched, served and alias paths always probe
+ * the row hash.  Errors: PM_EINVAL for another mode. */
 #define PM_SEARCH_LANE 0
 #define PM_SEARCH_WAVE 1
+#define PM_SEARCH_HASH 2
 pm_status pm_set_search_mode(int32_t mode);
 
 /* Device memory: the library keeps freed blocks for reuse (each tagged with
@@ -476,6 +480,19 @@ pm_status pm_device_copy(void *dst, const void *src, uint64_t bytes, void *strea
  * which the samplers' line traffic is read.  Table 4-byte aligned, at least
  * 4 bytes, count >= 0, else PM_EINVAL. */
 pm_status pm_device_gather(const void *table, uint64_t bytes, int64_t count, uint64_t seed, void *stream);
+
+/* The adjacency test of the samplers on its own (Algorithms 2 and 4
+ * "determine the subgraph induced by" the path): out[i] = 1 if relabelled
+ * vertices a[i] and b[i] are adjacent in the prepared graph, else 0, found
+ * with search mode `mode` (PM_SEARCH_LANE, PM_SEARCH_WAVE or PM_SEARCH_HASH;
+ * each searches the row of the smaller id, as the samplers do).  a, b and
+ * out are device arrays of `count` entries (ids in [0, n), a[i] != b[i];
+ * relabelled ids are positions in the degree order, see pm_graph_export's
+ * rank); asynchronous on `stream`.  Errors: PM_EINVAL (null arguments,
+ * count < 0, unknown mode), PM_EDEVICE.  Ids are not range-checked on the
+ * device: out-of-range ids are undefined behaviour. */
+pm_status pm_adjacent(const pm_graph *g, const int32_t *a, const int32_t *b, int64_t count, uint8_t *out,
+                      int32_t mode, void *stream);
 
 /* Per-kernel timing with HIP events recorded on each launch's stream.
  * pm_profile_enable clears the totals and switches recording on (1) or off

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpathsamp.so")
 FLAGS_NO_PACKED_F32 = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = ["alloc.cpp", "capi.cpp", "finalize.cpp", "profile.cpp", "streams.cpp", "prep.hip", "sample.hip", "batch.hip", "server.cpp", "ingest.hip", "exact.hip", "alias.hip"]
+SOURCES = ["alloc.cpp", "capi.cpp", "finalize.cpp", "profile.cpp", "streams.cpp", "prep.hip", "sample.hip", "batch.hip", "server.cpp", "ingest.hip", "exact.hip", "alias.hip", "rowhash.hip"]
 ARCH = "gfx950"
 
 

@@ -39,6 +39,8 @@ pm_status count_on_graph(const pm_graph *g, const pm_params *p, pm_result *out, 
 pm_status set_sampler_shape(int32_t samples_per_lane, int32_t blocks_per_cu);
 pm_status set_draw_order(int32_t enabled, uint64_t min_samples);
 pm_status set_search_mode(int32_t mode);
+pm_status adjacent(const pm_graph *g, const int32_t *a, const int32_t *b, int64_t count, uint8_t *out, int32_t mode,
+                   hipStream_t s);
 pm_status batch_create(const pm_graph *const *graphs, const pm_params *params, int32_t count, const pm_tune *tune,
                        hipStream_t user_stream, pm_batch **out);
 pm_status batch_set_params(pm_batch *b, const pm_params *params);
@@ -336,6 +338,12 @@ pm_status pm_device_copy(void *dst, const void *src, uint64_t bytes, void *strea
 pm_status pm_device_gather(const void *table, uint64_t bytes, int64_t count, uint64_t seed, void *stream)
 {
     PM_GUARD(return pm::device_gather(table, bytes, count, seed, (hipStream_t)stream);)
+}
+
+pm_status pm_adjacent(const pm_graph *g, const int32_t *a, const int32_t *b, int64_t count, uint8_t *out,
+                      int32_t mode, void *stream)
+{
+    PM_GUARD(return pm::adjacent(g, a, b, count, out, mode, (hipStream_t)stream);)
 }
 
 pm_status pm_philox_device(const uint32_t *in, uint32_t *out, int64_t count)

@@ -34,6 +34,7 @@ struct pm_graph {
     uint32_t *off = nullptr;      // [n+1] (every slot index is below 2^32)
     uint32_t *col = nullptr;      // [slots]
     pm::SlotRec *rec = nullptr;   // [slots] column, its row offset and degree, row
+    uint32_t *hash = nullptr;     // [2 slots + pad] row hash of the adjacency tests (rowhash.hpp)
     uint32_t *deg = nullptr;      // [n]
     int32_t *rank = nullptr;      // [n] input id -> relabelled id
     uint64_t *p_tau = nullptr;    // [slots] inclusive prefix of tau inside each kPrefixSeg-slot segment
@@ -85,6 +86,7 @@ struct SamplerView {
     const uint32_t *col;
     Ladder ladder;
     const SlotRec *rec;      // per-slot records
+    const uint32_t *hash;    // row hash (rowhash.hpp)
     const uint64_t *P;       // inclusive prefix of the sampler's weights, per segment
     const uint64_t *Pseg;    // prefix before each segment
     const uint32_t *guide;   // guide[j] = first slot with P > j << shift
@@ -101,6 +103,7 @@ inline SamplerView view_of(const pm_graph *g, bool centered)
     v.ladder.lvl[0] = g->col;
     for (int l = 1; l < kLadderMax; ++l) v.ladder.lvl[l] = l <= g->ladder_top ? g->ladder + g->ladder_off[l] : nullptr;
     v.rec = g->rec;
+    v.hash = g->hash;
     v.P = centered ? g->p_lam : g->p_tau;
     v.Pseg = centered ? g->seg_lam : g->seg_tau;
     v.guide = centered ? g->guide_lam : g->guide_tau;

@@ -12,6 +12,7 @@
 #include "graph.hpp"
 #include "profile.hpp"
 #include "radix.hpp"
+#include "rowhash.hpp"
 #include "streams.hpp"
 
 #include <algorithm>
@@ -736,6 +737,7 @@ __global__ void k_row_classes(const uint32_t *__restrict__ deg, const uint32_t *
             lo = mid + 1;
     }
     cls[c] = lo;
+    cls[kRowClasses + 1 + c] = off[lo];  // first slot of the class's rows
     if (c == kRowClasses - 1) cls[kRowClasses] = off[lo];
 }
 
@@ -1097,7 +1099,7 @@ const char *err_text(uint32_t e)
 void graph_free(pm_graph *g, hipStream_t s)
 {
     if (!g) return;
-    void *const arrays[] = {g->off,     g->col,     g->rec,       g->ladder,    g->deg,       g->rank,
+    void *const arrays[] = {g->off,     g->col,     g->rec,       g->hash,      g->ladder,    g->deg,       g->rank,
                             g->p_tau,   g->p_lam,   g->seg_tau,   g->seg_lam,   g->guide_tau, g->guide_lam,
                             g->alias_tau, g->alias_lam};
     dev_free_batch(arrays, sizeof(arrays) / sizeof(arrays[0]), s);
@@ -1106,6 +1108,9 @@ void graph_free(pm_graph *g, hipStream_t s)
 
 // Device bytes a prepared graph of n vertices and `slots` directed slots
 // holds (what graph_create adds up in pm_graph::bytes).
+pm_status build_rowhash(const pm_graph *g, const int64_t rows[5], const int64_t slot_at[5], uint32_t *H,
+                        hipStream_t s);
+
 uint64_t graph_bytes_for(int64_t n, int64_t slots)
 {
     const uint64_t nn = (uint64_t)std::max<int64_t>(n, 1), ss = (uint64_t)std::max<int64_t>(slots, 1);
@@ -1115,6 +1120,7 @@ uint64_t graph_bytes_for(int64_t n, int64_t slots)
     for (int l = 1; l <= top; ++l) total += (ladder_count(slots, l) + 31) / 32 * 32;
     if (top > 0) b += 4 * (total + 32);
     b += 20 * ss + 16 * ss;  // col and slot records; both prefix arrays
+    b += 4 * (2 * ss + (uint64_t)kHashPad);  // row hash
     b += 2 * 8 * ((uint64_t)prefix_segments(slots) + 1);
     b += 2 * 4 * (guide_target(slots) + 1);
     return b;
@@ -1265,12 +1271,12 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
     uint32_t *ladder1 = g->ladder_top > 0 ? g->ladder + g->ladder_off[1] : nullptr;
 
     // the rows, sorted where they are built (by size class)
+    int64_t cls[2 * kRowClasses + 1] = {0};  // first row of each class, then the hub rows' and classes' first slots
     if (slots > 0) {
         int64_t *cls_d = nullptr;
-        PM_TRY(tmp.get(&cls_d, kRowClasses + 1));
+        PM_TRY(tmp.get(&cls_d, 2 * kRowClasses + 1));
         hipLaunchKernelGGL(k_row_classes, dim3(1), dim3(kWave), 0, s, g->deg, g->off, n, cls_d);
         PM_HIP(hipGetLastError());
-        int64_t cls[kRowClasses + 1];
         PM_HIP(hipMemcpyAsync(cls, cls_d, sizeof(cls), hipMemcpyDeviceToHost, s));
         PM_HIP(hipStreamSynchronize(s));
         ProfScope prof("build_rows", s);
@@ -1379,6 +1385,25 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
                            g->ladder + g->ladder_off[l - 1], cnt, g->ladder + g->ladder_off[l]);
         PM_HIP(hipGetLastError());
     }
+    // the row hash of the adjacency tests (rows of degree <= 1024 many per
+    // block, longer ones in windows; rows above 4096 have several windows)
+    static_assert(kHashSmallBound == 1024, "row hash classes follow the row classes");
+    PM_TRY(dev_alloc((void **)&g->hash, sizeof(uint32_t) * (2 * ss + kHashPad), s));
+    g->bytes += sizeof(uint32_t) * (2 * ss + kHashPad);
+    // built on a side stream beside the reverse sort and the weights pass
+    // (it reads only the finished rows), joined back before returning
+    hipStream_t hside[2];
+    PM_HIP(side_streams(hside));
+    Fork hfork(s, hside, 1);
+    PM_HIP(hfork.status);
+    {
+        // row classes 0, 5..8: degree above 0, 1024, 4096, 8192, 16384
+        const int64_t rows[5] = {cls[0], cls[5], cls[6], cls[7], cls[8]};
+        const int64_t slot_at[5] = {cls[kRowClasses + 1 + 0], cls[kRowClasses + 1 + 5], cls[kRowClasses + 1 + 6],
+                                    cls[kRowClasses + 1 + 7], cls[kRowClasses + 1 + 8]};
+        PM_TRY(build_rowhash(g, rows, slot_at, g->hash, hside[0]));
+    }
+
     uint32_t *ka, *kb, *vfree, *v2a;
     PM_TRY(tmp.get(&ka, ss));
     PM_TRY(tmp.get(&kb, ss));
@@ -1479,6 +1504,7 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
         g->nb_lam = ((g->R_lam - 1) >> g->shift_lam) + 1;
     }
 
+    PM_HIP(hfork.join());
     PM_HIP(hipStreamSynchronize(s));
     guard.g = nullptr;
     *out = g;

@@ -15,7 +15,7 @@ namespace pm {
 
 // U samples per lane per round of the grid-stride loop (U > 1 only
 // unrolls the loop; each sample is independent).
-template <bool CENTERED, int U>
+template <bool CENTERED, int U, int SEARCH>
 __global__ __launch_bounds__(kBlock) void k_sample(SamplerView g, uint64_t seed, uint64_t first, uint64_t k,
                                                    unsigned long long *__restrict__ tally)
 {
@@ -28,7 +28,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(SamplerView g, uint64_t seed,
 #pragma unroll
         for (int q = 0; q < U; ++q) {
             const uint64_t i = base + (uint64_t)q * nthreads + tid;
-            if (i < k) tally_add(cnt, sample_class<CENTERED>(g, seed, first + i));
+            if (i < k) tally_add(cnt, sample_class<CENTERED, SEARCH>(g, seed, first + i));
         }
     }
     tally_flush(cnt, tally);
@@ -64,7 +64,7 @@ static std::atomic<int> g_samples_per_lane{1};
 static std::atomic<int> g_blocks_per_cu{4};
 static std::atomic<int> g_draw_order{1};  // draw-ordered sampling for large k (pm_set_draw_order)
 static std::atomic<uint64_t> g_draw_min{kSortedMinDefault};
-static std::atomic<int> g_search_mode{PM_SEARCH_LANE};  // adjacency tests (pm_set_search_mode)
+static std::atomic<int> g_search_mode{PM_SEARCH_HASH};  // adjacency tests (pm_set_search_mode)
 
 bool draw_order_enabled() { return g_draw_order.load() != 0; }
 uint64_t draw_order_min() { return g_draw_min.load(); }
@@ -78,8 +78,8 @@ pm_status set_draw_order(int32_t enabled, uint64_t min_samples)
 
 pm_status set_search_mode(int32_t mode)
 {
-    if (mode != PM_SEARCH_LANE && mode != PM_SEARCH_WAVE) {
-        set_error("search mode: PM_SEARCH_LANE (0) or PM_SEARCH_WAVE (1)");
+    if (mode != PM_SEARCH_LANE && mode != PM_SEARCH_WAVE && mode != PM_SEARCH_HASH) {
+        set_error("search mode: PM_SEARCH_LANE (0), PM_SEARCH_WAVE (1) or PM_SEARCH_HASH (2)");
         return PM_EINVAL;
     }
     g_search_mode.store(mode);
@@ -102,8 +102,12 @@ template <bool CENTERED, int U>
 static void launch_k_sample(unsigned blocks, hipStream_t s, const SamplerView &v, uint64_t seed, uint64_t first,
                             uint64_t k, uint64_t *tally)
 {
-    hipLaunchKernelGGL((k_sample<CENTERED, U>), dim3(blocks), dim3(kBlock), 0, s, v, seed, first, k,
-                       (unsigned long long *)tally);
+    if (g_search_mode.load() == PM_SEARCH_HASH)
+        hipLaunchKernelGGL((k_sample<CENTERED, U, PM_SEARCH_HASH>), dim3(blocks), dim3(kBlock), 0, s, v, seed, first,
+                           k, (unsigned long long *)tally);
+    else
+        hipLaunchKernelGGL((k_sample<CENTERED, U, PM_SEARCH_LANE>), dim3(blocks), dim3(kBlock), 0, s, v, seed, first,
+                           k, (unsigned long long *)tally);
 }
 
 int sampler_cu_count(int dev)
@@ -135,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void k_draw_keys(SamplerView g, uint64_t se
         keys[i] = (uint32_t)(draw_bounded(seed, CENTERED ? 1u : 0u, first + i, g.R) >> kshift);
 }
 
-template <bool CENTERED>
+template <bool CENTERED, int SEARCH>
 __global__ __launch_bounds__(kBlock) void k_sample_sorted(SamplerView g, uint64_t seed, uint64_t first, uint64_t k,
                                                           const uint32_t *__restrict__ ids,
                                                           unsigned long long *__restrict__ tally)
@@ -144,7 +148,7 @@ __global__ __launch_bounds__(kBlock) void k_sample_sorted(SamplerView g, uint64_
 #pragma unroll
     for (int c = 0; c < PM_NUM_TALLIES; ++c) cnt[c] = 0;
     for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < k; j += (uint64_t)gridDim.x * blockDim.x)
-        tally_add(cnt, sample_class<CENTERED>(g, seed, first + ids[j]));
+        tally_add(cnt, sample_class<CENTERED, SEARCH>(g, seed, first + ids[j]));
     tally_flush(cnt, tally);
 }
 
@@ -189,12 +193,19 @@ static pm_status launch_sorted(const pm_graph *g, const SamplerView &v, bool cen
                 else
                     hipLaunchKernelGGL((k_sample_wave<false, true>), dim3(kb), dim3(kBlock), 0, s, v, seed,
                                        first + c0, kc, ids, (unsigned long long *)tally);
+            } else if (g_search_mode.load() == PM_SEARCH_HASH) {
+                if (centered)
+                    hipLaunchKernelGGL((k_sample_sorted<true, PM_SEARCH_HASH>), dim3(kb), dim3(kBlock), 0, s, v, seed,
+                                       first + c0, kc, ids, (unsigned long long *)tally);
+                else
+                    hipLaunchKernelGGL((k_sample_sorted<false, PM_SEARCH_HASH>), dim3(kb), dim3(kBlock), 0, s, v,
+                                       seed, first + c0, kc, ids, (unsigned long long *)tally);
             } else if (centered)
-                hipLaunchKernelGGL((k_sample_sorted<true>), dim3(kb), dim3(kBlock), 0, s, v, seed, first + c0, kc, ids,
-                                   (unsigned long long *)tally);
+                hipLaunchKernelGGL((k_sample_sorted<true, PM_SEARCH_LANE>), dim3(kb), dim3(kBlock), 0, s, v, seed,
+                                   first + c0, kc, ids, (unsigned long long *)tally);
             else
-                hipLaunchKernelGGL((k_sample_sorted<false>), dim3(kb), dim3(kBlock), 0, s, v, seed, first + c0, kc,
-                                   ids, (unsigned long long *)tally);
+                hipLaunchKernelGGL((k_sample_sorted<false, PM_SEARCH_LANE>), dim3(kb), dim3(kBlock), 0, s, v, seed,
+                                   first + c0, kc, ids, (unsigned long long *)tally);
             PM_HIP(hipGetLastError());
         }
     }
@@ -238,6 +249,61 @@ static pm_status launch_sampler(const pm_graph *g, bool centered, uint64_t seed,
 }
 
 pm_status check_device(const pm_graph *g);
+
+// The samplers' adjacency test over a list of pairs (each in the row of the
+// smaller id, bounds from the offsets).
+template <int SEARCH>
+__global__ __launch_bounds__(kBlock) void k_adjacent(SamplerView g, const int32_t *__restrict__ a,
+                                                     const int32_t *__restrict__ b, int64_t count,
+                                                     uint8_t *__restrict__ out)
+{
+    const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+    // wave-uniform loop (the cooperative search needs every lane)
+    const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave * kWave;
+    for (int64_t base = wave0; base < count; base += nthreads) {
+        const int64_t i = base + lane_id();
+        const bool act = i < count;
+        SampleTests t;
+        if (act) {
+            const uint32_t x = (uint32_t)a[i], y = (uint32_t)b[i];
+            const uint32_t lo = x < y ? x : y;
+            t.lo[0] = g.off[lo];
+            t.hi[0] = g.off[lo + 1];
+            t.key[0] = x < y ? y : x;
+        }
+        uint32_t r;
+        if (SEARCH == PM_SEARCH_WAVE)
+            r = ladder_contains_wave(g.ladder, act, t.lo[0], t.hi[0], t.key[0]) ? 1u : 0u;
+        else
+            r = act ? row_contains<SEARCH>(g, t, 0) : 0u;
+        if (act) out[i] = (uint8_t)r;
+    }
+}
+
+pm_status adjacent(const pm_graph *g, const int32_t *a, const int32_t *b, int64_t count, uint8_t *out, int32_t mode,
+                   hipStream_t s)
+{
+    if (!g || count < 0 || (count > 0 && (!a || !b || !out))) {
+        set_error("adjacent: null argument or negative count");
+        return PM_EINVAL;
+    }
+    if (mode != PM_SEARCH_LANE && mode != PM_SEARCH_WAVE && mode != PM_SEARCH_HASH) {
+        set_error("adjacent: unknown search mode");
+        return PM_EINVAL;
+    }
+    PM_TRY(check_device(g));
+    if (count == 0) return PM_OK;
+    const SamplerView v = view_of(g, false);
+    const unsigned blocks = (unsigned)grid_for(count, kBlock, 1 << 16);
+    if (mode == PM_SEARCH_HASH)
+        hipLaunchKernelGGL((k_adjacent<PM_SEARCH_HASH>), dim3(blocks), dim3(kBlock), 0, s, v, a, b, count, out);
+    else if (mode == PM_SEARCH_WAVE)
+        hipLaunchKernelGGL((k_adjacent<PM_SEARCH_WAVE>), dim3(blocks), dim3(kBlock), 0, s, v, a, b, count, out);
+    else
+        hipLaunchKernelGGL((k_adjacent<PM_SEARCH_LANE>), dim3(blocks), dim3(kBlock), 0, s, v, a, b, count, out);
+    PM_HIP(hipGetLastError());
+    return PM_OK;
+}
 
 pm_status sample_async(const pm_graph *g, const pm_params *p, uint64_t *tallies_dev, hipStream_t s)
 {

@@ -10,6 +10,7 @@
 
 #include "graph.hpp"
 #include "ladder_wave.hpp"
+#include "rowhash.hpp"
 
 namespace pm {
 
@@ -86,24 +87,34 @@ __device__ __forceinline__ uint32_t classify_path(uint32_t x, uint32_t y, uint32
     return edges == 0 ? 2u : edges == 1 ? (z ? 4u : 3u) : edges == 2 ? 5u : 6u;
 }
 
-// Tally index of the sample at slot s (per-lane searches through the ladder).
-// Centered (Algorithm 4): centered iff u'~v' (Definition 4.1); then the
-// chords u'~v and u~v' give 4-cycle, chordal-4-cycle or 4-clique.
-template <bool CENTERED>
+// One adjacency test of a sample in this lane: key in the row window
+// [lo, hi)?  SEARCH = PM_SEARCH_HASH probes the row hash, PM_SEARCH_LANE
+// walks the ladder index; both give the same answer.
+template <int SEARCH>
+__device__ __forceinline__ uint32_t row_contains(const SamplerView &g, const SampleTests &t, int i)
+{
+    if (SEARCH == PM_SEARCH_HASH) return rowhash_contains(g.hash, t.lo[i], t.hi[i] - t.lo[i], t.key[i]) ? 1u : 0u;
+    return ladder_contains(g.ladder, t.lo[i], t.hi[i], t.key[i]) ? 1u : 0u;
+}
+
+// Tally index of the sample at slot s (per-lane searches).  Centered
+// (Algorithm 4): centered iff u'~v' (Definition 4.1); then the chords u'~v
+// and u~v' give 4-cycle, chordal-4-cycle or 4-clique.
+template <bool CENTERED, int SEARCH = PM_SEARCH_HASH>
 __device__ __forceinline__ uint32_t sample_decode(const SamplerView &g, uint32_t s, uint64_t o, uint64_t ws)
 {
     SampleTests t;
     const uint32_t pre = sample_picks<CENTERED>(g, s, o, ws, t);
     if (pre != kUndecided) return pre;
     if (!CENTERED) {
-        const uint32_t x = ladder_contains(g.ladder, t.lo[0], t.hi[0], t.key[0]) ? 1u : 0u;
-        const uint32_t y = ladder_contains(g.ladder, t.lo[1], t.hi[1], t.key[1]) ? 1u : 0u;
-        const uint32_t z = ladder_contains(g.ladder, t.lo[2], t.hi[2], t.key[2]) ? 1u : 0u;
+        const uint32_t x = row_contains<SEARCH>(g, t, 0);
+        const uint32_t y = row_contains<SEARCH>(g, t, 1);
+        const uint32_t z = row_contains<SEARCH>(g, t, 2);
         return classify_path(x, y, z);
     } else {
-        if (!ladder_contains(g.ladder, t.lo[2], t.hi[2], t.key[2])) return PM_TALLY_OPEN;
-        const uint32_t x = ladder_contains(g.ladder, t.lo[0], t.hi[0], t.key[0]) ? 1u : 0u;
-        const uint32_t y = ladder_contains(g.ladder, t.lo[1], t.hi[1], t.key[1]) ? 1u : 0u;
+        if (!row_contains<SEARCH>(g, t, 2)) return PM_TALLY_OPEN;
+        const uint32_t x = row_contains<SEARCH>(g, t, 0);
+        const uint32_t y = row_contains<SEARCH>(g, t, 1);
         return 4u + x + y;
     }
 }
@@ -161,12 +172,12 @@ __device__ __forceinline__ uint32_t sample_slot(const SamplerView &g, uint64_t s
 }
 
 // Tally index of sample `id` (R > 0), per-lane searches.
-template <bool CENTERED>
+template <bool CENTERED, int SEARCH = PM_SEARCH_HASH>
 __device__ __forceinline__ uint32_t sample_class(const SamplerView &g, uint64_t seed, uint64_t id)
 {
     uint64_t o, ws;
     const uint32_t s = sample_slot<CENTERED>(g, seed, id, o, ws);
-    return sample_decode<CENTERED>(g, s, o, ws);
+    return sample_decode<CENTERED, SEARCH>(g, s, o, ws);
 }
 
 // Tally index of the sample in this lane (`active`) with the adjacency tests

@@ -134,6 +134,7 @@ _SIGNATURES = {
     "pm_set_sampler_shape": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32]),
     "pm_set_draw_order": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_uint64]),
     "pm_set_search_mode": (ctypes.c_int32, [ctypes.c_int32]),
+    "pm_adjacent": (ctypes.c_int32, [_P, _P, _P, ctypes.c_int64, _P, ctypes.c_int32, _P]),
     "pm_release_cached_memory": (ctypes.c_int32, []),
     "pm_profile_enable": (ctypes.c_int32, [ctypes.c_int32]),
     "pm_profile_read": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
@@ -353,6 +354,19 @@ class Graph:
         _check(lib().pm_sample_async(self._h, ctypes.byref(p), ctypes.c_void_p(tallies.data_ptr()),
                                      _stream_ptr(stream)), "pm_sample_async")
 
+    def adjacent(self, a, b, mode: int = 2, stream=None):
+        """pm_adjacent: uint8 tensor, 1 where relabelled ids a[i], b[i] are
+        adjacent (a, b int32 CUDA tensors of one length)."""
+        import torch
+
+        assert a.is_cuda and b.is_cuda and a.dtype == torch.int32 and b.dtype == torch.int32
+        assert a.numel() == b.numel()
+        a, b = a.contiguous(), b.contiguous()
+        out = torch.empty(a.numel(), dtype=torch.uint8, device=a.device)
+        _check(lib().pm_adjacent(self._h, a.data_ptr(), b.data_ptr(), a.numel(), out.data_ptr(), mode,
+                                 _stream_ptr(stream)), "pm_adjacent")
+        return out
+
     def destroy(self):
         if getattr(self, "_h", None) and self._h.value:
             _check(lib().pm_graph_destroy(self._h), "pm_graph_destroy")
@@ -541,11 +555,12 @@ def set_draw_order(enabled: bool, min_samples: int = 0):
     _check(lib().pm_set_draw_order(1 if enabled else 0, min_samples), "pm_set_draw_order")
 
 
-SEARCH_LANE, SEARCH_WAVE = 0, 1
+SEARCH_LANE, SEARCH_WAVE, SEARCH_HASH = 0, 1, 2
 
 
 def set_search_mode(mode: int):
-    """pm_set_search_mode: adjacency tests per lane (0) or by the whole wave (1)."""
+    """pm_set_search_mode: adjacency tests through the sorted rows per lane (0)
+    or by the whole wave (1), or through the row hash (2, the default)."""
     _check(lib().pm_set_search_mode(mode), "pm_set_search_mode")
 
 

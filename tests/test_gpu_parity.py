@@ -90,9 +90,9 @@ def test_prep_and_tallies_bit_exact(name, graph):
     off, col = graph
     og, g = _check_prep(name, off, col)
     try:
-        # both ways of running the adjacency tests (the per-lane search is
-        # the default)
-        for mode in (ps.SEARCH_LANE, ps.SEARCH_WAVE):
+        # every way of running the adjacency tests (the row hash is the
+        # default)
+        for mode in (ps.SEARCH_HASH, ps.SEARCH_LANE, ps.SEARCH_WAVE):
             ps.set_search_mode(mode)
             for seed, kp, kc, fp, fc in [(1, 20000, 20000, 0, 0), (0xDEADBEEFCAFEF00D, 777, 1234, 5, 2 ** 33 + 7)]:
                 got = g.count(kp, kc, seed=seed, first_path=fp, first_cent=fc)
@@ -103,9 +103,9 @@ def test_prep_and_tallies_bit_exact(name, graph):
                     assert got["est"][i] == pytest.approx(want["est"][i], rel=1e-12, abs=1e-9)
                     assert got["est_basic"][i] == pytest.approx(want["est_basic"][i], rel=1e-12, abs=1e-9)
     finally:
-        ps.set_search_mode(ps.SEARCH_LANE)
+        ps.set_search_mode(ps.SEARCH_HASH)
     with pytest.raises(ps.PathSampError):
-        ps.set_search_mode(2)
+        ps.set_search_mode(3)
     g.destroy()
 
 
@@ -380,10 +380,11 @@ def test_draw_order_does_not_change_tallies():
         a = g.count(k, k, seed=3, first_path=7, first_cent=2 ** 33)
         assert a["tally_path"] == og.sample_path(3, k, 7).tolist()
         assert a["tally_cent"] == og.sample_centered(3, k, 2 ** 33).tolist()
-        ps.set_search_mode(ps.SEARCH_WAVE)  # the wave-cooperative search over draw-ordered ids
-        a2 = g.count(k, k, seed=3, first_path=7, first_cent=2 ** 33)
-        ps.set_search_mode(ps.SEARCH_LANE)
-        assert a2["tally_path"] == a["tally_path"] and a2["tally_cent"] == a["tally_cent"]
+        for mode in (ps.SEARCH_LANE, ps.SEARCH_WAVE):  # the sorted-row searches over draw-ordered ids
+            ps.set_search_mode(mode)
+            a2 = g.count(k, k, seed=3, first_path=7, first_cent=2 ** 33)
+            assert a2["tally_path"] == a["tally_path"] and a2["tally_cent"] == a["tally_cent"], mode
+        ps.set_search_mode(ps.SEARCH_HASH)
         k2 = (1 << 24) * 2 + 777  # three sort chunks, the last one ragged
         on = g.count(k2, k2, seed=9)
         ps.set_draw_order(False)
@@ -391,7 +392,7 @@ def test_draw_order_does_not_change_tallies():
         off_ = g.count(k2, k2, seed=9)
     finally:
         ps.set_draw_order(True, 0)
-        ps.set_search_mode(ps.SEARCH_LANE)
+        ps.set_search_mode(ps.SEARCH_HASH)
     assert a["tally_path"] == b["tally_path"] and a["tally_cent"] == b["tally_cent"]
     assert on["tally_path"] == off_["tally_path"] and on["tally_cent"] == off_["tally_cent"]
     g.destroy()
