@@ -158,6 +158,25 @@ pm_status pm_graph_destroy(pm_graph *g);
  * estimates and bars are exactly 0.  k_path = k_cent = 0 is PM_EINVAL. */
 pm_status pm_count(const pm_graph *g, const pm_params *p, pm_result *out, void *stream);
 
+/* pm_count for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same samples, tallies and results as pm_count, with every device buffer
+ * it needs in a fixed array inside the library instead of allocated: both
+ * samplers' tallies and the buffers of one draw-order sort chunk of 2^22
+ * sample ids, 82 MiB in all (pm_static_scratch_bytes).  Each device the
+ * library runs on holds its own copy of the array until the process ends.
+ * Budgets above one chunk are sorted and sampled chunk by chunk, so no k is
+ * rejected for size.  The call allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine); the array keeps the last call's contents and
+ * the tallies are cleared at the start of each call.  Every call on one
+ * device shares that device's array: calls that overlap on one device (from
+ * several host threads or streams) race, so the caller serialises them.
+ * Synchronises `stream`.  Errors as pm_count (PM_EINVAL, PM_EDEVICE). */
+pm_status pm_count_noalloc(const pm_graph *g, const pm_params *p, pm_result *out, void *stream);
+
+/* Bytes of the fixed per-device array pm_count_noalloc uses. */
+uint64_t pm_static_scratch_bytes(void);
+
 /* Alias-table edge draw: the variant of the weighted edge pick of
  * Algorithm 1 step 2 and Algorithm 3 step 2 by Walker's alias method (the
  * paper leaves the mechanism open).  pm_graph_build_alias adds one table per

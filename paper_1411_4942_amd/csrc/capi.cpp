@@ -39,6 +39,8 @@ pm_status count_on_graph(const pm_graph *g, const pm_params *p, pm_result *out, 
 pm_status set_sampler_shape(int32_t samples_per_lane, int32_t blocks_per_cu);
 pm_status set_draw_order(int32_t enabled, uint64_t min_samples);
 pm_status set_search_mode(int32_t mode);
+pm_status count_noalloc(const pm_graph *g, const pm_params *p, pm_result *out, hipStream_t s);
+size_t static_scratch_bytes();
 pm_status adjacent(const pm_graph *g, const int32_t *a, const int32_t *b, int64_t count, uint8_t *out, int32_t mode,
                    hipStream_t s);
 pm_status batch_create(const pm_graph *const *graphs, const pm_params *params, int32_t count, const pm_tune *tune,
@@ -144,6 +146,13 @@ pm_status pm_count(const pm_graph *g, const pm_params *p, pm_result *out, void *
 {
     PM_GUARD(return pm::count_on_graph(g, p, out, (hipStream_t)stream);)
 }
+
+pm_status pm_count_noalloc(const pm_graph *g, const pm_params *p, pm_result *out, void *stream)
+{
+    PM_GUARD(return pm::count_noalloc(g, p, out, (hipStream_t)stream);)
+}
+
+uint64_t pm_static_scratch_bytes(void) { return (uint64_t)pm::static_scratch_bytes(); }
 
 pm_status pm_graph_build_alias(pm_graph *g, void *stream)
 {

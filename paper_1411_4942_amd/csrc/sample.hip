@@ -152,37 +152,35 @@ __global__ __launch_bounds__(kBlock) void k_sample_sorted(SamplerView g, uint64_
     tally_flush(cnt, tally);
 }
 
-static pm_status launch_sorted(const pm_graph *g, const SamplerView &v, bool centered, uint64_t seed,
-                               uint64_t first, uint64_t k, uint64_t *tally, unsigned blocks, hipStream_t s)
+// Device buffers of the draw-ordered launch: draw keys, the radix sort's
+// key/id ping-pong arrays of `chunk` entries each, and its scratch.
+struct SortBufs {
+    uint32_t *kin, *k0, *v0, *k1, *v1;
+    void *scr;
+    uint64_t chunk;
+};
+
+static pm_status launch_sorted_in(const SamplerView &v, bool centered, uint64_t seed, uint64_t first, uint64_t k,
+                                  uint64_t *tally, unsigned blocks, hipStream_t s, const SortBufs &b)
 {
     const int rbits = bits_for(v.R - 1);  // r < R
     const int kshift = rbits > kDrawKeyBits ? rbits - kDrawKeyBits : 0;
     const int kbits = rbits - kshift;
-    const uint64_t chunk = std::min<uint64_t>(k, kSortedChunk);
-    Temps tmp(s);
-    uint32_t *kin, *k0, *v0, *k1, *v1;
-    char *scr = nullptr;
-    PM_TRY(tmp.get(&kin, (size_t)chunk));
-    PM_TRY(tmp.get(&k0, (size_t)chunk));
-    PM_TRY(tmp.get(&v0, (size_t)chunk));
-    PM_TRY(tmp.get(&k1, (size_t)chunk));
-    PM_TRY(tmp.get(&v1, (size_t)chunk));
-    PM_TRY(tmp.get(&scr, radix_scratch_bytes((int64_t)chunk)));
-    for (uint64_t c0 = 0; c0 < k; c0 += chunk) {
-        const uint64_t kc = std::min(chunk, k - c0);
+    for (uint64_t c0 = 0; c0 < k; c0 += b.chunk) {
+        const uint64_t kc = std::min(b.chunk, k - c0);
         const unsigned kb = (unsigned)std::min<uint64_t>((kc + kBlock - 1) / kBlock, blocks);
         {
             ProfScope pd("draw_keys", s);
             if (centered)
                 hipLaunchKernelGGL((k_draw_keys<true>), dim3(kb), dim3(kBlock), 0, s, v, seed, first + c0, kc, kshift,
-                                   kin);
+                                   b.kin);
             else
                 hipLaunchKernelGGL((k_draw_keys<false>), dim3(kb), dim3(kBlock), 0, s, v, seed, first + c0, kc, kshift,
-                                   kin);
+                                   b.kin);
             PM_HIP(hipGetLastError());
         }
         uint32_t *ks = nullptr, *ids = nullptr;
-        PM_TRY(radix_sort("draw_sort", kin, nullptr, k0, v0, k1, v1, (int64_t)kc, kbits, scr, s, &ks, &ids,
+        PM_TRY(radix_sort("draw_sort", b.kin, nullptr, b.k0, b.v0, b.k1, b.v1, (int64_t)kc, kbits, b.scr, s, &ks, &ids,
                           nullptr, nullptr, false));  // only the ids are used
         {
             ProfScope pk(centered ? "sample_centered.sorted" : "sample_path.sorted", s);
@@ -212,8 +210,30 @@ static pm_status launch_sorted(const pm_graph *g, const SamplerView &v, bool cen
     return PM_OK;
 }
 
+// the draw-ordered launch with its buffers from the stream-ordered allocator
+static pm_status launch_sorted(const SamplerView &v, bool centered, uint64_t seed, uint64_t first, uint64_t k,
+                               uint64_t *tally, unsigned blocks, hipStream_t s)
+{
+    const uint64_t chunk = std::min<uint64_t>(k, kSortedChunk);
+    Temps tmp(s);
+    SortBufs b{};
+    char *scr = nullptr;
+    PM_TRY(tmp.get(&b.kin, (size_t)chunk));
+    PM_TRY(tmp.get(&b.k0, (size_t)chunk));
+    PM_TRY(tmp.get(&b.v0, (size_t)chunk));
+    PM_TRY(tmp.get(&b.k1, (size_t)chunk));
+    PM_TRY(tmp.get(&b.v1, (size_t)chunk));
+    PM_TRY(tmp.get(&scr, radix_scratch_bytes((int64_t)chunk)));
+    b.scr = scr;
+    b.chunk = chunk;
+    return launch_sorted_in(v, centered, seed, first, k, tally, blocks, s, b);
+}
+
+// One sampler's k samples from id `first` into tally (device, added to).
+// Draw-ordered launches take their buffers from `fixed` when given, else
+// from the allocator.
 static pm_status launch_sampler(const pm_graph *g, bool centered, uint64_t seed, uint64_t first, uint64_t k,
-                                uint64_t *tally, hipStream_t s)
+                                uint64_t *tally, hipStream_t s, const SortBufs *fixed = nullptr)
 {
     const SamplerView v = view_of(g, centered);
     if (v.R == 0 || k == 0) return PM_OK;
@@ -223,7 +243,8 @@ static pm_status launch_sampler(const pm_graph *g, bool centered, uint64_t seed,
     const unsigned blocks = (unsigned)std::max<uint64_t>(1, std::min(want, cap));
     ProfScope prof(centered ? "sample_centered" : "sample_path", s);
     if (k >= draw_order_min() && v.R > 1 && draw_order_enabled())
-        return launch_sorted(g, v, centered, seed, first, k, tally, (unsigned)cap, s);
+        return fixed ? launch_sorted_in(v, centered, seed, first, k, tally, (unsigned)cap, s, *fixed)
+                     : launch_sorted(v, centered, seed, first, k, tally, (unsigned)cap, s);
     if (g_search_mode.load() == PM_SEARCH_WAVE) {
         const uint64_t wants = (k + kBlock - 1) / kBlock;
         const unsigned wb = (unsigned)std::max<uint64_t>(1, std::min(wants, cap));
@@ -486,6 +507,96 @@ pm_status count_with(const pm_graph *g, const pm_params *p, pm_result *out, hipS
 pm_status count_on_graph(const pm_graph *g, const pm_params *p, pm_result *out, hipStream_t s)
 {
     return count_with(g, p, out, s, sample_async);
+}
+
+// ---------------------------------------------------------------------------
+// pm_count_noalloc: pm_count with its device scratch in a fixed array of the
+// library (for callers that cannot allocate).  The array holds both
+// samplers' tallies and the buffers of one draw-order sort chunk of
+// kStaticChunk ids; larger budgets are sorted and sampled chunk by chunk.
+// Each device the library runs on keeps its own copy of the array for the
+// life of the process; every call on a device shares it.
+// ---------------------------------------------------------------------------
+
+constexpr uint64_t kStaticChunk = 1ull << 22;
+constexpr size_t kStaticTallyBytes = 256;  // 2 x PM_NUM_TALLIES u64, padded to 256
+constexpr size_t kStaticRadixBytes = 2u << 20;
+constexpr size_t kStaticScratchBytes = kStaticTallyBytes + 5 * sizeof(uint32_t) * kStaticChunk + kStaticRadixBytes;
+static_assert(2 * PM_NUM_TALLIES * sizeof(uint64_t) <= kStaticTallyBytes, "tallies fit their slice");
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+// the device address of this device's copy of `scratch` (looked up once per
+// device, with that device current; host code never uses the symbol's name
+// as an address)
+static pm_status scratch_on_device(int dev, unsigned char **out)
+{
+    static std::mutex mu;
+    static unsigned char *ptr[64] = {nullptr};
+    if (dev < 0 || dev >= 64) {
+        set_error("pm_count_noalloc: device index out of range");
+        return PM_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error(std::string("pm_count_noalloc: hipGetSymbolAddress: ") + hipGetErrorString(e));
+            return PM_EDEVICE;
+        }
+        ptr[dev] = (unsigned char *)p;
+    }
+    *out = ptr[dev];
+    return PM_OK;
+}
+
+size_t static_scratch_bytes() { return kStaticScratchBytes; }
+
+pm_status count_noalloc(const pm_graph *g, const pm_params *p, pm_result *out, hipStream_t s)
+{
+    if (!g || !p || !out) {
+        set_error("null argument");
+        return PM_EINVAL;
+    }
+    if (p->k_path == 0 && p->k_cent == 0) {
+        set_error("k_path and k_cent are both 0");
+        return PM_EINVAL;
+    }
+    if (!(p->delta > 0.0 && p->delta < 1.0)) {
+        set_error("delta must lie in (0,1)");
+        return PM_EINVAL;
+    }
+    PM_TRY(check_device(g));
+    if (radix_scratch_bytes((int64_t)kStaticChunk) > kStaticRadixBytes) {
+        set_error("pm_count_noalloc: the sort chunk's radix scratch exceeds its fixed slice");
+        return PM_EDEVICE;
+    }
+    unsigned char *base = nullptr;
+    PM_TRY(scratch_on_device(g->device, &base));
+    uint64_t *tally = reinterpret_cast<uint64_t *>(base);
+    uint32_t *ids = reinterpret_cast<uint32_t *>(base + kStaticTallyBytes);
+    SortBufs b{};
+    b.kin = ids;
+    b.k0 = ids + kStaticChunk;
+    b.v0 = ids + 2 * kStaticChunk;
+    b.k1 = ids + 3 * kStaticChunk;
+    b.v1 = ids + 4 * kStaticChunk;
+    b.scr = ids + 5 * kStaticChunk;
+    b.chunk = kStaticChunk;
+    // the tallies keep the last call's contents: clear them (a fill kernel)
+    PM_TRY(fill_async<uint64_t>(tally, 0ull, 2 * PM_NUM_TALLIES, s));
+    PM_TRY(launch_sampler(g, false, p->seed, p->first_id_path, p->k_path, tally, s, &b));
+    PM_TRY(launch_sampler(g, true, p->seed, p->first_id_cent, p->k_cent, tally + PM_NUM_TALLIES, s, &b));
+    uint64_t host[2 * PM_NUM_TALLIES];
+    hipError_t e = hipMemcpyAsync(host, tally, sizeof(host), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        set_error(std::string("pm_count_noalloc: ") + hipGetErrorString(e));
+        return PM_EDEVICE;
+    }
+    return finalize(host, host + PM_NUM_TALLIES, g->R_tau / 2, g->R_lam / 2, g->N1, p->k_path, p->k_cent, p->delta,
+                    out);
 }
 
 }  // namespace pm

@@ -134,6 +134,8 @@ _SIGNATURES = {
     "pm_set_sampler_shape": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32]),
     "pm_set_draw_order": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_uint64]),
     "pm_set_search_mode": (ctypes.c_int32, [ctypes.c_int32]),
+    "pm_count_noalloc": (ctypes.c_int32, [_P, ctypes.POINTER(Params), ctypes.POINTER(Result), _P]),
+    "pm_static_scratch_bytes": (ctypes.c_uint64, []),
     "pm_adjacent": (ctypes.c_int32, [_P, _P, _P, ctypes.c_int64, _P, ctypes.c_int32, _P]),
     "pm_release_cached_memory": (ctypes.c_int32, []),
     "pm_profile_enable": (ctypes.c_int32, [ctypes.c_int32]),
@@ -315,6 +317,15 @@ class Graph:
         p = Params(k_path, k_path if k_cent is None else k_cent, seed, first_path, first_cent, delta)
         r = Result()
         _check(lib().pm_count(self._h, ctypes.byref(p), ctypes.byref(r), _stream_ptr(stream)), "pm_count")
+        return r.to_dict()
+
+    def count_noalloc(self, k_path: int, k_cent: int | None = None, seed: int = 1, first_path: int = 0,
+                      first_cent: int = 0, delta: float = 0.01, stream=None) -> dict:
+        """pm_count_noalloc: pm_count with the library's fixed device scratch."""
+        p = Params(k_path, k_path if k_cent is None else k_cent, seed, first_path, first_cent, delta)
+        r = Result()
+        _check(lib().pm_count_noalloc(self._h, ctypes.byref(p), ctypes.byref(r), _stream_ptr(stream)),
+               "pm_count_noalloc")
         return r.to_dict()
 
     def build_alias(self, stream=None):
@@ -567,6 +578,11 @@ def set_search_mode(mode: int):
 def set_sampler_shape(samples_per_lane: int, blocks_per_cu: int):
     """Launch shape of the sampling kernels (tallies do not depend on it)."""
     _check(lib().pm_set_sampler_shape(samples_per_lane, blocks_per_cu), "pm_set_sampler_shape")
+
+
+def static_scratch_bytes() -> int:
+    """pm_static_scratch_bytes: size of pm_count_noalloc's per-device array."""
+    return int(lib().pm_static_scratch_bytes())
 
 
 def release_cached_memory():
