@@ -34,13 +34,31 @@ __global__ __launch_bounds__(kBlock) void k_sample_batch(const BatchGraph *__res
                                                          unsigned long long *__restrict__ tallies)
 {
     __shared__ uint32_t s_tile;
-    const uint32_t ntiles = ctl->ntiles;
+    const uint32_t ntiles = ctl->ntiles, nlists = ctl->nlists;
+    const uint32_t home = nlists ? blockIdx.x % nlists : 0u;
+    uint32_t tried = 0;  // lists found exhausted (thread 0's)
     for (;;) {
-        if (threadIdx.x == 0) s_tile = atomicAdd(&ctl->cursor, 1u);
+        if (threadIdx.x == 0) {
+            uint32_t t = ntiles;  // none left
+            if (nlists == 0) {
+                t = atomicAdd(&ctl->cursor, 1u);
+            } else {
+                while (tried < nlists) {
+                    const uint32_t x = (home + tried) % nlists;
+                    const uint32_t c = atomicAdd(&ctl->lcursor[x], 1u);
+                    if (c < ctl->begin[x + 1] - ctl->begin[x]) {
+                        t = ctl->begin[x] + c;
+                        break;
+                    }
+                    ++tried;  // cursors only grow: this list stays exhausted
+                }
+            }
+            s_tile = t;
+        }
         __syncthreads();
         const uint32_t t = s_tile;
         __syncthreads();  // every thread has read s_tile before it is reused
-        if (t >= ntiles) break;  // the cursor only grows: every block leaves
+        if (t >= ntiles) break;  // every block leaves once all its lists are exhausted
         const BatchTile T = tiles[t];
         uint32_t cnt[PM_NUM_TALLIES];
 #pragma unroll
@@ -109,11 +127,40 @@ uint32_t tiles_needed(const std::vector<const pm_graph *> &gs, const std::vector
     return n > 0xFFFFFFF0ull ? 0xFFFFFFF0u : (uint32_t)n;
 }
 
-// graph-major table: consecutive tiles share a graph (and its cached lines)
+uint32_t fill_graph_tiles(pm_batch *b, int32_t i, uint32_t per, uint32_t n);
+
+// The tile table: graphs dealt to kTileLists lists, largest budget first to
+// the least loaded list; each list graph-major (consecutive tiles share a
+// graph and its cached lines).
 uint32_t fill_tiles(pm_batch *b, uint32_t per)
 {
+    std::vector<int32_t> order((size_t)b->count);
+    for (int32_t i = 0; i < b->count; ++i) order[(size_t)i] = i;
+    const auto work = [&](int32_t i) { return budget(b->graphs[i], b->params[i], 0) + budget(b->graphs[i], b->params[i], 1); };
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return work(x) > work(y); });
+    std::vector<std::vector<int32_t>> lists(kTileLists);
+    uint64_t load[kTileLists] = {0};
+    for (int32_t i : order) {
+        uint32_t best = 0;
+        for (uint32_t x = 1; x < kTileLists; ++x)
+            if (load[x] < load[best]) best = x;
+        lists[best].push_back(i);
+        load[best] += work(i);
+    }
     uint32_t n = 0;
-    for (int32_t i = 0; i < b->count; ++i)
+    for (uint32_t x = 0; x < kTileLists; ++x) {
+        b->h_ctl->begin[x] = n;
+        b->h_ctl->lcursor[x] = 0;
+        for (int32_t i : lists[x]) n = fill_graph_tiles(b, i, per, n);
+    }
+    b->h_ctl->begin[kTileLists] = n;
+    b->h_ctl->nlists = kTileLists;
+    return n;
+}
+
+uint32_t fill_graph_tiles(pm_batch *b, int32_t i, uint32_t per, uint32_t n)
+{
+    {
         for (int tag = 0; tag < 2; ++tag) {
             const uint64_t k = budget(b->graphs[i], b->params[i], tag);
             const uint64_t first = tag == 0 ? b->params[i].first_id_path : b->params[i].first_id_cent;
@@ -127,6 +174,7 @@ uint32_t fill_tiles(pm_batch *b, uint32_t per)
                 t.seed = b->params[i].seed;
             }
         }
+    }
     return n;
 }
 

@@ -21,13 +21,24 @@ struct BatchTile {
     uint64_t seed;
 };
 
+constexpr uint32_t kTileLists = 8;  // one tile list per XCD of an MI355X
+
+// With nlists = 0 every block takes tiles from one cursor over [0, ntiles).
+// With nlists > 0 the table is cut into nlists lists, list x holding tiles
+// [begin[x], begin[x+1]); block b starts on list b mod nlists (consecutive
+// blocks go to consecutive XCDs, so each XCD works through its own graphs
+// and keeps their lines in its own L2) and, once that list is exhausted,
+// helps with the next ones.
 struct BatchCtl {
     uint32_t ntiles;
     uint32_t cursor;
+    uint32_t nlists;
+    uint32_t begin[kTileLists + 1];
+    uint32_t lcursor[kTileLists];
 };
 
-// Enqueue the persistent kernel: `blocks` blocks take tiles from ctl->cursor
-// until ctl->ntiles are done, adding into tallies[slot * 16 + tag * 8 + c].
+// Enqueue the persistent kernel: `blocks` blocks take tiles from ctl's
+// cursors until every tile is done, adding into tallies[slot * 16 + tag * 8 + c].
 pm_status launch_tiles(const BatchGraph *graphs, const BatchTile *tiles, BatchCtl *ctl, uint64_t *tallies,
                        unsigned blocks, hipStream_t s);
 

@@ -368,6 +368,7 @@ pm_status launch_step(pm_server *S, uint32_t ntiles)
 {
     S->h_ctl->ntiles = ntiles;
     S->h_ctl->cursor = 0;
+    S->h_ctl->nlists = 0;  // one cursor
     const size_t tb = sizeof(uint64_t) * (size_t)S->cfg.max_active * 2 * PM_NUM_TALLIES;
     PM_HIP(hipEventRecord(S->ev_a, S->s_step));
     PM_HIP(hipMemcpyAsync(S->d_tiles, S->h_tiles, sizeof(BatchTile) * ntiles, hipMemcpyHostToDevice, S->s_step));
