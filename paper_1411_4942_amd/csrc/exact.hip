@@ -13,7 +13,9 @@
 //   N_4 = 4-cycles: at each cycle's highest vertex x, pairs of lower wedge
 //         middles between x and each lower opposite vertex y
 //   N_5 = sum_e C(t_e, 2)                  diamonds
-//   N_6 = 4-cliques u < v < w < x: x in N+(u) ^ N+(v) ^ N+(w)
+//   N_6 = 4-cliques, counted at their lowest vertex u without listing them:
+//         the graph induced on N+(u) as bit rows, a clique {u, v, w, x}
+//         being a bit of row(v) & row(w) for an edge (v, w) inside N+(u)
 // t_e = triangles on edge e (each found once, from its lowest vertex).
 #include <algorithm>
 #include <cstring>
@@ -89,24 +91,22 @@ __global__ __launch_bounds__(kBlock) void k_split(const uint32_t *__restrict__ o
 
 // One forward slot s = (u, v), v > u, per thread: the triangles {u, v, w},
 // w > v, found by merging N+(u) beyond v with N+(v); each adds one to t_e of
-// its three edges (slots (u,v), (u,w), (v,w), all forward).  For each such w
-// the 4-cliques {u, v, w, x}, x > w, come from the rest of the merge, each x
-// checked against N+(w).
+// its three edges (slots (u,v), (u,w), (v,w), all forward).
 __global__ __launch_bounds__(kBlock) void k_triangles(const uint32_t *__restrict__ off,
                                                       const uint32_t *__restrict__ col,
                                                       const SlotRec *__restrict__ rec,
                                                       const uint32_t *__restrict__ split, int64_t slots,
                                                       uint32_t *__restrict__ t_e, ExactAcc *acc)
 {
-    unsigned long long tri = 0, k4 = 0;
+    unsigned long long tri = 0;
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < slots;
          s += (int64_t)gridDim.x * blockDim.x) {
         const SlotRec e = rec[s];
         const uint32_t u = e.row, v = e.col;
         if (v <= u) continue;
-        const int64_t a0 = s + 1, a1 = off[u + 1];
+        const int64_t a1 = off[u + 1];
         const int64_t b0 = off[v] + split[v], b1 = off[v + 1];
-        int64_t i = a0, j = b0;
+        int64_t i = s + 1, j = b0;
         uint32_t here = 0;
         while (i < a1 && j < b1) {
             const uint32_t x = col[i], y = col[j];
@@ -115,26 +115,9 @@ __global__ __launch_bounds__(kBlock) void k_triangles(const uint32_t *__restrict
             } else if (y < x) {
                 ++j;
             } else {
-                const uint32_t w = x;
                 ++here;
                 atomicAdd(&t_e[i], 1u);  // (u, w)
                 atomicAdd(&t_e[j], 1u);  // (v, w)
-                // 4-cliques through (u, v, w): the rest of N+(u) ^ N+(v), in N+(w)
-                int64_t i2 = i + 1, j2 = j + 1, k = off[w] + split[w];
-                const int64_t k1 = off[w + 1];
-                while (i2 < a1 && j2 < b1 && k < k1) {
-                    const uint32_t p = col[i2], q = col[j2];
-                    if (p < q) {
-                        ++i2;
-                    } else if (q < p) {
-                        ++j2;
-                    } else {
-                        while (k < k1 && col[k] < p) ++k;
-                        if (k < k1 && col[k] == p) ++k4;
-                        ++i2;
-                        ++j2;
-                    }
-                }
                 ++i;
                 ++j;
             }
@@ -143,11 +126,90 @@ __global__ __launch_bounds__(kBlock) void k_triangles(const uint32_t *__restrict
         tri += here;
     }
     const unsigned __int128 bt = block_sum128<kBlock>(tri);
-    const unsigned __int128 bk = block_sum128<kBlock>(k4);
-    if (threadIdx.x == 0) {
-        if (bt) atomicAdd(&acc->tri, (unsigned long long)bt);
-        if (bk) atomicAdd(&acc->k4, (unsigned long long)bk);
+    if (threadIdx.x == 0 && bt) atomicAdd(&acc->tri, (unsigned long long)bt);
+}
+
+// 4-cliques at their lowest vertex u, one u per block at a time (vertices
+// with lo < d+(u) <= 32 W; W words of 32 bits per row).  Row i of the graph
+// induced on N+(u) = {ids[0] < ids[1] < ...} has bit j when ids[i] ~ ids[j],
+// j > i (only forward neighbours are looked up).  A clique {u, v_i, v_j, v_k}
+// (i < j < k) is bit k of row i & row j for each bit j of row i, so each is
+// counted once, by whole words.  Rows live in LDS (`rows` null) or, for long
+// forward rows, in the block's slice of a global scratch array.
+template <int W, bool GLOBAL>
+__global__ __launch_bounds__(kBlock) void k_cliques(const uint32_t *__restrict__ off,
+                                                    const uint32_t *__restrict__ col,
+                                                    const uint32_t *__restrict__ split, int64_t n, uint32_t lo_d,
+                                                    uint32_t hi_d, uint32_t *__restrict__ scratch, ExactAcc *acc)
+{
+    constexpr int kLdsIds = GLOBAL ? 1 : 32 * W;
+    constexpr int kLdsRows = GLOBAL ? 1 : 32 * W * W;
+    __shared__ uint32_t s_ids[kLdsIds];
+    __shared__ uint32_t s_rows[kLdsRows];
+    const uint32_t wd = GLOBAL ? (hi_d + 31) / 32 : (uint32_t)W;  // words per row
+    uint32_t *ids = GLOBAL ? scratch + (uint64_t)blockIdx.x * ((uint64_t)hi_d * wd + hi_d) : s_ids;
+    uint32_t *rows = GLOBAL ? ids + hi_d : s_rows;
+    const int wv = threadIdx.x / kWave, lane = lane_id(), nwv = kBlock / kWave;
+    unsigned long long k4 = 0;
+    for (int64_t u = blockIdx.x; u < n; u += gridDim.x) {
+        const uint32_t beg = off[u] + split[u], D = off[u + 1] - beg;
+        if (D <= lo_d || D > hi_d) continue;  // block-uniform
+        for (uint32_t i = threadIdx.x; i < D; i += kBlock) ids[i] = col[beg + i];
+        for (uint64_t i = threadIdx.x; i < (uint64_t)D * wd; i += kBlock) rows[i] = 0;
+        if (GLOBAL) __threadfence();  // the cleared rows, before the atomics below
+        __syncthreads();
+        // rows: each wave takes a member v_i and looks its forward neighbours up
+        for (uint32_t i = wv; i < D; i += nwv) {
+            const uint32_t v = ids[i];
+            const uint32_t vb = off[v] + split[v], ve = off[v + 1];
+            for (uint32_t p = vb + lane; p < ve; p += kWave) {
+                const uint32_t x = col[p];
+                uint32_t lo = i + 1, hi = D;  // x > v = ids[i]
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (ids[mid] < x)
+                        lo = mid + 1;
+                    else
+                        hi = mid;
+                }
+                if (lo < D && ids[lo] == x) atomicOr(&rows[(uint64_t)i * wd + (lo >> 5)], 1u << (lo & 31));
+            }
+        }
+        if (GLOBAL) __threadfence();  // the finished rows, before they are read back
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < D; i += kBlock) {
+            const uint32_t *ri = rows + (uint64_t)i * wd;
+            for (uint32_t wj = 0; wj < wd; ++wj) {
+                uint32_t bits = ri[wj];
+                while (bits) {
+                    const uint32_t j = wj * 32 + (uint32_t)__builtin_ctz(bits);
+                    bits &= bits - 1;
+                    const uint32_t *rj = rows + (uint64_t)j * wd;
+                    for (uint32_t w = j >> 5; w < wd; ++w) k4 += (unsigned long long)__popc(ri[w] & rj[w]);
+                }
+            }
+        }
+        __syncthreads();  // the rows are rebuilt for the next u
     }
+    const unsigned __int128 bk = block_sum128<kBlock>(k4);
+    if (threadIdx.x == 0 && bk) atomicAdd(&acc->k4, (unsigned long long)bk);
+}
+
+// largest forward degree d+(u)
+__global__ __launch_bounds__(kBlock) void k_dplus_max(const uint32_t *__restrict__ off,
+                                                      const uint32_t *__restrict__ split, int64_t n,
+                                                      uint32_t *__restrict__ out)
+{
+    uint32_t m = 0;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t d = off[u + 1] - off[u] - split[u];
+        m = d > m ? d : m;
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const uint32_t x = __shfl_xor(m, o, kWave);
+        m = x > m ? x : m;
+    }
+    if (lane_id() == 0 && m) atomicMax(out, m);
 }
 
 // Sums over forward slots: 2 N_3 = sum t_e (d_u + d_v - 4), N_5 = sum C(t_e, 2)
@@ -251,6 +313,37 @@ pm_status exact_counts(const pm_graph *g, pm_exact *out, hipStream_t s)
                            t_e, slots, acc);
         PM_HIP(hipGetLastError());
         tmp.release(t_e);
+        {
+            // 4-cliques by forward degree class: rows in LDS up to 1024
+            // members, in a global slice per block above
+            ProfScope prof("exact.cliques", s);
+            uint32_t *dmax_d = nullptr;
+            PM_TRY(tmp.get(&dmax_d, 1));
+            PM_TRY(fill_async<uint32_t>(dmax_d, 0u, 1, s));
+            hipLaunchKernelGGL(k_dplus_max, dim3(grid_for(n, kBlock, 1024)), dim3(kBlock), 0, s, g->off, split, n,
+                               dmax_d);
+            uint32_t dmax = 0;
+            PM_HIP(hipMemcpyAsync(&dmax, dmax_d, sizeof(dmax), hipMemcpyDeviceToHost, s));
+            PM_HIP(hipStreamSynchronize(s));
+            const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(n, 8192));
+            hipLaunchKernelGGL((k_cliques<2, false>), dim3(grid), dim3(kBlock), 0, s, g->off, g->col, split, n, 2u,
+                               64u, nullptr, acc);
+            hipLaunchKernelGGL((k_cliques<8, false>), dim3(grid), dim3(kBlock), 0, s, g->off, g->col, split, n, 64u,
+                               256u, nullptr, acc);
+            hipLaunchKernelGGL((k_cliques<32, false>), dim3(grid), dim3(kBlock), 0, s, g->off, g->col, split, n, 256u,
+                               1024u, nullptr, acc);
+            if (dmax > 1024) {
+                const uint32_t wd = (dmax + 31) / 32;
+                const uint64_t slice = ((uint64_t)dmax * wd + dmax) * sizeof(uint32_t);
+                // blocks with a slice each, at most 1 GiB of slices
+                const unsigned gb = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(256, (1ull << 30) / slice));
+                uint32_t *scr = nullptr;
+                PM_TRY(tmp.get(&scr, (size_t)gb * ((size_t)dmax * wd + dmax)));
+                hipLaunchKernelGGL((k_cliques<1, true>), dim3(gb), dim3(kBlock), 0, s, g->off, g->col, split, n, 1024u,
+                                   dmax, scr, acc);
+            }
+            PM_HIP(hipGetLastError());
+        }
         // 4-cycles: one counter array and one touched list of n words per block
         const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(256, n));
         uint32_t *cnt = nullptr, *touched = nullptr;

@@ -46,7 +46,22 @@ def _graphs():
     gs.append(("er_2000_20000", synth.erdos_renyi(2000, 20000, 1)))
     gs.append(("chunglu_50k_500k", synth.chung_lu(50000, 500000, 2.3, 1000.0, 9)))
     gs.append(("rmat_s14", synth.rmat(14, 16, seed=2)))
+    # dense: forward rows of every 4-clique class (up to 64, 256, 1024 members)
+    gs.append(("er_dense_400", synth.erdos_renyi(400, 40000, 3)))
+    gs.append(("cliques_300_70_40", _disjoint([synth.complete(300), synth.complete(70), synth.complete(40),
+                                               synth.erdos_renyi(500, 3000, 4)])))
     return gs
+
+
+def _disjoint(parts):
+    """Disjoint union of CSR graphs (vertex ids shifted)."""
+    offs, cols, base, top = [np.zeros(1, np.int64)], [], 0, 0
+    for off, col in parts:
+        offs.append(off[1:].astype(np.int64) + top)
+        cols.append(col.astype(np.int64) + base)
+        base += off.size - 1
+        top += int(off[-1])
+    return np.concatenate(offs), np.concatenate(cols).astype(np.int32)
 
 
 GRAPHS = _graphs()
@@ -68,6 +83,19 @@ def test_exact_counts_equal_oracle(name, graph):
     got = g.exact()
     g.destroy()
     _check(name, off, col, got)
+
+
+def test_exact_counts_complete_1100_closed_form():
+    """K_1100: C(1100, 4) 4-cliques and nothing else; its lowest vertex has
+    1099 forward neighbours, past the LDS classes of the clique counter."""
+    _say("exact K1100")
+    off, col = synth.complete(1100)
+    g = ps.Graph(*_dev(off, col))
+    got = g.exact()
+    g.destroy()
+    n = 1100
+    assert got["C"][1:] == [0, 0, 0, 0, 0, n * (n - 1) * (n - 2) * (n - 3) // 24]
+    assert got["triangles"] == n * (n - 1) * (n - 2) // 6
 
 
 def test_exact_counts_chunglu_1e6_1e7():
