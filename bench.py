@@ -651,11 +651,12 @@ def main():
     samp = "sample_path.sorted" if "sample_path.sorted" in kernels else "sample_path"
     cent = "sample_centered.sorted" if "sample_centered.sorted" in kernels else "sample_centered"
     alg_samp = {
-        # the sampling kernels: algorithmic bytes per sample x samples per launch
-        "sample_path.sorted": (BYTES_PER_SAMPLE * k, "pm::k_sample_sorted<false>"),
-        "sample_centered.sorted": (BYTES_PER_SAMPLE * k, "pm::k_sample_sorted<true>"),
-        "sample_path": (BYTES_PER_SAMPLE * k, "pm::k_sample<false, 1>"),
-        "sample_centered": (BYTES_PER_SAMPLE * k, "pm::k_sample<true, 1>"),
+        # the sampling kernels (row-hash adjacency tests, the default search
+        # mode 2): algorithmic bytes per sample x samples per launch
+        "sample_path.sorted": (BYTES_PER_SAMPLE * k, "pm::k_sample_sorted<false, 2>"),
+        "sample_centered.sorted": (BYTES_PER_SAMPLE * k, "pm::k_sample_sorted<true, 2>"),
+        "sample_path": (BYTES_PER_SAMPLE * k, "pm::k_sample<false, 1, 2>"),
+        "sample_centered": (BYTES_PER_SAMPLE * k, "pm::k_sample<true, 1, 2>"),
     }
 
     # the timed region: K steps; HIP events only around the 3-path sampling
@@ -722,12 +723,15 @@ def main():
         "reverse_sort.histogram": (4 * slots, "pm::radix_histogram"),
         # per slot: input column 4, its rank 4, column 4 and edge 8 written
         "build_rows": (20 * slots, "pm::k_rows_block"),
-        # per slot: edge 8 + rev 4, both rows' 32-bit offset pairs 16, both segment prefixes written 16
-        "weights.reduce": (44 * slots, "pm::k_weights_reduce"),
+        # per slot: edge 8 + rev 4, both rows' 32-bit offset pairs 16, both
+        # segment prefixes written 16, the slot record written 16
+        "weights.reduce": (60 * slots, "pm::k_weights_reduce"),
+        # per slot: its column read 4, two row-hash entries written 8
+        "rowhash": (12 * slots, "pm::k_rowhash_small"),
         # per slot: both segment prefixes read 16, guide entries 2 (2m/4 buckets of 4 bytes per table)
         "weights.guide": (18 * slots, "pm::k_guide_fill"),
     }
-    multi = {"build_rows"}  # a scope over several kernels: reported, never the dominant kernel
+    multi = {"build_rows", "rowhash"}  # scopes over several kernels: reported, never the dominant kernel
     cand = {n: v for n, v in prep_kernels.items() if n in prep_alg and n not in multi}
     prep_dom = max(cand, key=lambda n: cand[n]["ms_per_step"])
     roofline_prep = roofline_for(prep_dom, prep_kernels[prep_dom], prep_alg[prep_dom], traffic, copy_gbs)
