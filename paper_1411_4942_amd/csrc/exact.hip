@@ -22,6 +22,7 @@
 
 #include "graph.hpp"
 #include "profile.hpp"
+#include "rowhash.hpp"
 
 namespace pm {
 
@@ -237,25 +238,113 @@ __global__ __launch_bounds__(kBlock) void k_edge_sums(const uint32_t *__restrict
     }
 }
 
-// 4-cycles by the highest vertex x: block b takes x = n-1-b, n-1-b-G, ...
-// (the hubs, with the most wedges, first).  For each lower neighbour w of x
-// and each lower neighbour y of w below x, cnt[y] += 1 in the block's own
-// counter array; then sum C(cnt[y], 2) over the touched y and clear them.
+// 4-cycles by the highest vertex x.  For each lower neighbour w of x and
+// each lower neighbour y of w below x, the pair (x, y) gains a wedge; a pair
+// with c wedges closes C(c, 2) 4-cycles at x.  Counted per x either in an LDS
+// hash of the touched y (below) or in a counter array of n words per block.
+
+constexpr int kC4Hash = 4096;  // LDS slots of the per-x wedge count table
+constexpr uint32_t kC4Empty = 0xFFFFFFFFu;
+
+// Vertices x in [0, x_end), one per block at a time, their wedge endpoints
+// counted in an LDS open-addressing table.  An x with more than 3/4 of the
+// table's slots in distinct endpoints is left to the global-array kernel
+// (appended to `spill`).
+__global__ __launch_bounds__(kBlock) void k_four_cycles_lds(const uint32_t *__restrict__ off,
+                                                            const uint32_t *__restrict__ col,
+                                                            const uint32_t *__restrict__ split, int64_t x_end,
+                                                            uint32_t *__restrict__ spill, uint32_t *n_spill,
+                                                            ExactAcc *acc)
+{
+    __shared__ uint32_t keys[kC4Hash];
+    __shared__ uint32_t cnts[kC4Hash];
+    __shared__ uint32_t touched[kC4Hash];
+    __shared__ uint32_t s_nt, s_fail;
+    const int w_id = threadIdx.x / kWave, lane = lane_id(), nw = kBlock / kWave;
+    for (int i = threadIdx.x; i < kC4Hash; i += kBlock) {
+        keys[i] = kC4Empty;
+        cnts[i] = 0;
+    }
+    unsigned __int128 n4 = 0;
+    for (int64_t x = blockIdx.x; x < x_end; x += gridDim.x) {
+        const uint32_t lo_begin = off[x], lo_end = off[x] + split[x];
+        if (lo_end - lo_begin < 2) continue;  // two wedges at least (block-uniform)
+        if (threadIdx.x == 0) {
+            s_nt = 0;
+            s_fail = 0;
+        }
+        __syncthreads();
+        for (uint32_t p = lo_begin + w_id; p < lo_end && !s_fail; p += nw) {
+            const uint32_t w = col[p];  // w < x
+            const uint32_t r0 = off[w], r1 = off[w + 1];
+            for (uint32_t q = r0 + lane; q < r1; q += kWave) {
+                const uint32_t y = col[q];
+                if (y >= (uint32_t)x) break;  // rows ascending: the rest are higher too
+                uint32_t h = hash_mix32(y) & (kC4Hash - 1);
+                for (int t = 0; t < kC4Hash; ++t) {
+                    const uint32_t k = keys[h];
+                    if (k == y) {
+                        atomicAdd(&cnts[h], 1u);
+                        break;
+                    }
+                    if (k == kC4Empty) {
+                        const uint32_t old = atomicCAS(&keys[h], kC4Empty, y);
+                        if (old == kC4Empty) {
+                            atomicAdd(&cnts[h], 1u);
+                            const uint32_t nt = atomicAdd(&s_nt, 1u);
+                            touched[nt] = h;
+                            if (nt + 1 > kC4Hash * 3 / 4) s_fail = 1;
+                            break;
+                        }
+                        if (old == y) {
+                            atomicAdd(&cnts[h], 1u);
+                            break;
+                        }
+                    }
+                    h = (h + 1) & (kC4Hash - 1);
+                }
+            }
+        }
+        __syncthreads();
+        const uint32_t nt = s_nt < (uint32_t)kC4Hash ? s_nt : (uint32_t)kC4Hash;
+        const bool fail = s_fail != 0;
+        for (uint32_t i = threadIdx.x; i < nt; i += kBlock) {
+            const uint32_t h = touched[i];
+            const uint64_t c = cnts[h];
+            if (!fail) n4 += (unsigned __int128)(c * (c - 1) / 2);
+            keys[h] = kC4Empty;
+            cnts[h] = 0;
+        }
+        if (fail && threadIdx.x == 0) spill[atomicAdd(n_spill, 1u)] = (uint32_t)x;
+        __syncthreads();  // the table is clear before the next x
+    }
+    n4 = block_sum128<kBlock>(n4);
+    if (threadIdx.x == 0 && n4) add128(&acc->n4_lo, &acc->n4_hi, n4);
+}
+
+// Vertices x = n-1-b for b < n_top (the highest ids, hubs first), then
+// the spilled ones: counted in the block's own counter array of n words.
 constexpr int kC4Threads = 1024;
+constexpr int kC4Hot = 16384;  // LDS counters for the highest ids
 
 __global__ __launch_bounds__(kC4Threads) void k_four_cycles(const uint32_t *__restrict__ off,
                                                             const uint32_t *__restrict__ col,
                                                             const uint32_t *__restrict__ split, int64_t n,
-                                                            uint32_t *__restrict__ cnt_all,
+                                                            int64_t n_top, const uint32_t *__restrict__ spill,
+                                                            const uint32_t *n_spill, uint32_t *__restrict__ cnt_all,
                                                             uint32_t *__restrict__ touched_all, ExactAcc *acc)
 {
     __shared__ uint32_t s_nt;
+    __shared__ uint32_t hot[kC4Hot];  // counters of the kC4Hot highest ids (the hubs every wedge ends on)
     uint32_t *cnt = cnt_all + (int64_t)blockIdx.x * n;
     uint32_t *touched = touched_all + (int64_t)blockIdx.x * n;
     const int w_id = threadIdx.x / kWave, lane = lane_id(), nw = kC4Threads / kWave;
+    const int64_t total = n_top + (int64_t)*n_spill;
+    const uint32_t hot0 = n > kC4Hot ? (uint32_t)(n - kC4Hot) : 0u;
+    for (int i = threadIdx.x; i < kC4Hot; i += kC4Threads) hot[i] = 0;
     unsigned __int128 n4 = 0;
-    for (int64_t b = blockIdx.x; b < n; b += gridDim.x) {
-        const int64_t x = n - 1 - b;
+    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+        const int64_t x = b < n_top ? n - 1 - b : (int64_t)spill[b - n_top];
         if (threadIdx.x == 0) s_nt = 0;
         __syncthreads();
         const int64_t lo_end = off[x] + split[x];
@@ -265,7 +354,10 @@ __global__ __launch_bounds__(kC4Threads) void k_four_cycles(const uint32_t *__re
             for (int64_t q = r0 + lane; q < r1; q += kWave) {
                 const uint32_t y = col[q];
                 if (y >= (uint32_t)x) break;  // rows ascending: the rest are higher too
-                if (atomicAdd(&cnt[y], 1u) == 0u) touched[atomicAdd(&s_nt, 1u)] = y;
+                if (y >= hot0)
+                    atomicAdd(&hot[y - hot0], 1u);
+                else if (atomicAdd(&cnt[y], 1u) == 0u)
+                    touched[atomicAdd(&s_nt, 1u)] = y;
             }
         }
         __syncthreads();
@@ -276,10 +368,30 @@ __global__ __launch_bounds__(kC4Threads) void k_four_cycles(const uint32_t *__re
             n4 += (unsigned __int128)(c * (c - 1) / 2);
             cnt[y] = 0;
         }
+        if ((uint32_t)x > hot0)  // block-uniform: hot counters below x may be set
+            for (uint32_t i = threadIdx.x; i < (uint32_t)x - hot0; i += blockDim.x) {
+                const uint64_t c = hot[i];
+                n4 += (unsigned __int128)(c * (c - 1) / 2);
+                hot[i] = 0;
+            }
         __syncthreads();  // counters clear before the next x
     }
     n4 = block_sum128<kC4Threads>(n4);
     if (threadIdx.x == 0 && n4) add128(&acc->n4_lo, &acc->n4_hi, n4);
+}
+
+// first vertex with degree above `bound` (degrees ascend)
+__global__ void k_first_above(const uint32_t *__restrict__ deg, int64_t n, uint32_t bound, int64_t *out)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (deg[mid] > bound)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    *out = lo;
 }
 
 }  // namespace
@@ -344,17 +456,31 @@ pm_status exact_counts(const pm_graph *g, pm_exact *out, hipStream_t s)
             }
             PM_HIP(hipGetLastError());
         }
-        // 4-cycles: one counter array and one touched list of n words per block
+        // 4-cycles: vertices of degree at most kC4LdsDegree in LDS tables,
+        // the rest (and any whose table fills) with one counter array and
+        // one touched list of n words per block
+        constexpr uint32_t kC4LdsDegree = 1024;
+        ProfScope prof("exact.four_cycles", s);
+        int64_t *xb_d = nullptr;
+        uint32_t *spill = nullptr, *n_spill = nullptr;
+        PM_TRY(tmp.get(&xb_d, 1));
+        PM_TRY(tmp.get(&n_spill, 1));
+        hipLaunchKernelGGL(k_first_above, dim3(1), dim3(1), 0, s, g->deg, n, kC4LdsDegree, xb_d);
+        PM_TRY(fill_async<uint32_t>(n_spill, 0u, 1, s));
+        int64_t x_big = 0;
+        PM_HIP(hipMemcpyAsync(&x_big, xb_d, sizeof(x_big), hipMemcpyDeviceToHost, s));
+        PM_HIP(hipStreamSynchronize(s));
+        PM_TRY(tmp.get(&spill, (size_t)std::max<int64_t>(x_big, 1)));
+        if (x_big > 0)
+            hipLaunchKernelGGL(k_four_cycles_lds, dim3((unsigned)std::min<int64_t>(x_big, 16384)), dim3(kBlock), 0, s,
+                               g->off, g->col, split, x_big, spill, n_spill, acc);
         const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(256, n));
         uint32_t *cnt = nullptr, *touched = nullptr;
         PM_TRY(tmp.get(&cnt, (size_t)blocks * (size_t)n));
         PM_TRY(tmp.get(&touched, (size_t)blocks * (size_t)n));
         PM_TRY(fill_async<uint32_t>(cnt, 0u, (int64_t)blocks * n, s));
-        {
-            ProfScope prof("exact.four_cycles", s);
-            hipLaunchKernelGGL(k_four_cycles, dim3(blocks), dim3(kC4Threads), 0, s, g->off, g->col, split, n, cnt,
-                               touched, acc);
-        }
+        hipLaunchKernelGGL(k_four_cycles, dim3(blocks), dim3(kC4Threads), 0, s, g->off, g->col, split, n, n - x_big,
+                           spill, n_spill, cnt, touched, acc);
         PM_HIP(hipGetLastError());
     }
     ExactAcc h;
