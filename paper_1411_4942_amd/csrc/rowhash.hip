@@ -104,7 +104,10 @@ __device__ __forceinline__ uint64_t window_base(const uint32_t *off, int64_t r_b
     return 2ull * (off[a] - off[r_begin]) / kHashWin + (uint64_t)(a - r_begin);
 }
 
-__device__ __forceinline__ uint32_t window_count(uint32_t d) { return (2u * d + kHashWin - 1) / kHashWin; }
+__device__ __forceinline__ uint32_t window_count(uint32_t d)
+{
+    return (uint32_t)((2ull * d + kHashWin - 1) / kHashWin);
+}
 
 struct SpillList {
     uint32_t count;
