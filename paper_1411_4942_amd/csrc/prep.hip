@@ -1280,48 +1280,11 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
         PM_HIP(hipMemcpyAsync(cls, cls_d, sizeof(cls), hipMemcpyDeviceToHost, s));
         PM_HIP(hipStreamSynchronize(s));
         ProfScope prof("build_rows", s);
-        if (cls[1] > cls[0]) {
-            ProfScope pc("build_rows.lane", s);
-            hipLaunchKernelGGL(k_rows_group<16>, dim3((unsigned)((cls[1] - cls[0] + 15) / 16)), dim3(kBlock), 0, s,
-                               off_in, col_in, order, g->rank, g->off, n, cls[0], cls[1], g->col, edge, ladder1,
-                               st);
-        }
-        if (cls[2] > cls[1]) {
-            ProfScope pc("build_rows.wave", s);
-            hipLaunchKernelGGL(k_rows_group<64>, dim3((unsigned)((cls[2] - cls[1] + 3) / 4)), dim3(kBlock), 0, s,
-                               off_in, col_in, order, g->rank, g->off, n, cls[1], cls[2], g->col, edge, ladder1,
-                               st);
-        }
-        if (cls[3] > cls[2]) {
-            ProfScope pc("build_rows.w128", s);
-            hipLaunchKernelGGL(k_rows_bitonic<2>, dim3((unsigned)((cls[3] - cls[2] + 3) / 4)), dim3(kBlock), 0, s,
-                               off_in, col_in, order, g->rank, g->off, n, cls[2], cls[3], g->col, edge, ladder1,
-                               st);
-        }
-        if (cls[4] > cls[3]) {
-            ProfScope pc("build_rows.w256", s);
-            hipLaunchKernelGGL(k_rows_bitonic<4>, dim3((unsigned)((cls[4] - cls[3] + 3) / 4)), dim3(kBlock), 0, s,
-                               off_in, col_in, order, g->rank, g->off, n, cls[3], cls[4], g->col, edge, ladder1,
-                               st);
-        }
-        if (cls[5] > cls[4]) {
-            ProfScope pc("build_rows.b1024", s);
-            hipLaunchKernelGGL((k_rows_block<64, 16>), dim3((unsigned)(cls[5] - cls[4])), dim3(64), 0, s, off_in,
-                               col_in, order, g->rank, g->off, n, cls[4], vbits, g->col, edge, ladder1, st);
-        }
-        if (cls[6] > cls[5]) {
-            ProfScope pc("build_rows.b4096", s);
-            hipLaunchKernelGGL((k_rows_block<256, 16>), dim3((unsigned)(cls[6] - cls[5])), dim3(256), 0, s, off_in,
-                               col_in, order, g->rank, g->off, n, cls[5], vbits, g->col, edge, ladder1, st);
-        }
-        if (cls[7] > cls[6]) {
-            ProfScope pc("build_rows.b8192", s);
-            hipLaunchKernelGGL((k_rows_block<512, 16>), dim3((unsigned)(cls[7] - cls[6])), dim3(512), 0, s, off_in,
-                               col_in, order, g->rank, g->off, n, cls[6], vbits, g->col, edge, ladder1, st);
-        }
-        PM_HIP(hipGetLastError());
-        // the rows above 8192 (one block of 1024 per row or chunk) run on two
-        // side streams, forked from s after everything above and joined back
+        // the rows above 8192 (one block of 1024 per row or chunk, whose few
+        // large blocks leave CUs idle at the ends of their launches) run on two
+        // side streams, forked from s before the other classes are enqueued
+        // (they read only the offsets, order and rank) and joined back; the
+        // many small blocks of the other classes fill the CUs beside them
         const int64_t T = slots - cls[kRowClasses];
         const int64_t rt = cls[kRowClasses - 1], H = n - rt;
         uint32_t *run0 = nullptr, *run1 = nullptr, *hstart = nullptr, *cstart = nullptr;
@@ -1363,6 +1326,45 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
                                    ladder1);
                 std::swap(src, dst);
             }
+        }
+        if (cls[1] > cls[0]) {
+            ProfScope pc("build_rows.lane", s);
+            hipLaunchKernelGGL(k_rows_group<16>, dim3((unsigned)((cls[1] - cls[0] + 15) / 16)), dim3(kBlock), 0, s,
+                               off_in, col_in, order, g->rank, g->off, n, cls[0], cls[1], g->col, edge, ladder1,
+                               st);
+        }
+        if (cls[2] > cls[1]) {
+            ProfScope pc("build_rows.wave", s);
+            hipLaunchKernelGGL(k_rows_group<64>, dim3((unsigned)((cls[2] - cls[1] + 3) / 4)), dim3(kBlock), 0, s,
+                               off_in, col_in, order, g->rank, g->off, n, cls[1], cls[2], g->col, edge, ladder1,
+                               st);
+        }
+        if (cls[3] > cls[2]) {
+            ProfScope pc("build_rows.w128", s);
+            hipLaunchKernelGGL(k_rows_bitonic<2>, dim3((unsigned)((cls[3] - cls[2] + 3) / 4)), dim3(kBlock), 0, s,
+                               off_in, col_in, order, g->rank, g->off, n, cls[2], cls[3], g->col, edge, ladder1,
+                               st);
+        }
+        if (cls[4] > cls[3]) {
+            ProfScope pc("build_rows.w256", s);
+            hipLaunchKernelGGL(k_rows_bitonic<4>, dim3((unsigned)((cls[4] - cls[3] + 3) / 4)), dim3(kBlock), 0, s,
+                               off_in, col_in, order, g->rank, g->off, n, cls[3], cls[4], g->col, edge, ladder1,
+                               st);
+        }
+        if (cls[5] > cls[4]) {
+            ProfScope pc("build_rows.b1024", s);
+            hipLaunchKernelGGL((k_rows_block<64, 16>), dim3((unsigned)(cls[5] - cls[4])), dim3(64), 0, s, off_in,
+                               col_in, order, g->rank, g->off, n, cls[4], vbits, g->col, edge, ladder1, st);
+        }
+        if (cls[6] > cls[5]) {
+            ProfScope pc("build_rows.b4096", s);
+            hipLaunchKernelGGL((k_rows_block<256, 16>), dim3((unsigned)(cls[6] - cls[5])), dim3(256), 0, s, off_in,
+                               col_in, order, g->rank, g->off, n, cls[5], vbits, g->col, edge, ladder1, st);
+        }
+        if (cls[7] > cls[6]) {
+            ProfScope pc("build_rows.b8192", s);
+            hipLaunchKernelGGL((k_rows_block<512, 16>), dim3((unsigned)(cls[7] - cls[6])), dim3(512), 0, s, off_in,
+                               col_in, order, g->rank, g->off, n, cls[6], vbits, g->col, edge, ladder1, st);
         }
         const hipError_t launched = hipGetLastError();
         PM_HIP(fork.join());  // before anything can return: the temporaries are released on s
