@@ -41,8 +41,8 @@ __host__ __device__ __forceinline__ uint32_t hash_home(uint32_t b, uint32_t size
 }
 
 // Is key in the row whose slots are [lo, lo + d)?  H holds the row hash.
-__device__ __forceinline__ bool rowhash_contains(const uint32_t *__restrict__ H, uint32_t lo, uint32_t d,
-                                                 uint32_t key)
+__host__ __device__ __forceinline__ bool rowhash_contains(const uint32_t *__restrict__ H, uint32_t lo, uint32_t d,
+                                                          uint32_t key)
 {
     if (d == 0) return false;
     const uint64_t base = 2ull * lo, end = base + 2ull * d;
