@@ -322,19 +322,37 @@ __global__ __launch_bounds__(kBlock) void k_four_cycles_lds(const uint32_t *__re
     if (threadIdx.x == 0 && n4) add128(&acc->n4_lo, &acc->n4_hi, n4);
 }
 
+// Sum of one 128-bit value per lane over the wave, valid in lane 0.
+__device__ __forceinline__ unsigned __int128 wave_sum128(unsigned __int128 v)
+{
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        const unsigned long long lo = __shfl_down((unsigned long long)v, d, kWave);
+        const unsigned long long hi = __shfl_down((unsigned long long)(v >> 64), d, kWave);
+        v += (unsigned __int128)lo | ((unsigned __int128)hi << 64);
+    }
+    return v;
+}
+
 // Vertices x = n-1-b for b < n_top (the highest ids, hubs first), then
 // the spilled ones: counted in the block's own counter array of n words.
+// Blocks take the next b from a queue, so the hubs' unequal work spreads
+// over the blocks as it comes (a fixed stride left the busiest block 1.27x
+// the mean at R-MAT scale 22).
 constexpr int kC4Threads = 1024;
-constexpr int kC4Hot = 16384;  // LDS counters for the highest ids
+// LDS counters for the highest ids: all of a 160 KB LDS but the few words
+// below (at R-MAT scale 22 they take 44% of the wedges, 16384 of them 26%)
+constexpr int kC4Hot = 40928;
 
 __global__ __launch_bounds__(kC4Threads) void k_four_cycles(const uint32_t *__restrict__ off,
                                                             const uint32_t *__restrict__ col,
                                                             const uint32_t *__restrict__ split, int64_t n,
                                                             int64_t n_top, const uint32_t *__restrict__ spill,
                                                             const uint32_t *n_spill, uint32_t *__restrict__ cnt_all,
-                                                            uint32_t *__restrict__ touched_all, ExactAcc *acc)
+                                                            uint32_t *__restrict__ touched_all, uint32_t *queue,
+                                                            ExactAcc *acc)
 {
-    __shared__ uint32_t s_nt;
+    __shared__ uint32_t s_nt, s_b;
     __shared__ uint32_t hot[kC4Hot];  // counters of the kC4Hot highest ids (the hubs every wedge ends on)
     uint32_t *cnt = cnt_all + (int64_t)blockIdx.x * n;
     uint32_t *touched = touched_all + (int64_t)blockIdx.x * n;
@@ -343,10 +361,15 @@ __global__ __launch_bounds__(kC4Threads) void k_four_cycles(const uint32_t *__re
     const uint32_t hot0 = n > kC4Hot ? (uint32_t)(n - kC4Hot) : 0u;
     for (int i = threadIdx.x; i < kC4Hot; i += kC4Threads) hot[i] = 0;
     unsigned __int128 n4 = 0;
-    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
-        const int64_t x = b < n_top ? n - 1 - b : (int64_t)spill[b - n_top];
-        if (threadIdx.x == 0) s_nt = 0;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            s_b = atomicAdd(queue, 1u);
+            s_nt = 0;
+        }
         __syncthreads();
+        const int64_t b = s_b;
+        if (b >= total) break;  // block-uniform
+        const int64_t x = b < n_top ? n - 1 - b : (int64_t)spill[b - n_top];
         const int64_t lo_end = off[x] + split[x];
         for (int64_t p = off[x] + w_id; p < lo_end; p += nw) {
             const uint32_t w = col[p];  // w < x
@@ -374,10 +397,10 @@ __global__ __launch_bounds__(kC4Threads) void k_four_cycles(const uint32_t *__re
                 n4 += (unsigned __int128)(c * (c - 1) / 2);
                 hot[i] = 0;
             }
-        __syncthreads();  // counters clear before the next x
+        __syncthreads();  // counters clear, s_b read, before the next x
     }
-    n4 = block_sum128<kC4Threads>(n4);
-    if (threadIdx.x == 0 && n4) add128(&acc->n4_lo, &acc->n4_hi, n4);
+    n4 = wave_sum128(n4);
+    if (lane == 0 && n4) add128(&acc->n4_lo, &acc->n4_hi, n4);
 }
 
 // first vertex with degree above `bound` (degrees ascend)
@@ -475,12 +498,14 @@ pm_status exact_counts(const pm_graph *g, pm_exact *out, hipStream_t s)
             hipLaunchKernelGGL(k_four_cycles_lds, dim3((unsigned)std::min<int64_t>(x_big, 16384)), dim3(kBlock), 0, s,
                                g->off, g->col, split, x_big, spill, n_spill, acc);
         const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(256, n));
-        uint32_t *cnt = nullptr, *touched = nullptr;
+        uint32_t *cnt = nullptr, *touched = nullptr, *queue = nullptr;
         PM_TRY(tmp.get(&cnt, (size_t)blocks * (size_t)n));
         PM_TRY(tmp.get(&touched, (size_t)blocks * (size_t)n));
+        PM_TRY(tmp.get(&queue, 1));
         PM_TRY(fill_async<uint32_t>(cnt, 0u, (int64_t)blocks * n, s));
+        PM_TRY(fill_async<uint32_t>(queue, 0u, 1, s));
         hipLaunchKernelGGL(k_four_cycles, dim3(blocks), dim3(kC4Threads), 0, s, g->off, g->col, split, n, n - x_big,
-                           spill, n_spill, cnt, touched, acc);
+                           spill, n_spill, cnt, touched, queue, acc);
         PM_HIP(hipGetLastError());
     }
     ExactAcc h;
