@@ -30,6 +30,7 @@
 #include "radix.hpp"
 #include "sampler.hpp"
 #include "scan.hpp"
+#include "streams.hpp"
 
 #include <algorithm>
 #include <mutex>
@@ -366,41 +367,70 @@ __global__ __launch_bounds__(kBlock) void k_sample_alias_sorted(SamplerView g, c
     tally_flush(cnt, tally);
 }
 
-pm_status launch_alias_sorted(const SamplerView &v, const AliasEntry *T, uint64_t N, bool centered, uint64_t seed,
-                              uint64_t first, uint64_t k, uint64_t *tally, unsigned blocks, hipStream_t s)
+// Buffers of one alias draw-order sort chunk of `chunk` ids.
+struct AliasSortBufs {
+    uint32_t *kin, *k0, *v0, *k1, *v1;
+    char *scr;
+    uint64_t chunk;
+};
+
+pm_status alias_sort_bufs(Temps &tmp, uint64_t k, AliasSortBufs *b)
+{
+    b->chunk = std::min<uint64_t>(k, kSortedChunk);
+    PM_TRY(tmp.get(&b->kin, (size_t)b->chunk));
+    PM_TRY(tmp.get(&b->k0, (size_t)b->chunk));
+    PM_TRY(tmp.get(&b->v0, (size_t)b->chunk));
+    PM_TRY(tmp.get(&b->k1, (size_t)b->chunk));
+    PM_TRY(tmp.get(&b->v1, (size_t)b->chunk));
+    return tmp.get(&b->scr, radix_scratch_bytes((int64_t)b->chunk));
+}
+
+// the bucket keys of ids [first, first + kc) and those ids sorted by them
+// (kc <= b.chunk); *ids receives the sorted ids (minus first)
+pm_status alias_sort_chunk(uint64_t N, bool centered, uint64_t seed, uint64_t first, uint64_t kc, unsigned blocks,
+                           hipStream_t s, const AliasSortBufs &b, uint32_t **ids)
 {
     const int nbits = bits_for(N - 1);  // b < N
     const int kshift = nbits > kDrawKeyBits ? nbits - kDrawKeyBits : 0;
     const int kbits = nbits - kshift;
-    const uint64_t chunk = std::min<uint64_t>(k, kSortedChunk);
+    const unsigned kb = (unsigned)std::min<uint64_t>((kc + kBlock - 1) / kBlock, blocks);
+    if (centered)
+        hipLaunchKernelGGL((k_alias_keys<true>), dim3(kb), dim3(kBlock), 0, s, N, seed, first, kc, kshift, b.kin);
+    else
+        hipLaunchKernelGGL((k_alias_keys<false>), dim3(kb), dim3(kBlock), 0, s, N, seed, first, kc, kshift, b.kin);
+    PM_HIP(hipGetLastError());
+    uint32_t *ks = nullptr;
+    return radix_sort("alias_draw_sort", b.kin, nullptr, b.k0, b.v0, b.k1, b.v1, (int64_t)kc, kbits, b.scr, s, &ks,
+                      ids, nullptr, nullptr, false);  // only the ids are used
+}
+
+// the samples first + ids[j] for j < kc, into tally
+pm_status alias_sample_chunk(const SamplerView &v, const AliasEntry *T, uint64_t N, bool centered, uint64_t seed,
+                             uint64_t first, uint64_t kc, const uint32_t *ids, uint64_t *tally, unsigned blocks,
+                             hipStream_t s)
+{
+    const unsigned kb = (unsigned)std::min<uint64_t>((kc + kBlock - 1) / kBlock, blocks);
+    if (centered)
+        hipLaunchKernelGGL((k_sample_alias_sorted<true>), dim3(kb), dim3(kBlock), 0, s, v, T, N, seed, first, kc, ids,
+                           (unsigned long long *)tally);
+    else
+        hipLaunchKernelGGL((k_sample_alias_sorted<false>), dim3(kb), dim3(kBlock), 0, s, v, T, N, seed, first, kc,
+                           ids, (unsigned long long *)tally);
+    PM_HIP(hipGetLastError());
+    return PM_OK;
+}
+
+pm_status launch_alias_sorted(const SamplerView &v, const AliasEntry *T, uint64_t N, bool centered, uint64_t seed,
+                              uint64_t first, uint64_t k, uint64_t *tally, unsigned blocks, hipStream_t s)
+{
     Temps tmp(s);
-    uint32_t *kin, *k0, *v0, *k1, *v1;
-    char *scr = nullptr;
-    PM_TRY(tmp.get(&kin, (size_t)chunk));
-    PM_TRY(tmp.get(&k0, (size_t)chunk));
-    PM_TRY(tmp.get(&v0, (size_t)chunk));
-    PM_TRY(tmp.get(&k1, (size_t)chunk));
-    PM_TRY(tmp.get(&v1, (size_t)chunk));
-    PM_TRY(tmp.get(&scr, radix_scratch_bytes((int64_t)chunk)));
-    for (uint64_t c0 = 0; c0 < k; c0 += chunk) {
-        const uint64_t kc = std::min(chunk, k - c0);
-        const unsigned kb = (unsigned)std::min<uint64_t>((kc + kBlock - 1) / kBlock, blocks);
-        if (centered)
-            hipLaunchKernelGGL((k_alias_keys<true>), dim3(kb), dim3(kBlock), 0, s, N, seed, first + c0, kc, kshift, kin);
-        else
-            hipLaunchKernelGGL((k_alias_keys<false>), dim3(kb), dim3(kBlock), 0, s, N, seed, first + c0, kc, kshift,
-                               kin);
-        PM_HIP(hipGetLastError());
-        uint32_t *ks = nullptr, *ids = nullptr;
-        PM_TRY(radix_sort("alias_draw_sort", kin, nullptr, k0, v0, k1, v1, (int64_t)kc, kbits, scr, s, &ks, &ids,
-                          nullptr, nullptr, false));  // only the ids are used
-        if (centered)
-            hipLaunchKernelGGL((k_sample_alias_sorted<true>), dim3(kb), dim3(kBlock), 0, s, v, T, N, seed, first + c0,
-                               kc, ids, (unsigned long long *)tally);
-        else
-            hipLaunchKernelGGL((k_sample_alias_sorted<false>), dim3(kb), dim3(kBlock), 0, s, v, T, N, seed, first + c0,
-                               kc, ids, (unsigned long long *)tally);
-        PM_HIP(hipGetLastError());
+    AliasSortBufs b{};
+    PM_TRY(alias_sort_bufs(tmp, k, &b));
+    for (uint64_t c0 = 0; c0 < k; c0 += b.chunk) {
+        const uint64_t kc = std::min(b.chunk, k - c0);
+        uint32_t *ids = nullptr;
+        PM_TRY(alias_sort_chunk(N, centered, seed, first + c0, kc, blocks, s, b, &ids));
+        PM_TRY(alias_sample_chunk(v, T, N, centered, seed, first + c0, kc, ids, tally, blocks, s));
     }
     return PM_OK;
 }
@@ -435,6 +465,40 @@ pm_status sample_alias_async(const pm_graph *g, const pm_params *p, uint64_t *ta
         return PM_EINVAL;
     }
     PM_TRY(fill_async<uint64_t>(tallies_dev, 0ull, 2 * PM_NUM_TALLIES, s));
+    const uint64_t N = (uint64_t)g->slots;
+    const auto one_chunk = [&](uint64_t R, uint64_t k) {
+        return R > 0 && k > 0 && k >= draw_order_min() && N > 1 && draw_order_enabled() && k <= kSortedChunk;
+    };
+    if (one_chunk(g->R_tau, p->k_path) && one_chunk(g->R_lam, p->k_cent)) {
+        // as the main draw does: the centered sampler's ids sorted on a side
+        // stream beside the 3-path sampler's sort and samples
+        const SamplerView vp = view_of(g, false), vc = view_of(g, true);
+        const AliasEntry *Tp = (const AliasEntry *)g->alias_tau, *Tc = (const AliasEntry *)g->alias_lam;
+        const unsigned cap = (unsigned)((uint64_t)sampler_cu_count(g->device) * 4u);
+        Temps tmp(s);
+        AliasSortBufs bp{}, bc{};
+        PM_TRY(alias_sort_bufs(tmp, p->k_path, &bp));
+        PM_TRY(alias_sort_bufs(tmp, p->k_cent, &bc));
+        hipStream_t side[2];
+        PM_HIP(side_streams(side));
+        uint32_t *ids_c = nullptr;
+        {
+            Fork fork(s, side, 1);  // joined before the temporaries are released on s
+            PM_HIP(fork.status);
+            PM_TRY(alias_sort_chunk(N, true, p->seed, p->first_id_cent, p->k_cent, cap, side[0], bc, &ids_c));
+            {
+                ProfScope prof("sample_path_alias", s);
+                uint32_t *ids_p = nullptr;
+                PM_TRY(alias_sort_chunk(N, false, p->seed, p->first_id_path, p->k_path, cap, s, bp, &ids_p));
+                PM_TRY(alias_sample_chunk(vp, Tp, N, false, p->seed, p->first_id_path, p->k_path, ids_p, tallies_dev,
+                                          cap, s));
+            }
+            PM_HIP(fork.join());
+        }
+        ProfScope prof("sample_centered_alias", s);
+        return alias_sample_chunk(vc, Tc, N, true, p->seed, p->first_id_cent, p->k_cent, ids_c,
+                                  tallies_dev + PM_NUM_TALLIES, cap, s);
+    }
     PM_TRY(launch_alias(g, false, p->seed, p->first_id_path, p->k_path, tallies_dev, s));
     PM_TRY(launch_alias(g, true, p->seed, p->first_id_cent, p->k_cent, tallies_dev + PM_NUM_TALLIES, s));
     return PM_OK;

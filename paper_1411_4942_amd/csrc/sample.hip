@@ -6,6 +6,7 @@
 #include "profile.hpp"
 #include "radix.hpp"
 #include "sampler.hpp"
+#include "streams.hpp"
 
 #include <algorithm>
 #include <atomic>
@@ -160,53 +161,83 @@ struct SortBufs {
     uint64_t chunk;
 };
 
-static pm_status launch_sorted_in(const SamplerView &v, bool centered, uint64_t seed, uint64_t first, uint64_t k,
-                                  uint64_t *tally, unsigned blocks, hipStream_t s, const SortBufs &b)
+// The draw keys of ids [first, first + kc) and those ids sorted by them, in
+// b's buffers (kc <= b.chunk); *ids receives the sorted ids (minus first).
+static pm_status sort_chunk(const SamplerView &v, bool centered, uint64_t seed, uint64_t first, uint64_t kc,
+                            unsigned blocks, hipStream_t s, const SortBufs &b, uint32_t **ids)
 {
     const int rbits = bits_for(v.R - 1);  // r < R
     const int kshift = rbits > kDrawKeyBits ? rbits - kDrawKeyBits : 0;
     const int kbits = rbits - kshift;
+    const unsigned kb = (unsigned)std::min<uint64_t>((kc + kBlock - 1) / kBlock, blocks);
+    {
+        ProfScope pd("draw_keys", s);
+        if (centered)
+            hipLaunchKernelGGL((k_draw_keys<true>), dim3(kb), dim3(kBlock), 0, s, v, seed, first, kc, kshift, b.kin);
+        else
+            hipLaunchKernelGGL((k_draw_keys<false>), dim3(kb), dim3(kBlock), 0, s, v, seed, first, kc, kshift, b.kin);
+        PM_HIP(hipGetLastError());
+    }
+    uint32_t *ks = nullptr;
+    return radix_sort("draw_sort", b.kin, nullptr, b.k0, b.v0, b.k1, b.v1, (int64_t)kc, kbits, b.scr, s, &ks, ids,
+                      nullptr, nullptr, false);  // only the ids are used
+}
+
+// The samples first + ids[j] for j < kc, into tally.
+static pm_status sample_chunk(const SamplerView &v, bool centered, uint64_t seed, uint64_t first, uint64_t kc,
+                              const uint32_t *ids, uint64_t *tally, unsigned blocks, hipStream_t s)
+{
+    const unsigned kb = (unsigned)std::min<uint64_t>((kc + kBlock - 1) / kBlock, blocks);
+    unsigned long long *t = (unsigned long long *)tally;
+    ProfScope pk(centered ? "sample_centered.sorted" : "sample_path.sorted", s);
+    const int mode = g_search_mode.load();
+    if (mode == PM_SEARCH_WAVE) {
+        if (centered)
+            hipLaunchKernelGGL((k_sample_wave<true, true>), dim3(kb), dim3(kBlock), 0, s, v, seed, first, kc, ids, t);
+        else
+            hipLaunchKernelGGL((k_sample_wave<false, true>), dim3(kb), dim3(kBlock), 0, s, v, seed, first, kc, ids, t);
+    } else if (mode == PM_SEARCH_HASH) {
+        if (centered)
+            hipLaunchKernelGGL((k_sample_sorted<true, PM_SEARCH_HASH>), dim3(kb), dim3(kBlock), 0, s, v, seed, first,
+                               kc, ids, t);
+        else
+            hipLaunchKernelGGL((k_sample_sorted<false, PM_SEARCH_HASH>), dim3(kb), dim3(kBlock), 0, s, v, seed, first,
+                               kc, ids, t);
+    } else if (centered)
+        hipLaunchKernelGGL((k_sample_sorted<true, PM_SEARCH_LANE>), dim3(kb), dim3(kBlock), 0, s, v, seed, first, kc,
+                           ids, t);
+    else
+        hipLaunchKernelGGL((k_sample_sorted<false, PM_SEARCH_LANE>), dim3(kb), dim3(kBlock), 0, s, v, seed, first, kc,
+                           ids, t);
+    PM_HIP(hipGetLastError());
+    return PM_OK;
+}
+
+static pm_status launch_sorted_in(const SamplerView &v, bool centered, uint64_t seed, uint64_t first, uint64_t k,
+                                  uint64_t *tally, unsigned blocks, hipStream_t s, const SortBufs &b)
+{
     for (uint64_t c0 = 0; c0 < k; c0 += b.chunk) {
         const uint64_t kc = std::min(b.chunk, k - c0);
-        const unsigned kb = (unsigned)std::min<uint64_t>((kc + kBlock - 1) / kBlock, blocks);
-        {
-            ProfScope pd("draw_keys", s);
-            if (centered)
-                hipLaunchKernelGGL((k_draw_keys<true>), dim3(kb), dim3(kBlock), 0, s, v, seed, first + c0, kc, kshift,
-                                   b.kin);
-            else
-                hipLaunchKernelGGL((k_draw_keys<false>), dim3(kb), dim3(kBlock), 0, s, v, seed, first + c0, kc, kshift,
-                                   b.kin);
-            PM_HIP(hipGetLastError());
-        }
-        uint32_t *ks = nullptr, *ids = nullptr;
-        PM_TRY(radix_sort("draw_sort", b.kin, nullptr, b.k0, b.v0, b.k1, b.v1, (int64_t)kc, kbits, b.scr, s, &ks, &ids,
-                          nullptr, nullptr, false));  // only the ids are used
-        {
-            ProfScope pk(centered ? "sample_centered.sorted" : "sample_path.sorted", s);
-            if (g_search_mode.load() == PM_SEARCH_WAVE) {
-                if (centered)
-                    hipLaunchKernelGGL((k_sample_wave<true, true>), dim3(kb), dim3(kBlock), 0, s, v, seed, first + c0,
-                                       kc, ids, (unsigned long long *)tally);
-                else
-                    hipLaunchKernelGGL((k_sample_wave<false, true>), dim3(kb), dim3(kBlock), 0, s, v, seed,
-                                       first + c0, kc, ids, (unsigned long long *)tally);
-            } else if (g_search_mode.load() == PM_SEARCH_HASH) {
-                if (centered)
-                    hipLaunchKernelGGL((k_sample_sorted<true, PM_SEARCH_HASH>), dim3(kb), dim3(kBlock), 0, s, v, seed,
-                                       first + c0, kc, ids, (unsigned long long *)tally);
-                else
-                    hipLaunchKernelGGL((k_sample_sorted<false, PM_SEARCH_HASH>), dim3(kb), dim3(kBlock), 0, s, v,
-                                       seed, first + c0, kc, ids, (unsigned long long *)tally);
-            } else if (centered)
-                hipLaunchKernelGGL((k_sample_sorted<true, PM_SEARCH_LANE>), dim3(kb), dim3(kBlock), 0, s, v, seed,
-                                   first + c0, kc, ids, (unsigned long long *)tally);
-            else
-                hipLaunchKernelGGL((k_sample_sorted<false, PM_SEARCH_LANE>), dim3(kb), dim3(kBlock), 0, s, v, seed,
-                                   first + c0, kc, ids, (unsigned long long *)tally);
-            PM_HIP(hipGetLastError());
-        }
+        uint32_t *ids = nullptr;
+        PM_TRY(sort_chunk(v, centered, seed, first + c0, kc, blocks, s, b, &ids));
+        PM_TRY(sample_chunk(v, centered, seed, first + c0, kc, ids, tally, blocks, s));
     }
+    return PM_OK;
+}
+
+// buffers of one draw-order sort chunk of min(k, kSortedChunk) ids from tmp
+static pm_status sort_bufs(Temps &tmp, uint64_t k, SortBufs *b)
+{
+    const uint64_t chunk = std::min<uint64_t>(k, kSortedChunk);
+    char *scr = nullptr;
+    PM_TRY(tmp.get(&b->kin, (size_t)chunk));
+    PM_TRY(tmp.get(&b->k0, (size_t)chunk));
+    PM_TRY(tmp.get(&b->v0, (size_t)chunk));
+    PM_TRY(tmp.get(&b->k1, (size_t)chunk));
+    PM_TRY(tmp.get(&b->v1, (size_t)chunk));
+    PM_TRY(tmp.get(&scr, radix_scratch_bytes((int64_t)chunk)));
+    b->scr = scr;
+    b->chunk = chunk;
     return PM_OK;
 }
 
@@ -214,18 +245,9 @@ static pm_status launch_sorted_in(const SamplerView &v, bool centered, uint64_t 
 static pm_status launch_sorted(const SamplerView &v, bool centered, uint64_t seed, uint64_t first, uint64_t k,
                                uint64_t *tally, unsigned blocks, hipStream_t s)
 {
-    const uint64_t chunk = std::min<uint64_t>(k, kSortedChunk);
     Temps tmp(s);
     SortBufs b{};
-    char *scr = nullptr;
-    PM_TRY(tmp.get(&b.kin, (size_t)chunk));
-    PM_TRY(tmp.get(&b.k0, (size_t)chunk));
-    PM_TRY(tmp.get(&b.v0, (size_t)chunk));
-    PM_TRY(tmp.get(&b.k1, (size_t)chunk));
-    PM_TRY(tmp.get(&b.v1, (size_t)chunk));
-    PM_TRY(tmp.get(&scr, radix_scratch_bytes((int64_t)chunk)));
-    b.scr = scr;
-    b.chunk = chunk;
+    PM_TRY(sort_bufs(tmp, k, &b));
     return launch_sorted_in(v, centered, seed, first, k, tally, blocks, s, b);
 }
 
@@ -326,6 +348,47 @@ pm_status adjacent(const pm_graph *g, const int32_t *a, const int32_t *b, int64_
     return PM_OK;
 }
 
+// Is a sampler's launch draw-ordered in a single sort chunk?
+static bool one_sorted_chunk(const SamplerView &v, uint64_t k)
+{
+    return v.R > 1 && k > 0 && k >= draw_order_min() && draw_order_enabled() && k <= kSortedChunk;
+}
+
+// Both samplers draw-ordered in one chunk each: the centered sampler's keys
+// are drawn and sorted on a side stream while the caller's stream sorts the
+// 3-path sampler's and runs its samples; the centered samples follow on s
+// once the side stream has joined.  The two sorts are small launches that
+// leave the GPU partly idle, so side by side they take less time than in
+// turn (sorting the centered ids beside the 3-path sampling kernel instead
+// slows that kernel by more than it saves).  Each sampler runs the same
+// kernels on the same ids as in sequence, so the tallies are the same.
+static pm_status sample_pair_overlapped(const pm_graph *g, const pm_params *p, uint64_t *tallies, hipStream_t s)
+{
+    const SamplerView vp = view_of(g, false), vc = view_of(g, true);
+    const unsigned cap = (unsigned)((uint64_t)sampler_cu_count(g->device) * (uint64_t)g_blocks_per_cu.load());
+    Temps tmp(s);
+    SortBufs bp{}, bc{};
+    PM_TRY(sort_bufs(tmp, p->k_path, &bp));
+    PM_TRY(sort_bufs(tmp, p->k_cent, &bc));
+    hipStream_t side[2];
+    PM_HIP(side_streams(side));
+    uint32_t *ids_c = nullptr;
+    {
+        Fork fork(s, side, 1);  // joined before the temporaries are released on s
+        PM_HIP(fork.status);
+        PM_TRY(sort_chunk(vc, true, p->seed, p->first_id_cent, p->k_cent, cap, side[0], bc, &ids_c));
+        {
+            ProfScope prof("sample_path", s);
+            uint32_t *ids_p = nullptr;
+            PM_TRY(sort_chunk(vp, false, p->seed, p->first_id_path, p->k_path, cap, s, bp, &ids_p));
+            PM_TRY(sample_chunk(vp, false, p->seed, p->first_id_path, p->k_path, ids_p, tallies, cap, s));
+        }
+        PM_HIP(fork.join());
+    }
+    ProfScope prof("sample_centered", s);
+    return sample_chunk(vc, true, p->seed, p->first_id_cent, p->k_cent, ids_c, tallies + PM_NUM_TALLIES, cap, s);
+}
+
 pm_status sample_async(const pm_graph *g, const pm_params *p, uint64_t *tallies_dev, hipStream_t s)
 {
     if (!g || !p || !tallies_dev) {
@@ -334,6 +397,8 @@ pm_status sample_async(const pm_graph *g, const pm_params *p, uint64_t *tallies_
     }
     PM_TRY(check_device(g));
     PM_TRY(fill_async<uint64_t>(tallies_dev, 0ull, 2 * PM_NUM_TALLIES, s));
+    if (one_sorted_chunk(view_of(g, false), p->k_path) && one_sorted_chunk(view_of(g, true), p->k_cent))
+        return sample_pair_overlapped(g, p, tallies_dev, s);
     PM_TRY(launch_sampler(g, false, p->seed, p->first_id_path, p->k_path, tallies_dev, s));
     PM_TRY(launch_sampler(g, true, p->seed, p->first_id_cent, p->k_cent, tallies_dev + PM_NUM_TALLIES, s));
     return PM_OK;

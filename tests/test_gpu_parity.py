@@ -380,6 +380,11 @@ def test_draw_order_does_not_change_tallies():
         a = g.count(k, k, seed=3, first_path=7, first_cent=2 ** 33)
         assert a["tally_path"] == og.sample_path(3, k, 7).tolist()
         assert a["tally_cent"] == og.sample_centered(3, k, 2 ** 33).tolist()
+        # one sampler draw-ordered, the other below the threshold (the two are
+        # then launched in turn instead of with their sorts side by side)
+        mixed = g.count(k, 5000, seed=3, first_path=7, first_cent=2 ** 33)
+        assert mixed["tally_path"] == a["tally_path"]
+        assert mixed["tally_cent"] == og.sample_centered(3, 5000, 2 ** 33).tolist()
         for mode in (ps.SEARCH_LANE, ps.SEARCH_WAVE):  # the sorted-row searches over draw-ordered ids
             ps.set_search_mode(mode)
             a2 = g.count(k, k, seed=3, first_path=7, first_cent=2 ** 33)
