@@ -13,6 +13,29 @@ namespace pm {
 constexpr int kHashChunk = 2048;             // slots per block of the small-row kernel
 constexpr int kHashSmall = kHashSmallBound;  // degree bound of the small-row kernel
 constexpr int kHashSpan = 2 * (kHashChunk + kHashSmall);  // entries a small-row block can own
+// slots per thread of a small-row block: its rows start in one chunk, so they
+// span fewer than kHashChunk + kHashSmall slots
+constexpr int kHashRun = (kHashChunk + kHashSmall + kBlock - 1) / kBlock;
+constexpr int kHashBatch = 8;  // keys a thread loads before handling them
+
+// f(key) for the keys src[j], j in [j0, j1), this thread's share of the
+// block (stride blockDim.x); kHashBatch keys are loaded before any of them
+// is handled, so their loads overlap.  j1 < 2^31.
+template <typename F>
+__device__ __forceinline__ void for_keys(const uint32_t *__restrict__ src, uint32_t j0, uint32_t j1, F f)
+{
+    for (uint32_t base = j0 + threadIdx.x; base < j1; base += kHashBatch * blockDim.x) {
+        uint32_t kv[kHashBatch];
+#pragma unroll
+        for (int q = 0; q < kHashBatch; ++q) {
+            const uint32_t j = base + q * blockDim.x;
+            kv[q] = j < j1 ? src[j] : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < kHashBatch; ++q)
+            if (base + q * blockDim.x < j1) f(kv[q]);
+    }
+}
 
 // insert key into the row's entries t[0, size) (LDS), probing from its home
 __device__ __forceinline__ void lds_insert(uint32_t *t, uint32_t size, uint32_t key)
@@ -59,11 +82,15 @@ __global__ __launch_bounds__(kBlock) void k_rowhash_small(const uint32_t *__rest
     for (uint32_t i = threadIdx.x; i < span; i += blockDim.x) t[i] = kHashEmpty;
     __syncthreads();
     // each thread a run of consecutive slots: one search for the run's first
-    // row, then the rows follow in order
+    // row, then the rows follow in order; the run's keys are loaded together
+    // before the first insert
     const uint32_t nslots = roff[nrows] - first;
     const uint32_t per = (nslots + blockDim.x - 1) / blockDim.x;
     const uint32_t r0 = threadIdx.x * per, r1 = r0 + per < nslots ? r0 + per : nslots;
     if (r0 < r1) {
+        uint32_t kv[kHashRun];
+#pragma unroll
+        for (int q = 0; q < kHashRun; ++q) kv[q] = r0 + q < r1 ? col[first + r0 + q] : 0u;
         int64_t lo = 0, hi = nrows;  // last row start <= first + r0
         while (hi - lo > 1) {
             const int64_t mid = (lo + hi) >> 1;
@@ -72,7 +99,15 @@ __global__ __launch_bounds__(kBlock) void k_rowhash_small(const uint32_t *__rest
             else
                 hi = mid;
         }
-        for (uint32_t i = r0; i < r1; ++i) {
+#pragma unroll
+        for (int q = 0; q < kHashRun; ++q) {
+            const uint32_t i = r0 + q;
+            if (i >= r1) break;
+            while (roff[lo + 1] <= first + i) ++lo;
+            const uint32_t rb = roff[lo], d = roff[lo + 1] - rb;
+            lds_insert(t + 2u * (rb - first), 2u * d, kv[q]);
+        }
+        for (uint32_t i = r0 + kHashRun; i < r1; ++i) {  // never taken while the bound above holds
             while (roff[lo + 1] <= first + i) ++lo;
             const uint32_t rb = roff[lo], d = roff[lo + 1] - rb;
             lds_insert(t + 2u * (rb - first), 2u * d, col[first + i]);
@@ -136,10 +171,10 @@ __global__ __launch_bounds__(1024) void k_rowhash_sort(const uint32_t *__restric
         const uint32_t gw = nwin - g0 < kHashGroup ? nwin - g0 : kHashGroup;
         for (uint32_t i = threadIdx.x; i < gw; i += blockDim.x) cnt[i] = 0;
         __syncthreads();
-        for (uint32_t j = threadIdx.x; j < d; j += blockDim.x) {
-            const uint32_t w = hash_home(col[rb + j], size) / kHashWin;
+        for_keys(col + rb, 0u, d, [&](uint32_t key) {
+            const uint32_t w = hash_home(key, size) / kHashWin;
             if (w >= g0 && w - g0 < gw) atomicAdd(&cnt[w - g0], 1u);
-        }
+        });
         __syncthreads();
         if (threadIdx.x == 0) {  // exclusive starts, kept as the scatter cursors
             uint32_t run = placed;
@@ -152,11 +187,10 @@ __global__ __launch_bounds__(1024) void k_rowhash_sort(const uint32_t *__restric
             placed = run;
         }
         __syncthreads();
-        for (uint32_t j = threadIdx.x; j < d; j += blockDim.x) {
-            const uint32_t key = col[rb + j];
+        for_keys(col + rb, 0u, d, [&](uint32_t key) {
             const uint32_t w = hash_home(key, size) / kHashWin;
             if (w >= g0 && w - g0 < gw) keys[atomicAdd(&cnt[w - g0], 1u)] = key;
-        }
+        });
         __syncthreads();  // (only thread 0's `placed` is used)
     }
 }
@@ -210,11 +244,11 @@ __global__ __launch_bounds__(kBlock) void k_rowhash_window(const uint32_t *__res
         }
     };
     if (nwin == 1) {
-        for (uint32_t j = threadIdx.x; j < d; j += blockDim.x) insert(col[rb + j]);
+        for_keys(col + rb, 0u, d, insert);
     } else {
         const uint32_t *keys = part + (rb - off[r_sort]);
         const uint32_t k0 = wstart[wb + wi], k1 = wi + 1 < nwin ? wstart[wb + wi + 1] : d;
-        for (uint32_t j = k0 + threadIdx.x; j < k1; j += blockDim.x) insert(keys[j]);
+        for_keys(keys, k0, k1, insert);
     }
     __syncthreads();
     uint32_t *out = H + 2ull * rb + w0;
