@@ -1106,11 +1106,12 @@ void graph_free(pm_graph *g, hipStream_t s)
     delete g;
 }
 
+// The row hash (rowhash.hip): `parts` is kRowHashSmall, kRowHashWide or both.
+pm_status build_rowhash(const pm_graph *g, const int64_t rows[5], const int64_t slot_at[5], uint32_t *H,
+                        hipStream_t s, int parts);
+
 // Device bytes a prepared graph of n vertices and `slots` directed slots
 // holds (what graph_create adds up in pm_graph::bytes).
-pm_status build_rowhash(const pm_graph *g, const int64_t rows[5], const int64_t slot_at[5], uint32_t *H,
-                        hipStream_t s);
-
 uint64_t graph_bytes_for(int64_t n, int64_t slots)
 {
     const uint64_t nn = (uint64_t)std::max<int64_t>(n, 1), ss = (uint64_t)std::max<int64_t>(slots, 1);
@@ -1392,19 +1393,19 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
     static_assert(kHashSmallBound == 1024, "row hash classes follow the row classes");
     PM_TRY(dev_alloc((void **)&g->hash, sizeof(uint32_t) * (2 * ss + kHashPad), s));
     g->bytes += sizeof(uint32_t) * (2 * ss + kHashPad);
-    // built on a side stream beside the reverse sort and the weights pass
-    // (it reads only the finished rows), joined back before returning
+    // built on a side stream (it reads only the finished rows) and joined back
+    // before returning: the rows of degree <= 1024 beside the reverse sort,
+    // the longer ones beside the weights pass, so that each of the two
+    // shares the GPU with a part of the build
     hipStream_t hside[2];
     PM_HIP(side_streams(hside));
     Fork hfork(s, hside, 1);
     PM_HIP(hfork.status);
-    {
-        // row classes 0, 5..8: degree above 0, 1024, 4096, 8192, 16384
-        const int64_t rows[5] = {cls[0], cls[5], cls[6], cls[7], cls[8]};
-        const int64_t slot_at[5] = {cls[kRowClasses + 1 + 0], cls[kRowClasses + 1 + 5], cls[kRowClasses + 1 + 6],
-                                    cls[kRowClasses + 1 + 7], cls[kRowClasses + 1 + 8]};
-        PM_TRY(build_rowhash(g, rows, slot_at, g->hash, hside[0]));
-    }
+    // row classes 0, 5..8: degree above 0, 1024, 4096, 8192, 16384
+    const int64_t hrows[5] = {cls[0], cls[5], cls[6], cls[7], cls[8]};
+    const int64_t hslot_at[5] = {cls[kRowClasses + 1 + 0], cls[kRowClasses + 1 + 5], cls[kRowClasses + 1 + 6],
+                                 cls[kRowClasses + 1 + 7], cls[kRowClasses + 1 + 8]};
+    PM_TRY(build_rowhash(g, hrows, hslot_at, g->hash, hside[0], kRowHashSmall));
 
     uint32_t *ka, *kb, *vfree, *v2a;
     PM_TRY(tmp.get(&ka, ss));
@@ -1417,6 +1418,9 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
     uint32_t *keys_unused, *rev;
     PM_TRY(radix_sort("reverse_sort", g->col, nullptr, kb, vfree, ka, v2a, slots, vbits, rscr, s, &keys_unused, &rev,
                       nullptr, nullptr, false));
+    Fork hfork2(s, hside, 1);  // the side stream now also waits for the reverse sort
+    PM_HIP(hfork2.status);
+    PM_TRY(build_rowhash(g, hrows, hslot_at, g->hash, hside[0], kRowHashWide));
 
     // weights, their prefixes and the guide tables of the edge draws (nothing
     // below indexes memory through the weights until the checks are read back)
@@ -1506,6 +1510,7 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
         g->nb_lam = ((g->R_lam - 1) >> g->shift_lam) + 1;
     }
 
+    PM_HIP(hfork2.join());
     PM_HIP(hfork.join());
     PM_HIP(hipStreamSynchronize(s));
     guard.g = nullptr;

@@ -300,23 +300,24 @@ __global__ __launch_bounds__(kBlock) void k_rowhash_repair(const uint32_t *__res
 // rows[c] = first row with degree above bound[c] of {0, kHashSmallBound,
 // 4096, 8192, 16384}, slot_at[c] = that row's first slot (rows ascend by
 // degree; rows before rows[0] have no slots).  H has 2 slots + kHashPad
-// entries.
+// entries.  `parts` selects the rows built (kRowHashSmall, kRowHashWide);
+// the two parts write disjoint entries and may run on different streams.
 pm_status build_rowhash(const pm_graph *g, const int64_t rows[5], const int64_t slot_at[5], uint32_t *H,
-                        hipStream_t s)
+                        hipStream_t s, int parts)
 {
     const int64_t n = g->n, slots = g->slots;
     static_assert(2 * 4096 == kHashWin, "rows of degree up to 4096 are one window");
     ProfScope prof("rowhash", s);
-    PM_TRY(fill_async<uint32_t>(H + 2 * slots, kHashEmpty, kHashPad, s));  // padding reads as empty
+    if (parts & kRowHashSmall) PM_TRY(fill_async<uint32_t>(H + 2 * slots, kHashEmpty, kHashPad, s));  // padding reads as empty
     const int64_t small_end = slot_at[1];
-    if (small_end > 0) {
+    if ((parts & kRowHashSmall) && small_end > 0) {
         ProfScope pc("rowhash.small", s);
         const int64_t blocks = (small_end + kHashChunk - 1) / kHashChunk;
         hipLaunchKernelGGL(k_rowhash_small, dim3((unsigned)blocks), dim3(kBlock), 0, s, g->off, g->col, rows[0],
                            rows[1], small_end, H);
         PM_HIP(hipGetLastError());
     }
-    if (n > rows[1]) {
+    if ((parts & kRowHashWide) && n > rows[1]) {
         ProfScope pc("rowhash.wide", s);
         const int64_t r_begin = rows[1], r_sort = rows[2];  // rows above 1024; above 4096 (several windows)
         const int64_t wide_slots = slots - slot_at[1];

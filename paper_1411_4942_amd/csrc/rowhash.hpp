@@ -20,6 +20,9 @@ constexpr int64_t kHashPad = 8;              // entries after the last row (wind
 // the build takes rows up to this degree many per block, longer rows in
 // windows (the row classes of the preparation's row build bound it too)
 constexpr int kHashSmallBound = 1024;
+// the parts of the build: the rows of degree <= kHashSmallBound (with the
+// padding after the last row), the longer rows
+constexpr int kRowHashSmall = 1, kRowHashWide = 2;
 
 // MurmurHash3's 32-bit finalizer (Appleby, public domain): spreads the bits
 // of a column id over the word.
