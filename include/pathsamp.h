@@ -13,6 +13,12 @@
  *  - "stream" arguments are hipStream_t values passed as void*; NULL means
  *    the default stream.  Calls that take a stream return after the results
  *    they report are on the host (they synchronise that stream).
+ *  - A call may run part of its work on the library's own side streams (two
+ *    per device, default priority): they wait for the work already on
+ *    `stream`, and `stream` waits for them before anything the call enqueues
+ *    after them, so everything the call does is ordered on `stream` as if it
+ *    ran there (pm_sample_async's tallies are complete once `stream` has
+ *    passed the call).
  *  - The caller owns every buffer it passes in; the library never frees or
  *    keeps a pointer to caller memory past the call.
  *  - No C++ exception crosses this boundary.
