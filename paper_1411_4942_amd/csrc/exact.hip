@@ -334,70 +334,122 @@ __device__ __forceinline__ unsigned __int128 wave_sum128(unsigned __int128 v)
     return v;
 }
 
-// Vertices x = n-1-b for b < n_top (the highest ids, hubs first), then
-// the spilled ones: counted in the block's own counter array of n words.
-// Blocks take the next b from a queue, so the hubs' unequal work spreads
-// over the blocks as it comes (a fixed stride left the busiest block 1.27x
-// the mean at R-MAT scale 22).
+// Vertices x = n-1-b for b < n_top (the highest ids, hubs first), then the
+// spilled ones; blocks take the next b from a queue, so the hubs' unequal
+// work spreads over the blocks as it comes.  The opposite vertices y < x are
+// counted one range of kC4Range ids at a time in LDS.  Each lower neighbour
+// w of x keeps a cursor into its row (rows ascend, so the entries of one
+// range follow those of the range before): per range a lane reads the
+// cursor and the id it points at, and walks the row's segment inside the
+// range only when that id lies in it.  A row is thus read segment by
+// segment, about once over all ranges, instead of one random counter update
+// in global memory per wedge.  Lanes walk up to kC4LaneRun entries of a
+// segment; longer segments go to an LDS queue that whole waves walk 64
+// entries at a time.
 constexpr int kC4Threads = 1024;
-// LDS counters for the highest ids: all of a 160 KB LDS but the few words
-// below (at R-MAT scale 22 they take 44% of the wedges, 16384 of them 26%)
-constexpr int kC4Hot = 40928;
+constexpr uint32_t kC4Range = 40448;  // LDS counters per range (all of a 160 KB LDS but the words below)
+constexpr uint32_t kC4LongCap = 256;  // queued long segments per range
+constexpr int kC4LaneRun = 16;        // entries a lane walks before queueing the rest of a segment
+constexpr uint32_t kC4Inf = 0xFFFFFFFFu;
 
+// state[i] of the i-th lower neighbour w of the current x: {cursor into row
+// w, end of row w, id at the cursor (kC4Inf past the end), unused}
 __global__ __launch_bounds__(kC4Threads) void k_four_cycles(const uint32_t *__restrict__ off,
                                                             const uint32_t *__restrict__ col,
                                                             const uint32_t *__restrict__ split, int64_t n,
                                                             int64_t n_top, const uint32_t *__restrict__ spill,
-                                                            const uint32_t *n_spill, uint32_t *__restrict__ cnt_all,
-                                                            uint32_t *__restrict__ touched_all, uint32_t *queue,
-                                                            ExactAcc *acc)
+                                                            const uint32_t *n_spill, uint4 *__restrict__ state_all,
+                                                            uint64_t cap, uint32_t *queue, ExactAcc *acc)
 {
-    __shared__ uint32_t s_nt, s_b;
-    __shared__ uint32_t hot[kC4Hot];  // counters of the kC4Hot highest ids (the hubs every wedge ends on)
-    uint32_t *cnt = cnt_all + (int64_t)blockIdx.x * n;
-    uint32_t *touched = touched_all + (int64_t)blockIdx.x * n;
-    const int w_id = threadIdx.x / kWave, lane = lane_id(), nw = kC4Threads / kWave;
+    __shared__ uint32_t cnt[kC4Range];
+    __shared__ uint32_t longq[kC4LongCap];
+    __shared__ uint32_t s_b, s_nlong;
+    uint4 *state = state_all + (uint64_t)blockIdx.x * cap;
+    const int tid = threadIdx.x, w_id = tid / kWave, lane = lane_id(), nw = kC4Threads / kWave;
     const int64_t total = n_top + (int64_t)*n_spill;
-    const uint32_t hot0 = n > kC4Hot ? (uint32_t)(n - kC4Hot) : 0u;
-    for (int i = threadIdx.x; i < kC4Hot; i += kC4Threads) hot[i] = 0;
+    for (uint32_t i = tid; i < kC4Range; i += kC4Threads) cnt[i] = 0;
     unsigned __int128 n4 = 0;
     for (;;) {
-        if (threadIdx.x == 0) {
-            s_b = atomicAdd(queue, 1u);
-            s_nt = 0;
-        }
+        if (tid == 0) s_b = atomicAdd(queue, 1u);
         __syncthreads();
         const int64_t b = s_b;
+        __syncthreads();  // every thread has read s_b before thread 0 writes it again
         if (b >= total) break;  // block-uniform
-        const int64_t x = b < n_top ? n - 1 - b : (int64_t)spill[b - n_top];
-        const int64_t lo_end = off[x] + split[x];
-        for (int64_t p = off[x] + w_id; p < lo_end; p += nw) {
-            const uint32_t w = col[p];  // w < x
-            const int64_t r0 = off[w], r1 = off[w + 1];
-            for (int64_t q = r0 + lane; q < r1; q += kWave) {
-                const uint32_t y = col[q];
-                if (y >= (uint32_t)x) break;  // rows ascending: the rest are higher too
-                if (y >= hot0)
-                    atomicAdd(&hot[y - hot0], 1u);
-                else if (atomicAdd(&cnt[y], 1u) == 0u)
-                    touched[atomicAdd(&s_nt, 1u)] = y;
+        const uint32_t x = b < n_top ? (uint32_t)(n - 1 - b) : spill[b - n_top];
+        const uint32_t lo = off[x], D = split[x];  // N-(x) = col[lo, lo + D)
+        if (D < 2) continue;  // fewer than two wedges per pair (block-uniform)
+        for (uint32_t i = tid; i < D; i += kC4Threads) {
+            const uint32_t w = col[lo + i], c = off[w], e = off[w + 1];
+            state[i] = make_uint4(c, e, c < e ? col[c] : kC4Inf, 0u);
+        }
+        for (uint32_t r0 = 0; r0 < x; r0 += kC4Range) {
+            const uint32_t E = x - r0 < kC4Range ? x : r0 + kC4Range;  // this range: ids [r0, E)
+            if (tid == 0) s_nlong = 0;
+            __syncthreads();  // the state, the cleared counters and s_nlong are in place
+            for (uint32_t i = tid; i < D; i += kC4Threads) {
+                const uint4 st = state[i];
+                if (st.z >= E) continue;  // nothing of row w in this range
+                uint32_t p = st.x, nxt = kC4Inf;
+                const uint32_t end = st.y;
+                bool queued = false, lane_only = false;
+                for (int taken = 0;;) {
+                    uint32_t v[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) v[j] = p + j < end ? col[p + j] : kC4Inf;
+                    int j = 0;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        if (j < q || v[q] >= E) continue;  // stop at the first id past the range
+                        atomicAdd(&cnt[v[q] - r0], 1u);
+                        j = q + 1;
+                    }
+                    p += j;
+                    if (j < 4) {
+                        nxt = v[j];  // the first id >= E, or kC4Inf past the row's end
+                        break;
+                    }
+                    taken += 4;
+                    if (!lane_only && taken >= kC4LaneRun) {
+                        const uint32_t q = atomicAdd(&s_nlong, 1u);
+                        if (q < kC4LongCap) {
+                            longq[q] = i;
+                            queued = true;
+                            break;
+                        }
+                        lane_only = true;  // the queue is full: this lane walks on
+                    }
+                }
+                state[i] = make_uint4(p, end, queued ? 0u : nxt, 0u);
             }
-        }
-        __syncthreads();
-        const uint32_t nt = s_nt;
-        for (uint32_t i = threadIdx.x; i < nt; i += blockDim.x) {
-            const uint32_t y = touched[i];
-            const uint64_t c = cnt[y];
-            n4 += (unsigned __int128)(c * (c - 1) / 2);
-            cnt[y] = 0;
-        }
-        if ((uint32_t)x > hot0)  // block-uniform: hot counters below x may be set
-            for (uint32_t i = threadIdx.x; i < (uint32_t)x - hot0; i += blockDim.x) {
-                const uint64_t c = hot[i];
+            __syncthreads();
+            // the long segments, a wave each, 64 entries per step (a prefix of
+            // each step's ids lies in the range: rows ascend)
+            const uint32_t nl = s_nlong < kC4LongCap ? s_nlong : kC4LongCap;
+            for (uint32_t q = w_id; q < nl; q += nw) {  // wave-uniform
+                const uint32_t i = longq[q];
+                const uint4 st = state[i];
+                uint32_t p = st.x, nxt = kC4Inf;
+                for (;;) {
+                    const uint32_t idx = p + lane;
+                    const uint32_t y = idx < st.y ? col[idx] : kC4Inf;
+                    const bool in = y < E;
+                    if (in) atomicAdd(&cnt[y - r0], 1u);
+                    const uint32_t c = (uint32_t)__popcll(__ballot(in));
+                    p += c;
+                    if (c < (uint32_t)kWave) {
+                        nxt = __shfl(y, (int)c, kWave);
+                        break;
+                    }
+                }
+                if (lane == 0) state[i] = make_uint4(p, st.y, nxt, 0u);
+            }
+            __syncthreads();
+            for (uint32_t j = tid; j < E - r0; j += kC4Threads) {
+                const uint64_t c = cnt[j];
                 n4 += (unsigned __int128)(c * (c - 1) / 2);
-                hot[i] = 0;
+                cnt[j] = 0;
             }
-        __syncthreads();  // counters clear, s_b read, before the next x
+        }
     }
     n4 = wave_sum128(n4);
     if (lane == 0 && n4) add128(&acc->n4_lo, &acc->n4_hi, n4);
@@ -480,8 +532,7 @@ pm_status exact_counts(const pm_graph *g, pm_exact *out, hipStream_t s)
             PM_HIP(hipGetLastError());
         }
         // 4-cycles: vertices of degree at most kC4LdsDegree in LDS tables,
-        // the rest (and any whose table fills) with one counter array and
-        // one touched list of n words per block
+        // the rest (and any whose table fills) range by range in LDS
         constexpr uint32_t kC4LdsDegree = 1024;
         ProfScope prof("exact.four_cycles", s);
         int64_t *xb_d = nullptr;
@@ -497,15 +548,18 @@ pm_status exact_counts(const pm_graph *g, pm_exact *out, hipStream_t s)
         if (x_big > 0)
             hipLaunchKernelGGL(k_four_cycles_lds, dim3((unsigned)std::min<int64_t>(x_big, 16384)), dim3(kBlock), 0, s,
                                g->off, g->col, split, x_big, spill, n_spill, acc);
-        const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(256, n));
-        uint32_t *cnt = nullptr, *touched = nullptr, *queue = nullptr;
-        PM_TRY(tmp.get(&cnt, (size_t)blocks * (size_t)n));
-        PM_TRY(tmp.get(&touched, (size_t)blocks * (size_t)n));
+        // one cursor state (16 bytes) per lower neighbour of the block's
+        // current vertex: at most dmax, within a 4 GiB budget of blocks
+        const uint64_t cap = (uint64_t)std::max<int64_t>(g->dmax, 1);
+        const int blocks = (int)std::max<uint64_t>(
+            1, std::min<uint64_t>(std::min<uint64_t>(256, (uint64_t)n), (4ull << 30) / (cap * sizeof(uint4))));
+        uint4 *state = nullptr;
+        uint32_t *queue = nullptr;
+        PM_TRY(tmp.get(&state, (size_t)blocks * (size_t)cap));
         PM_TRY(tmp.get(&queue, 1));
-        PM_TRY(fill_async<uint32_t>(cnt, 0u, (int64_t)blocks * n, s));
         PM_TRY(fill_async<uint32_t>(queue, 0u, 1, s));
         hipLaunchKernelGGL(k_four_cycles, dim3(blocks), dim3(kC4Threads), 0, s, g->off, g->col, split, n, n - x_big,
-                           spill, n_spill, cnt, touched, queue, acc);
+                           spill, n_spill, state, cap, queue, acc);
         PM_HIP(hipGetLastError());
     }
     ExactAcc h;
