@@ -90,72 +90,43 @@ __global__ __launch_bounds__(kBlock) void k_split(const uint32_t *__restrict__ o
     }
 }
 
-// One forward slot s = (u, v), v > u, per thread: the triangles {u, v, w},
-// w > v, found by merging N+(u) beyond v with N+(v); each adds one to t_e of
-// its three edges (slots (u,v), (u,w), (v,w), all forward).
-__global__ __launch_bounds__(kBlock) void k_triangles(const uint32_t *__restrict__ off,
-                                                      const uint32_t *__restrict__ col,
-                                                      const SlotRec *__restrict__ rec,
-                                                      const uint32_t *__restrict__ split, int64_t slots,
-                                                      uint32_t *__restrict__ t_e, ExactAcc *acc)
-{
-    unsigned long long tri = 0;
-    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < slots;
-         s += (int64_t)gridDim.x * blockDim.x) {
-        const SlotRec e = rec[s];
-        const uint32_t u = e.row, v = e.col;
-        if (v <= u) continue;
-        const int64_t a1 = off[u + 1];
-        const int64_t b0 = off[v] + split[v], b1 = off[v + 1];
-        int64_t i = s + 1, j = b0;
-        uint32_t here = 0;
-        while (i < a1 && j < b1) {
-            const uint32_t x = col[i], y = col[j];
-            if (x < y) {
-                ++i;
-            } else if (y < x) {
-                ++j;
-            } else {
-                ++here;
-                atomicAdd(&t_e[i], 1u);  // (u, w)
-                atomicAdd(&t_e[j], 1u);  // (v, w)
-                ++i;
-                ++j;
-            }
-        }
-        if (here) atomicAdd(&t_e[s], here);  // (u, v)
-        tri += here;
-    }
-    const unsigned __int128 bt = block_sum128<kBlock>(tri);
-    if (threadIdx.x == 0 && bt) atomicAdd(&acc->tri, (unsigned long long)bt);
-}
-
-// 4-cliques at their lowest vertex u, one u per block at a time (vertices
-// with lo < d+(u) <= 32 W; W words of 32 bits per row).  Row i of the graph
-// induced on N+(u) = {ids[0] < ids[1] < ...} has bit j when ids[i] ~ ids[j],
-// j > i (only forward neighbours are looked up).  A clique {u, v_i, v_j, v_k}
-// (i < j < k) is bit k of row i & row j for each bit j of row i, so each is
-// counted once, by whole words.  Rows live in LDS (`rows` null) or, for long
-// forward rows, in the block's slice of a global scratch array.
+// Triangles and 4-cliques at their lowest vertex u, one u per block at a time
+// (vertices with lo < d+(u) <= 32 W; W words of 32 bits per row).  Row i of
+// the graph induced on N+(u) = {ids[0] < ids[1] < ...} has bit j when
+// ids[i] ~ ids[j], j > i (only forward neighbours are looked up).
+//  - Each bit is a triangle {u, v_i, v_j}, found once.  It adds one to t_e
+//    of its three edges: (v_i, v_j) at the forward slot p of row v_i where
+//    the lookup found v_j, and (u, v_i), (u, v_j) at u's own forward slots
+//    (counted per member in the block, then added once per slot).
+//  - A clique {u, v_i, v_j, v_k} (i < j < k) is bit k of row i & row j for
+//    each bit j of row i, so each is counted once, by whole words.
+// Rows and member counters live in LDS (`scratch` null) or, for long forward
+// rows, in the block's slice of a global scratch array.
 template <int W, bool GLOBAL>
 __global__ __launch_bounds__(kBlock) void k_cliques(const uint32_t *__restrict__ off,
                                                     const uint32_t *__restrict__ col,
                                                     const uint32_t *__restrict__ split, int64_t n, uint32_t lo_d,
-                                                    uint32_t hi_d, uint32_t *__restrict__ scratch, ExactAcc *acc)
+                                                    uint32_t hi_d, uint32_t *__restrict__ scratch,
+                                                    uint32_t *__restrict__ t_e, ExactAcc *acc)
 {
     constexpr int kLdsIds = GLOBAL ? 1 : 32 * W;
     constexpr int kLdsRows = GLOBAL ? 1 : 32 * W * W;
     __shared__ uint32_t s_ids[kLdsIds];
+    __shared__ uint32_t s_tri[kLdsIds];  // triangles on (u, ids[i])
     __shared__ uint32_t s_rows[kLdsRows];
     const uint32_t wd = GLOBAL ? (hi_d + 31) / 32 : (uint32_t)W;  // words per row
-    uint32_t *ids = GLOBAL ? scratch + (uint64_t)blockIdx.x * ((uint64_t)hi_d * wd + hi_d) : s_ids;
-    uint32_t *rows = GLOBAL ? ids + hi_d : s_rows;
+    uint32_t *ids = GLOBAL ? scratch + (uint64_t)blockIdx.x * ((uint64_t)hi_d * wd + 2ull * hi_d) : s_ids;
+    uint32_t *tri_u = GLOBAL ? ids + hi_d : s_tri;
+    uint32_t *rows = GLOBAL ? ids + 2ull * hi_d : s_rows;
     const int wv = threadIdx.x / kWave, lane = lane_id(), nwv = kBlock / kWave;
-    unsigned long long k4 = 0;
+    unsigned long long k4 = 0, tri = 0;
     for (int64_t u = blockIdx.x; u < n; u += gridDim.x) {
         const uint32_t beg = off[u] + split[u], D = off[u + 1] - beg;
         if (D <= lo_d || D > hi_d) continue;  // block-uniform
-        for (uint32_t i = threadIdx.x; i < D; i += kBlock) ids[i] = col[beg + i];
+        for (uint32_t i = threadIdx.x; i < D; i += kBlock) {
+            ids[i] = col[beg + i];
+            tri_u[i] = 0;
+        }
         for (uint64_t i = threadIdx.x; i < (uint64_t)D * wd; i += kBlock) rows[i] = 0;
         if (GLOBAL) __threadfence();  // the cleared rows, before the atomics below
         __syncthreads();
@@ -173,11 +144,19 @@ __global__ __launch_bounds__(kBlock) void k_cliques(const uint32_t *__restrict__
                     else
                         hi = mid;
                 }
-                if (lo < D && ids[lo] == x) atomicOr(&rows[(uint64_t)i * wd + (lo >> 5)], 1u << (lo & 31));
+                if (lo < D && ids[lo] == x) {  // the triangle {u, v, x}
+                    atomicOr(&rows[(uint64_t)i * wd + (lo >> 5)], 1u << (lo & 31));
+                    ++tri;
+                    atomicAdd(&t_e[p], 1u);  // (v, x)
+                    atomicAdd(&tri_u[i], 1u);
+                    atomicAdd(&tri_u[lo], 1u);
+                }
             }
         }
         if (GLOBAL) __threadfence();  // the finished rows, before they are read back
         __syncthreads();
+        for (uint32_t i = threadIdx.x; i < D; i += kBlock)  // (u, ids[i]): other lowest vertices add here too
+            if (tri_u[i]) atomicAdd(&t_e[beg + i], tri_u[i]);
         for (uint32_t i = threadIdx.x; i < D; i += kBlock) {
             const uint32_t *ri = rows + (uint64_t)i * wd;
             for (uint32_t wj = 0; wj < wd; ++wj) {
@@ -194,6 +173,8 @@ __global__ __launch_bounds__(kBlock) void k_cliques(const uint32_t *__restrict__
     }
     const unsigned __int128 bk = block_sum128<kBlock>(k4);
     if (threadIdx.x == 0 && bk) atomicAdd(&acc->k4, (unsigned long long)bk);
+    const unsigned __int128 bt = block_sum128<kBlock>(tri);
+    if (threadIdx.x == 0 && bt) atomicAdd(&acc->tri, (unsigned long long)bt);
 }
 
 // largest forward degree d+(u)
@@ -492,18 +473,11 @@ pm_status exact_counts(const pm_graph *g, pm_exact *out, hipStream_t s)
         PM_TRY(fill_async<uint32_t>(t_e, 0u, slots, s));
         hipLaunchKernelGGL(k_split, dim3(grid_for(n, kBlock, 1 << 22)), dim3(kBlock), 0, s, g->off, g->col, n, split);
         {
-            ProfScope prof("exact.triangles", s);
-            hipLaunchKernelGGL(k_triangles, dim3(grid_for(slots, kBlock, 1 << 16)), dim3(kBlock), 0, s, g->off,
-                               g->col, g->rec, split, slots, t_e, acc);
-        }
-        hipLaunchKernelGGL(k_edge_sums, dim3(grid_for(slots, kBlock, 4096)), dim3(kBlock), 0, s, g->off, g->rec,
-                           t_e, slots, acc);
-        PM_HIP(hipGetLastError());
-        tmp.release(t_e);
-        {
-            // 4-cliques by forward degree class: rows in LDS up to 1024
-            // members, in a global slice per block above
-            ProfScope prof("exact.cliques", s);
+            // triangles (with t_e) and 4-cliques by forward degree class:
+            // rows in LDS up to 1024 members, in a global slice per block
+            // above; vertices with fewer than two forward neighbours close
+            // neither
+            ProfScope prof("exact.triangles_cliques", s);
             uint32_t *dmax_d = nullptr;
             PM_TRY(tmp.get(&dmax_d, 1));
             PM_TRY(fill_async<uint32_t>(dmax_d, 0u, 1, s));
@@ -513,23 +487,26 @@ pm_status exact_counts(const pm_graph *g, pm_exact *out, hipStream_t s)
             PM_HIP(hipMemcpyAsync(&dmax, dmax_d, sizeof(dmax), hipMemcpyDeviceToHost, s));
             PM_HIP(hipStreamSynchronize(s));
             const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(n, 8192));
-            hipLaunchKernelGGL((k_cliques<2, false>), dim3(grid), dim3(kBlock), 0, s, g->off, g->col, split, n, 2u,
-                               64u, nullptr, acc);
+            hipLaunchKernelGGL((k_cliques<2, false>), dim3(grid), dim3(kBlock), 0, s, g->off, g->col, split, n, 1u,
+                               64u, nullptr, t_e, acc);
             hipLaunchKernelGGL((k_cliques<8, false>), dim3(grid), dim3(kBlock), 0, s, g->off, g->col, split, n, 64u,
-                               256u, nullptr, acc);
+                               256u, nullptr, t_e, acc);
             hipLaunchKernelGGL((k_cliques<32, false>), dim3(grid), dim3(kBlock), 0, s, g->off, g->col, split, n, 256u,
-                               1024u, nullptr, acc);
+                               1024u, nullptr, t_e, acc);
             if (dmax > 1024) {
                 const uint32_t wd = (dmax + 31) / 32;
-                const uint64_t slice = ((uint64_t)dmax * wd + dmax) * sizeof(uint32_t);
+                const uint64_t slice = ((uint64_t)dmax * wd + 2ull * dmax) * sizeof(uint32_t);
                 // blocks with a slice each, at most 1 GiB of slices
                 const unsigned gb = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(256, (1ull << 30) / slice));
                 uint32_t *scr = nullptr;
-                PM_TRY(tmp.get(&scr, (size_t)gb * ((size_t)dmax * wd + dmax)));
+                PM_TRY(tmp.get(&scr, (size_t)gb * ((size_t)dmax * wd + 2ull * dmax)));
                 hipLaunchKernelGGL((k_cliques<1, true>), dim3(gb), dim3(kBlock), 0, s, g->off, g->col, split, n, 1024u,
-                                   dmax, scr, acc);
+                                   dmax, scr, t_e, acc);
             }
+            hipLaunchKernelGGL(k_edge_sums, dim3(grid_for(slots, kBlock, 4096)), dim3(kBlock), 0, s, g->off, g->rec,
+                               t_e, slots, acc);
             PM_HIP(hipGetLastError());
+            tmp.release(t_e);
         }
         // 4-cycles: vertices of degree at most kC4LdsDegree in LDS tables,
         // the rest (and any whose table fills) range by range in LDS
