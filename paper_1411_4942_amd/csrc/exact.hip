@@ -72,6 +72,26 @@ __device__ unsigned __int128 block_sum128(unsigned __int128 v)
     return (unsigned __int128)s_lo[0] | ((unsigned __int128)s_hi[0] << 64);
 }
 
+// Sum of one 64-bit value per lane over the wave, valid in lane 0.
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_down(v, d, kWave);
+    return v;
+}
+
+// Sum of one 128-bit value per lane over the wave, valid in lane 0.
+__device__ __forceinline__ unsigned __int128 wave_sum128(unsigned __int128 v)
+{
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        const unsigned long long lo = __shfl_down((unsigned long long)v, d, kWave);
+        const unsigned long long hi = __shfl_down((unsigned long long)(v >> 64), d, kWave);
+        v += (unsigned __int128)lo | ((unsigned __int128)hi << 64);
+    }
+    return v;
+}
+
 // split[x] = number of neighbours of x below x (rows ascending)
 __global__ __launch_bounds__(kBlock) void k_split(const uint32_t *__restrict__ off, const uint32_t *__restrict__ col,
                                                   int64_t n, uint32_t *__restrict__ split)
@@ -101,34 +121,61 @@ __global__ __launch_bounds__(kBlock) void k_split(const uint32_t *__restrict__ o
 //  - A clique {u, v_i, v_j, v_k} (i < j < k) is bit k of row i & row j for
 //    each bit j of row i, so each is counted once, by whole words.
 // Rows and member counters live in LDS (`scratch` null) or, for long forward
-// rows, in the block's slice of a global scratch array.
-template <int W, bool GLOBAL>
-__global__ __launch_bounds__(kBlock) void k_cliques(const uint32_t *__restrict__ off,
+// rows, in the block's slice of a global scratch array.  A member is found
+// in an LDS hash of N+(u) (id -> index, at most half full: one or two
+// reads) in the LDS classes, by binary search in the global one.
+constexpr uint32_t kNoId = 0xFFFFFFFFu;  // an empty member-hash slot (vertex ids are below 2^31)
+
+template <int W, bool GLOBAL, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_cliques(const uint32_t *__restrict__ off,
                                                     const uint32_t *__restrict__ col,
                                                     const uint32_t *__restrict__ split, int64_t n, uint32_t lo_d,
-                                                    uint32_t hi_d, uint32_t *__restrict__ scratch,
+                                                    uint32_t hi_d, uint32_t *__restrict__ scratch, uint32_t gslots,
                                                     uint32_t *__restrict__ t_e, ExactAcc *acc)
 {
     constexpr int kLdsIds = GLOBAL ? 1 : 32 * W;
     constexpr int kLdsRows = GLOBAL ? 1 : 32 * W * W;
+    constexpr uint32_t kSlots = GLOBAL ? 1 : 64 * W;  // member hash: twice the members
     __shared__ uint32_t s_ids[kLdsIds];
     __shared__ uint32_t s_tri[kLdsIds];  // triangles on (u, ids[i])
     __shared__ uint32_t s_rows[kLdsRows];
+    __shared__ uint32_t h_key[kSlots];   // member id, or kNoId
+    __shared__ uint16_t h_idx[kSlots];   // its index in ids
+    // GLOBAL with gslots > 0: ids, their counters and a member hash of gslots
+    // slots (a power of two >= 2 hi_d) in dynamic LDS; gslots = 0: ids and
+    // counters in the block's global slice, members found by binary search
+    extern __shared__ uint32_t dyn[];
     const uint32_t wd = GLOBAL ? (hi_d + 31) / 32 : (uint32_t)W;  // words per row
-    uint32_t *ids = GLOBAL ? scratch + (uint64_t)blockIdx.x * ((uint64_t)hi_d * wd + 2ull * hi_d) : s_ids;
+    const uint32_t slots = GLOBAL ? gslots : kSlots;
+    uint32_t *const slice = GLOBAL ? scratch + (uint64_t)blockIdx.x * ((uint64_t)hi_d * wd + 2ull * hi_d) : nullptr;
+    uint32_t *ids = GLOBAL ? (gslots ? dyn : slice) : s_ids;
     uint32_t *tri_u = GLOBAL ? ids + hi_d : s_tri;
-    uint32_t *rows = GLOBAL ? ids + 2ull * hi_d : s_rows;
-    const int wv = threadIdx.x / kWave, lane = lane_id(), nwv = kBlock / kWave;
+    uint32_t *rows = GLOBAL ? slice + 2ull * hi_d : s_rows;
+    uint32_t *hkey = GLOBAL ? dyn + 2ull * hi_d : h_key;
+    uint16_t *hidx = GLOBAL ? reinterpret_cast<uint16_t *>(dyn + 2ull * hi_d + gslots) : h_idx;
+    const int wv = threadIdx.x / kWave, lane = lane_id(), nwv = THREADS / kWave;
     unsigned long long k4 = 0, tri = 0;
     for (int64_t u = blockIdx.x; u < n; u += gridDim.x) {
         const uint32_t beg = off[u] + split[u], D = off[u + 1] - beg;
         if (D <= lo_d || D > hi_d) continue;  // block-uniform
-        for (uint32_t i = threadIdx.x; i < D; i += kBlock) {
+        for (uint32_t i = threadIdx.x; i < D; i += THREADS) {
             ids[i] = col[beg + i];
             tri_u[i] = 0;
         }
-        for (uint64_t i = threadIdx.x; i < (uint64_t)D * wd; i += kBlock) rows[i] = 0;
+        for (uint64_t i = threadIdx.x; i < (uint64_t)D * wd; i += THREADS) rows[i] = 0;
         if (GLOBAL) __threadfence();  // the cleared rows, before the atomics below
+        if (slots) {
+            for (uint32_t i = threadIdx.x; i < slots; i += THREADS) hkey[i] = kNoId;
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < D; i += THREADS) {  // D <= slots / 2: a free slot is always found
+                const uint32_t key = ids[i];
+                for (uint32_t h = hash_mix32(key) & (slots - 1);; h = (h + 1) & (slots - 1))
+                    if (atomicCAS(&hkey[h], kNoId, key) == kNoId) {
+                        hidx[h] = (uint16_t)i;
+                        break;
+                    }
+            }
+        }
         __syncthreads();
         // rows: each wave takes a member v_i and looks its forward neighbours up
         for (uint32_t i = wv; i < D; i += nwv) {
@@ -136,15 +183,29 @@ __global__ __launch_bounds__(kBlock) void k_cliques(const uint32_t *__restrict__
             const uint32_t vb = off[v] + split[v], ve = off[v + 1];
             for (uint32_t p = vb + lane; p < ve; p += kWave) {
                 const uint32_t x = col[p];
-                uint32_t lo = i + 1, hi = D;  // x > v = ids[i]
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (ids[mid] < x)
-                        lo = mid + 1;
-                    else
-                        hi = mid;
+                uint32_t lo = D;  // x's index in ids (> i: x > v = ids[i]), D if absent
+                if (!slots) {
+                    uint32_t hi = D;
+                    lo = i + 1;
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (ids[mid] < x)
+                            lo = mid + 1;
+                        else
+                            hi = mid;
+                    }
+                    if (lo < D && ids[lo] != x) lo = D;
+                } else {
+                    for (uint32_t h = hash_mix32(x) & (slots - 1);; h = (h + 1) & (slots - 1)) {
+                        const uint32_t k = hkey[h];
+                        if (k == x) {
+                            lo = hidx[h];
+                            break;
+                        }
+                        if (k == kNoId) break;
+                    }
                 }
-                if (lo < D && ids[lo] == x) {  // the triangle {u, v, x}
+                if (lo < D) {  // the triangle {u, v, x}
                     atomicOr(&rows[(uint64_t)i * wd + (lo >> 5)], 1u << (lo & 31));
                     ++tri;
                     atomicAdd(&t_e[p], 1u);  // (v, x)
@@ -155,9 +216,9 @@ __global__ __launch_bounds__(kBlock) void k_cliques(const uint32_t *__restrict__
         }
         if (GLOBAL) __threadfence();  // the finished rows, before they are read back
         __syncthreads();
-        for (uint32_t i = threadIdx.x; i < D; i += kBlock)  // (u, ids[i]): other lowest vertices add here too
+        for (uint32_t i = threadIdx.x; i < D; i += THREADS)  // (u, ids[i]): other lowest vertices add here too
             if (tri_u[i]) atomicAdd(&t_e[beg + i], tri_u[i]);
-        for (uint32_t i = threadIdx.x; i < D; i += kBlock) {
+        for (uint32_t i = threadIdx.x; i < D; i += THREADS) {
             const uint32_t *ri = rows + (uint64_t)i * wd;
             for (uint32_t wj = 0; wj < wd; ++wj) {
                 uint32_t bits = ri[wj];
@@ -171,10 +232,11 @@ __global__ __launch_bounds__(kBlock) void k_cliques(const uint32_t *__restrict__
         }
         __syncthreads();  // the rows are rebuilt for the next u
     }
-    const unsigned __int128 bk = block_sum128<kBlock>(k4);
-    if (threadIdx.x == 0 && bk) atomicAdd(&acc->k4, (unsigned long long)bk);
-    const unsigned __int128 bt = block_sum128<kBlock>(tri);
-    if (threadIdx.x == 0 && bt) atomicAdd(&acc->tri, (unsigned long long)bt);
+    // per-wave sums (a block reduction's LDS would not fit beside the rows)
+    k4 = wave_sum_u64(k4);
+    tri = wave_sum_u64(tri);
+    if (lane == 0 && k4) atomicAdd(&acc->k4, k4);
+    if (lane == 0 && tri) atomicAdd(&acc->tri, tri);
 }
 
 // largest forward degree d+(u)
@@ -301,18 +363,6 @@ __global__ __launch_bounds__(kBlock) void k_four_cycles_lds(const uint32_t *__re
     }
     n4 = block_sum128<kBlock>(n4);
     if (threadIdx.x == 0 && n4) add128(&acc->n4_lo, &acc->n4_hi, n4);
-}
-
-// Sum of one 128-bit value per lane over the wave, valid in lane 0.
-__device__ __forceinline__ unsigned __int128 wave_sum128(unsigned __int128 v)
-{
-#pragma unroll
-    for (int d = kWave / 2; d > 0; d >>= 1) {
-        const unsigned long long lo = __shfl_down((unsigned long long)v, d, kWave);
-        const unsigned long long hi = __shfl_down((unsigned long long)(v >> 64), d, kWave);
-        v += (unsigned __int128)lo | ((unsigned __int128)hi << 64);
-    }
-    return v;
 }
 
 // Vertices x = n-1-b for b < n_top (the highest ids, hubs first), then the
@@ -487,21 +537,36 @@ pm_status exact_counts(const pm_graph *g, pm_exact *out, hipStream_t s)
             PM_HIP(hipMemcpyAsync(&dmax, dmax_d, sizeof(dmax), hipMemcpyDeviceToHost, s));
             PM_HIP(hipStreamSynchronize(s));
             const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(n, 8192));
-            hipLaunchKernelGGL((k_cliques<2, false>), dim3(grid), dim3(kBlock), 0, s, g->off, g->col, split, n, 1u,
-                               64u, nullptr, t_e, acc);
-            hipLaunchKernelGGL((k_cliques<8, false>), dim3(grid), dim3(kBlock), 0, s, g->off, g->col, split, n, 64u,
-                               256u, nullptr, t_e, acc);
-            hipLaunchKernelGGL((k_cliques<32, false>), dim3(grid), dim3(kBlock), 0, s, g->off, g->col, split, n, 256u,
-                               1024u, nullptr, t_e, acc);
+            {
+                ProfScope pc("exact.cliques.64", s);
+                hipLaunchKernelGGL((k_cliques<2, false, kBlock>), dim3(grid), dim3(kBlock), 0, s, g->off, g->col, split, n,
+                                   1u, 64u, nullptr, 0u, t_e, acc);
+            }
+            {
+                ProfScope pc("exact.cliques.256", s);
+                hipLaunchKernelGGL((k_cliques<8, false, kBlock>), dim3(grid), dim3(kBlock), 0, s, g->off, g->col, split, n,
+                                   64u, 256u, nullptr, 0u, t_e, acc);
+            }
+            {
+                ProfScope pc("exact.cliques.1024", s);
+                hipLaunchKernelGGL((k_cliques<32, false, 1024>), dim3(grid), dim3(1024), 0, s, g->off, g->col, split, n,
+                                   256u, 1024u, nullptr, 0u, t_e, acc);
+            }
             if (dmax > 1024) {
+                ProfScope pc("exact.cliques.global", s);
                 const uint32_t wd = (dmax + 31) / 32;
                 const uint64_t slice = ((uint64_t)dmax * wd + 2ull * dmax) * sizeof(uint32_t);
                 // blocks with a slice each, at most 1 GiB of slices
                 const unsigned gb = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(256, (1ull << 30) / slice));
                 uint32_t *scr = nullptr;
                 PM_TRY(tmp.get(&scr, (size_t)gb * ((size_t)dmax * wd + 2ull * dmax)));
-                hipLaunchKernelGGL((k_cliques<1, true>), dim3(gb), dim3(kBlock), 0, s, g->off, g->col, split, n, 1024u,
-                                   dmax, scr, t_e, acc);
+                // ids, counters and the member hash in LDS when they fit in 64 KB
+                uint32_t gslots = 1;
+                while (gslots < 2 * dmax) gslots <<= 1;
+                const size_t dyn = (2ull * dmax + gslots) * sizeof(uint32_t) + gslots * sizeof(uint16_t);
+                const bool in_lds = dmax < 65536 && dyn <= (64u << 10);
+                hipLaunchKernelGGL((k_cliques<1, true, 1024>), dim3(gb), dim3(1024), in_lds ? dyn : 0, s, g->off, g->col,
+                                   split, n, 1024u, dmax, scr, in_lds ? gslots : 0u, t_e, acc);
             }
             hipLaunchKernelGGL(k_edge_sums, dim3(grid_for(slots, kBlock, 4096)), dim3(kBlock), 0, s, g->off, g->rec,
                                t_e, slots, acc);

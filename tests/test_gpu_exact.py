@@ -85,15 +85,18 @@ def test_exact_counts_equal_oracle(name, graph):
     _check(name, off, col, got)
 
 
-def test_exact_counts_complete_1100_closed_form():
-    """K_1100: C(1100, 4) 4-cliques and nothing else; its lowest vertex has
-    1099 forward neighbours, past the LDS classes of the clique counter."""
-    _say("exact K1100")
-    off, col = synth.complete(1100)
+@pytest.mark.parametrize("n", [1100, 2800])
+def test_exact_counts_complete_closed_form(n):
+    """K_n: C(n, 4) 4-cliques and nothing else.  Its lowest vertices have up
+    to n - 1 forward neighbours, past the LDS classes of the clique counter:
+    for n = 1100 the members and their hash still fit in LDS beside rows in
+    global memory; for n = 2800 they do not, and members are found by binary
+    search in global memory."""
+    _say(f"exact K{n}")
+    off, col = synth.complete(n)
     g = ps.Graph(*_dev(off, col))
     got = g.exact()
     g.destroy()
-    n = 1100
     assert got["C"][1:] == [0, 0, 0, 0, 0, n * (n - 1) * (n - 2) * (n - 3) // 24]
     assert got["triangles"] == n * (n - 1) * (n - 2) // 6
 
