@@ -363,37 +363,44 @@ static __global__ void radix_pair_copy(const uint32_t *__restrict__ k, const uin
     }
 }
 
-inline pm_status radix_sort(const char *name, const uint32_t *in_k, const uint32_t *in_v, uint32_t *k0, uint32_t *v0,
-                            uint32_t *k1, uint32_t *v1, int64_t N, int bits, void *scratch, hipStream_t s,
-                            uint32_t **out_k, uint32_t **out_v, uint64_t *pair_out = nullptr,
-                            uint32_t *sample_out = nullptr, bool keys_wanted = true)
-{
-    const std::string n_hist = std::string(name) + ".histogram", n_scan = std::string(name) + ".count_scan",
-                      n_scat = std::string(name) + ".scatter";
-    *out_k = k0;
-    *out_v = v0;
-    if (N <= 1 || bits <= 0) {
-        // nothing to sort: copy the input through (values, pairs, samples)
-        if (N > 0) {
-            hipLaunchKernelGGL(radix_pair_copy, dim3(grid_for(N, kBlock, 1 << 22)), dim3(kBlock), 0, s, in_k, in_v, N,
-                               pair_out, sample_out, v0);
-            PM_HIP(hipGetLastError());
-            if (!pair_out) PM_HIP(hipMemcpyAsync(k0, in_k, sizeof(uint32_t) * N, hipMemcpyDeviceToDevice, s));
-        }
-        if (pair_out) *out_k = nullptr;
-        return PM_OK;
+// One stable LSD sort as a sequence of 8-bit passes, enqueued one at a time
+// by step() (two sorts on two streams can then be enqueued pass by pass, so
+// that neither stream waits for the host to enqueue the other's passes).
+// Arguments as radix_sort; N > 1 and bits > 0.
+struct RadixRun {
+    std::string n_hist, n_scan, n_scat;
+    const uint32_t *ki, *vi;
+    uint32_t *k0, *v0, *k1, *v1, *ko, *vo;
+    int64_t N, tiles, chunks;
+    int bits, shift = 0;
+    uint32_t *counts, *offs, *chunk;
+    hipStream_t s;
+    uint64_t *pair_out;
+    uint32_t *sample_out;
+    bool keys_wanted;
+    uint32_t *out_k, *out_v;
+
+    RadixRun(const char *name, const uint32_t *in_k, const uint32_t *in_v, uint32_t *k0_, uint32_t *v0_,
+             uint32_t *k1_, uint32_t *v1_, int64_t N_, int bits_, void *scratch, hipStream_t s_,
+             uint64_t *pair_out_ = nullptr, uint32_t *sample_out_ = nullptr, bool keys_wanted_ = true)
+        : n_hist(std::string(name) + ".histogram"), n_scan(std::string(name) + ".count_scan"),
+          n_scat(std::string(name) + ".scatter"), ki(in_k), vi(in_v), k0(k0_), v0(v0_), k1(k1_), v1(v1_), ko(k0_),
+          vo(v0_), N(N_), bits(bits_), s(s_), pair_out(pair_out_), sample_out(sample_out_),
+          keys_wanted(keys_wanted_), out_k(k0_), out_v(v0_)
+    {
+        tiles = (N + kRadixTile - 1) / kRadixTile;
+        chunks = (tiles + kRadixChunk - 1) / kRadixChunk;
+        counts = (uint32_t *)scratch;
+        offs = counts + tiles * kRadixBins;
+        chunk = offs + tiles * kRadixBins;
     }
-    const int64_t tiles = (N + kRadixTile - 1) / kRadixTile;
-    const int64_t cnt = tiles * kRadixBins;
-    const int64_t chunks = (tiles + kRadixChunk - 1) / kRadixChunk;
-    uint32_t *counts = (uint32_t *)scratch;
-    uint32_t *offs = counts + cnt;
-    uint32_t *chunk = offs + cnt;
-    const uint32_t *ki = in_k, *vi = in_v;
-    uint32_t *ko = k0, *vo = v0;
-    for (int shift = 0; shift < bits; shift += 8) {
-        int nb = bits - shift < 8 ? bits - shift : 8;
-        uint32_t mask = (1u << nb) - 1u;
+    bool done() const { return shift >= bits; }
+
+    // the next pass: histogram, count scan, scatter
+    pm_status step()
+    {
+        const int nb = bits - shift < 8 ? bits - shift : 8;
+        const uint32_t mask = (1u << nb) - 1u;
         {
             ProfScope prof(n_hist.c_str(), s);
             hipLaunchKernelGGL(radix_histogram, dim3((unsigned)tiles), dim3(kRadixThreads), 0, s, ki, N, shift, mask,
@@ -418,14 +425,40 @@ inline pm_status radix_sort(const char *name, const uint32_t *in_k, const uint32
                                offs, tiles, kw, vo, po, so);
             PM_HIP(hipGetLastError());
         }
-        *out_k = ko;
-        *out_v = vo;
+        out_k = ko;
+        out_v = vo;
         ki = ko;
         vi = vo;
         ko = (ko == k0) ? k1 : k0;
         vo = (vo == v0) ? v1 : v0;
+        shift += 8;
+        if (done() && (pair_out || !keys_wanted)) out_k = nullptr;
+        return PM_OK;
     }
-    if (pair_out || !keys_wanted) *out_k = nullptr;
+};
+
+inline pm_status radix_sort(const char *name, const uint32_t *in_k, const uint32_t *in_v, uint32_t *k0, uint32_t *v0,
+                            uint32_t *k1, uint32_t *v1, int64_t N, int bits, void *scratch, hipStream_t s,
+                            uint32_t **out_k, uint32_t **out_v, uint64_t *pair_out = nullptr,
+                            uint32_t *sample_out = nullptr, bool keys_wanted = true)
+{
+    *out_k = k0;
+    *out_v = v0;
+    if (N <= 1 || bits <= 0) {
+        // nothing to sort: copy the input through (values, pairs, samples)
+        if (N > 0) {
+            hipLaunchKernelGGL(radix_pair_copy, dim3(grid_for(N, kBlock, 1 << 22)), dim3(kBlock), 0, s, in_k, in_v, N,
+                               pair_out, sample_out, v0);
+            PM_HIP(hipGetLastError());
+            if (!pair_out) PM_HIP(hipMemcpyAsync(k0, in_k, sizeof(uint32_t) * N, hipMemcpyDeviceToDevice, s));
+        }
+        if (pair_out) *out_k = nullptr;
+        return PM_OK;
+    }
+    RadixRun r(name, in_k, in_v, k0, v0, k1, v1, N, bits, scratch, s, pair_out, sample_out, keys_wanted);
+    while (!r.done()) PM_TRY(r.step());
+    *out_k = r.out_k;
+    *out_v = r.out_v;
     return PM_OK;
 }
 
