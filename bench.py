@@ -771,11 +771,11 @@ def main():
     roofline_prep = roofline_for(prep_dom, prep_kernels[prep_dom], prep_alg[prep_dom], traffic, copy_gbs)
     # the bytes of a multi-kernel scope are those of the whole preparation
     # (the row hash is built in two calls): time it per preparation
-    def prep_ms(n):
+    def scope_ms(n):
         return prep_kernels[n]["ms_per_step"] if n in multi else prep_kernels[n]["avg_ms"]
 
-    roofline_prep_all = {n: {"achieved_gbs": prep_alg[n][0] / (prep_ms(n) * 1e-3) / 1e9,
-                             "frac": prep_alg[n][0] / (prep_ms(n) * 1e-3) / 1e9 / HBM_PEAK_GBS,
+    roofline_prep_all = {n: {"achieved_gbs": prep_alg[n][0] / (scope_ms(n) * 1e-3) / 1e9,
+                             "frac": prep_alg[n][0] / (scope_ms(n) * 1e-3) / 1e9 / HBM_PEAK_GBS,
                              "ms_per_step": prep_kernels[n]["ms_per_step"]}
                          for n in prep_alg if n in prep_kernels}
     samp_ms = [kernels[n]["avg_ms"] for n in ("sample_path", "sample_centered") if n in kernels]
