@@ -471,7 +471,7 @@ pm_status sample_alias_async(const pm_graph *g, const pm_params *p, uint64_t *ta
     };
     if (one_chunk(g->R_tau, p->k_path) && one_chunk(g->R_lam, p->k_cent)) {
         // as the main draw does: the centered sampler's ids sorted on a side
-        // stream beside the 3-path sampler's sort and samples
+        // stream beside the 3-path sampler's sort, joined before the samples
         const SamplerView vp = view_of(g, false), vc = view_of(g, true);
         const AliasEntry *Tp = (const AliasEntry *)g->alias_tau, *Tc = (const AliasEntry *)g->alias_lam;
         const unsigned cap = (unsigned)((uint64_t)sampler_cu_count(g->device) * 4u);
@@ -481,19 +481,18 @@ pm_status sample_alias_async(const pm_graph *g, const pm_params *p, uint64_t *ta
         PM_TRY(alias_sort_bufs(tmp, p->k_cent, &bc));
         hipStream_t side[2];
         PM_HIP(side_streams(side));
-        uint32_t *ids_c = nullptr;
+        uint32_t *ids_c = nullptr, *ids_p = nullptr;
         {
             Fork fork(s, side, 1);  // joined before the temporaries are released on s
             PM_HIP(fork.status);
             PM_TRY(alias_sort_chunk(N, true, p->seed, p->first_id_cent, p->k_cent, cap, side[0], bc, &ids_c));
-            {
-                ProfScope prof("sample_path_alias", s);
-                uint32_t *ids_p = nullptr;
-                PM_TRY(alias_sort_chunk(N, false, p->seed, p->first_id_path, p->k_path, cap, s, bp, &ids_p));
-                PM_TRY(alias_sample_chunk(vp, Tp, N, false, p->seed, p->first_id_path, p->k_path, ids_p, tallies_dev,
-                                          cap, s));
-            }
-            PM_HIP(fork.join());
+            PM_TRY(alias_sort_chunk(N, false, p->seed, p->first_id_path, p->k_path, cap, s, bp, &ids_p));
+            PM_HIP(fork.join());  // before the 3-path kernel, as the main draw does
+        }
+        {
+            ProfScope prof("sample_path_alias", s);
+            PM_TRY(alias_sample_chunk(vp, Tp, N, false, p->seed, p->first_id_path, p->k_path, ids_p, tallies_dev, cap,
+                                      s));
         }
         ProfScope prof("sample_centered_alias", s);
         return alias_sample_chunk(vc, Tc, N, true, p->seed, p->first_id_cent, p->k_cent, ids_c,

@@ -356,12 +356,12 @@ static bool one_sorted_chunk(const SamplerView &v, uint64_t k)
 
 // Both samplers draw-ordered in one chunk each: the centered sampler's keys
 // are drawn and sorted on a side stream while the caller's stream sorts the
-// 3-path sampler's and runs its samples; the centered samples follow on s
-// once the side stream has joined.  The two sorts are small launches that
-// leave the GPU partly idle, so side by side they take less time than in
-// turn (sorting the centered ids beside the 3-path sampling kernel instead
-// slows that kernel by more than it saves).  Each sampler runs the same
-// kernels on the same ids as in sequence, so the tallies are the same.
+// 3-path sampler's; the side stream joins s before the 3-path samples, and
+// the centered samples follow.  The two sorts are small launches that leave
+// the GPU partly idle, so side by side they take less time than in turn
+// (sorting the centered ids beside the 3-path sampling kernel instead slows
+// that kernel by more than it saves).  Each sampler runs the same kernels on
+// the same ids as in sequence, so the tallies are the same.
 static pm_status sample_pair_overlapped(const pm_graph *g, const pm_params *p, uint64_t *tallies, hipStream_t s)
 {
     const SamplerView vp = view_of(g, false), vc = view_of(g, true);
@@ -372,18 +372,20 @@ static pm_status sample_pair_overlapped(const pm_graph *g, const pm_params *p, u
     PM_TRY(sort_bufs(tmp, p->k_cent, &bc));
     hipStream_t side[2];
     PM_HIP(side_streams(side));
-    uint32_t *ids_c = nullptr;
+    uint32_t *ids_c = nullptr, *ids_p = nullptr;
     {
+        ProfScope prof("draw_sorts", s);
         Fork fork(s, side, 1);  // joined before the temporaries are released on s
         PM_HIP(fork.status);
         PM_TRY(sort_chunk(vc, true, p->seed, p->first_id_cent, p->k_cent, cap, side[0], bc, &ids_c));
-        {
-            ProfScope prof("sample_path", s);
-            uint32_t *ids_p = nullptr;
-            PM_TRY(sort_chunk(vp, false, p->seed, p->first_id_path, p->k_path, cap, s, bp, &ids_p));
-            PM_TRY(sample_chunk(vp, false, p->seed, p->first_id_path, p->k_path, ids_p, tallies, cap, s));
-        }
+        PM_TRY(sort_chunk(vp, false, p->seed, p->first_id_path, p->k_path, cap, s, bp, &ids_p));
+        // joined before the 3-path kernel: a sort still running beside it
+        // slows it by more than the join costs
         PM_HIP(fork.join());
+    }
+    {
+        ProfScope prof("sample_path", s);
+        PM_TRY(sample_chunk(vp, false, p->seed, p->first_id_path, p->k_path, ids_p, tallies, cap, s));
     }
     ProfScope prof("sample_centered", s);
     return sample_chunk(vc, true, p->seed, p->first_id_cent, p->k_cent, ids_c, tallies + PM_NUM_TALLIES, cap, s);
