@@ -368,7 +368,9 @@ __global__ __launch_bounds__(kBlock) void k_four_cycles_lds(const uint32_t *__re
 // Vertices x = n-1-b for b < n_top (the highest ids, hubs first), then the
 // spilled ones; blocks take the next b from a queue, so the hubs' unequal
 // work spreads over the blocks as it comes.  The opposite vertices y < x are
-// counted one range of kC4Range ids at a time in LDS.  Each lower neighbour
+// counted one range of ids at a time in LDS: kC4Range 32-bit counters, or
+// twice as many 16-bit ones when x has fewer than 2^16 lower neighbours (a
+// pair's count never exceeds them).  Each lower neighbour
 // w of x keeps a cursor into its row (rows ascend, so the entries of one
 // range follow those of the range before): per range a lane reads the
 // cursor and the id it points at, and walks the row's segment inside the
@@ -413,8 +415,19 @@ __global__ __launch_bounds__(kC4Threads) void k_four_cycles(const uint32_t *__re
             const uint32_t w = col[lo + i], c = off[w], e = off[w + 1];
             state[i] = make_uint4(c, e, c < e ? col[c] : kC4Inf, 0u);
         }
-        for (uint32_t r0 = 0; r0 < x; r0 += kC4Range) {
-            const uint32_t E = x - r0 < kC4Range ? x : r0 + kC4Range;  // this range: ids [r0, E)
+        // a pair's count is at most D: below 2^16, two 16-bit counters share a
+        // word and a range spans twice the ids
+        const bool half = D < 65536u;
+        const uint32_t span = half ? 2 * kC4Range : kC4Range;
+        const auto bump = [&](uint32_t y, uint32_t r0) {
+            const uint32_t o = y - r0;
+            if (half)
+                atomicAdd(&cnt[o >> 1], 1u << ((o & 1u) << 4));
+            else
+                atomicAdd(&cnt[o], 1u);
+        };
+        for (uint32_t r0 = 0; r0 < x; r0 += span) {
+            const uint32_t E = x - r0 < span ? x : r0 + span;  // this range: ids [r0, E)
             if (tid == 0) s_nlong = 0;
             __syncthreads();  // the state, the cleared counters and s_nlong are in place
             for (uint32_t i = tid; i < D; i += kC4Threads) {
@@ -431,7 +444,7 @@ __global__ __launch_bounds__(kC4Threads) void k_four_cycles(const uint32_t *__re
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         if (j < q || v[q] >= E) continue;  // stop at the first id past the range
-                        atomicAdd(&cnt[v[q] - r0], 1u);
+                        bump(v[q], r0);
                         j = q + 1;
                     }
                     p += j;
@@ -464,7 +477,7 @@ __global__ __launch_bounds__(kC4Threads) void k_four_cycles(const uint32_t *__re
                     const uint32_t idx = p + lane;
                     const uint32_t y = idx < st.y ? col[idx] : kC4Inf;
                     const bool in = y < E;
-                    if (in) atomicAdd(&cnt[y - r0], 1u);
+                    if (in) bump(y, r0);
                     const uint32_t c = (uint32_t)__popcll(__ballot(in));
                     p += c;
                     if (c < (uint32_t)kWave) {
@@ -475,9 +488,16 @@ __global__ __launch_bounds__(kC4Threads) void k_four_cycles(const uint32_t *__re
                 if (lane == 0) state[i] = make_uint4(p, st.y, nxt, 0u);
             }
             __syncthreads();
-            for (uint32_t j = tid; j < E - r0; j += kC4Threads) {
-                const uint64_t c = cnt[j];
-                n4 += (unsigned __int128)(c * (c - 1) / 2);
+            const uint32_t words = half ? (E - r0 + 1) / 2 : E - r0;
+            for (uint32_t j = tid; j < words; j += kC4Threads) {
+                const uint32_t wv = cnt[j];
+                if (half) {
+                    const uint64_t c0 = wv & 0xFFFFu, c1 = wv >> 16;
+                    n4 += (unsigned __int128)(c0 * (c0 - 1) / 2 + c1 * (c1 - 1) / 2);
+                } else {
+                    const uint64_t c = wv;
+                    n4 += (unsigned __int128)(c * (c - 1) / 2);
+                }
                 cnt[j] = 0;
             }
         }

@@ -101,6 +101,22 @@ def test_exact_counts_complete_closed_form(n):
     assert got["triangles"] == n * (n - 1) * (n - 2) // 6
 
 
+@pytest.mark.parametrize("m", [60000, 70000])
+def test_exact_counts_k2m_closed_form(m):
+    """K_{2,m}: the higher hub's m lower neighbours (the leaves) all pair it
+    with the other hub, so that pair's wedge count is m: just below 2^16
+    (m = 60000, the 4-cycle counter's 16-bit mode) or above it (m = 70000,
+    its 32-bit mode).  Induced counts: 2 C(m, 3) 3-stars and C(m, 2)
+    4-cycles, nothing else."""
+    _say(f"exact K2,{m}")
+    off, col = synth.complete_bipartite(2, m)
+    g = ps.Graph(*_dev(off, col))
+    got = g.exact()
+    g.destroy()
+    assert got["C"][1:] == [2 * (m * (m - 1) * (m - 2) // 6), 0, 0, m * (m - 1) // 2, 0, 0]
+    assert got["triangles"] == 0
+
+
 def test_exact_counts_chunglu_1e6_1e7():
     _say("exact chung-lu 1e6/1e7")
     off_d, col_d = synth.chung_lu_torch(1_000_000, 10_000_000, 2.3, 5000.0, 1, device="cuda")
