@@ -370,11 +370,11 @@ __global__ __launch_bounds__(kBlock) void k_four_cycles_lds(const uint32_t *__re
 // work spreads over the blocks as it comes.  The opposite vertices y < x are
 // counted one range of ids at a time in LDS: kC4Range 32-bit counters, or
 // twice as many 16-bit ones when x has fewer than 2^16 lower neighbours (a
-// pair's count never exceeds them).  Each lower neighbour
-// w of x keeps a cursor into its row (rows ascend, so the entries of one
-// range follow those of the range before): per range a lane reads the
-// cursor and the id it points at, and walks the row's segment inside the
-// range only when that id lies in it.  A row is thus read segment by
+// pair's count never exceeds them).  Each lower neighbour w of x keeps a
+// cursor into its row (rows ascend, so the entries of one range follow
+// those of the range before): per range a lane reads the cursor and the id
+// it points at, and walks the row's segment inside the range only when that
+// id lies in it.  A row is thus read segment by
 // segment, about once over all ranges, instead of one random counter update
 // in global memory per wedge.  Lanes walk up to kC4LaneRun entries of a
 // segment; longer segments go to an LDS queue that whole waves walk 64
