@@ -169,7 +169,7 @@ pm_status pm_count(const pm_graph *g, const pm_params *p, pm_result *out, void *
  * same samples, tallies and results as pm_count, with every device buffer
  * it needs in a fixed array inside the library instead of allocated: both
  * samplers' tallies and the buffers of one draw-order sort chunk of 2^22
- * sample ids, 82 MiB in all (pm_static_scratch_bytes).  Each device the
+ * sample ids, 68 MiB in all (pm_static_scratch_bytes).  Each device the
  * library runs on holds its own copy of the array until the process ends.
  * Budgets above one chunk are sorted and sampled chunk by chunk, so no k is
  * rejected for size.  The call allocates nothing (no hipMalloc, hipFree or
@@ -457,6 +457,19 @@ pm_status pm_set_sampler_shape(int32_t samples_per_lane, int32_t blocks_per_cu);
  * the graph; each sample then runs as usual.  Tallies are sums over ids and
  * do not change: enabled = 0 gives the same results in id order. */
 pm_status pm_set_draw_order(int32_t enabled, uint64_t min_samples);
+
+/* The order in which a draw-ordered launch runs one sort chunk of a sampler
+ * (samples first_id .. first_id + k - 1, 1 <= k <= 2^24): ids_out[j] =
+ * id - first_id of the j-th sample run.  The ids are in nondecreasing order
+ * of the draw key of pm_set_draw_order (the top 24 bits of the sample's r of
+ * Algorithm 1 step 2 for centered = 0, Algorithm 3 step 2 for centered = 1;
+ * all of r when the sampler's total weight is below 2^24); the order among
+ * equal keys is unspecified.  ids_out is a device array of k entries, written
+ * asynchronously on `stream`.  Errors: PM_EINVAL (null arguments, k out of
+ * range, a sampler whose total weight is below 2, another device's graph),
+ * PM_ENOMEM, PM_EDEVICE. */
+pm_status pm_draw_order(const pm_graph *g, int32_t centered, uint64_t seed, uint64_t first_id, uint64_t k,
+                        uint32_t *ids_out, void *stream);
 
 /* How pm_count and pm_sample_async run the adjacency tests of Algorithms 2
  * and 4 ("determine the subgraph induced by" the sampled path) in this

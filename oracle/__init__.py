@@ -82,6 +82,7 @@ def _load():
         "or_philox4x32_10": (None, [P, P, P]),
         "or_lemire": (i32, [u64, u64, ctypes.c_int, ctypes.POINTER(u64)]),
         "or_draw": (u64, [u64, u32, u64, u64]),
+        "or_draws": (None, [u64, u32, u64, u64, u64, P]),
         "or_decode_path": (None, [gp, u64, P]),
         "or_decode_centered": (None, [gp, u64, P]),
         "or_classify_path": (ctypes.c_int, [gp, P]),
@@ -253,6 +254,13 @@ def lemire(x: int, R: int, bits: int):
 
 def draw(seed: int, tag: int, sample_id: int, R: int) -> int:
     return int(_load().or_draw(seed, tag, sample_id, R))
+
+
+def draws(seed: int, tag: int, first: int, k: int, R: int) -> np.ndarray:
+    """uint64[k]: draw(seed, tag, first + i, R) for i < k."""
+    out = np.zeros(k, np.uint64)
+    _load().or_draws(seed, tag, first, k, R, _ptr(out))
+    return out
 
 
 def alias_build(w):

@@ -361,6 +361,13 @@ uint64_t or_draw(uint64_t seed, uint32_t tag, uint64_t id, uint64_t R)
     }
 }
 
+/* r of samples first .. first + k - 1 of one sampler, each as or_draw */
+void or_draws(uint64_t seed, uint32_t tag, uint64_t first, uint64_t k, uint64_t R, uint64_t *out)
+{
+    for (uint64_t i = 0; i < k; i++)
+        out[i] = or_draw(seed, tag, first + i, R);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Algorithm 1 (sample) and Algorithm 2's classification                    */
 /* ------------------------------------------------------------------------ */

@@ -68,6 +68,9 @@ int or_lemire(uint64_t x, uint64_t R, int bits, uint64_t *r);
 /* Exact uniform integer in [0,R) for sample `id` of sampler `tag`. */
 uint64_t or_draw(uint64_t seed, uint32_t tag, uint64_t id, uint64_t R);
 
+/* out[i] = or_draw(seed, tag, first + i, R) for i < k. */
+void or_draws(uint64_t seed, uint32_t tag, uint64_t first, uint64_t k, uint64_t R, uint64_t *out);
+
 /* Map r in [0,R_tau) to the 3-path (u', u, v, v') of Algorithm 1;
  * q[0]=u', q[1]=u, q[2]=v, q[3]=v'. */
 void or_decode_path(const or_graph *g, uint64_t r, int32_t q[4]);

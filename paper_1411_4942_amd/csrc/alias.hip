@@ -27,6 +27,7 @@
 // sample is then decoded from (s, o) exactly as the main samplers decode it.
 #include "graph.hpp"
 #include "profile.hpp"
+#include "drawsort.hpp"
 #include "radix.hpp"
 #include "sampler.hpp"
 #include "scan.hpp"
@@ -343,15 +344,16 @@ __global__ __launch_bounds__(kBlock) void k_sample_alias(SamplerView g, const Al
 
 // Draw order for the alias draw: the key is the top bits of the bucket b (the
 // stream's first draw), so neighbouring lanes read neighbouring table lines.
-template <bool CENTERED>
-__global__ __launch_bounds__(kBlock) void k_alias_keys(uint64_t N, uint64_t seed, uint64_t first, uint64_t k,
-                                                       int kshift, uint32_t *__restrict__ keys)
-{
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += (uint64_t)gridDim.x * blockDim.x) {
-        DrawStream st(seed, CENTERED ? 3u : 2u, first + i);
-        keys[i] = (uint32_t)(st.bounded(N) >> kshift);
+struct AliasKey {
+    uint64_t N, seed, first;
+    uint32_t tag;
+    int kshift;
+    __device__ uint32_t operator()(int64_t i) const
+    {
+        DrawStream st(seed, tag, first + (uint64_t)i);
+        return (uint32_t)(st.bounded(N) >> kshift);
     }
-}
+};
 
 template <bool CENTERED>
 __global__ __launch_bounds__(kBlock) void k_sample_alias_sorted(SamplerView g, const AliasEntry *__restrict__ T,
@@ -367,41 +369,25 @@ __global__ __launch_bounds__(kBlock) void k_sample_alias_sorted(SamplerView g, c
     tally_flush(cnt, tally);
 }
 
-// Buffers of one alias draw-order sort chunk of `chunk` ids.
-struct AliasSortBufs {
-    uint32_t *kin, *k0, *v0, *k1, *v1;
-    char *scr;
-    uint64_t chunk;
-};
-
-pm_status alias_sort_bufs(Temps &tmp, uint64_t k, AliasSortBufs *b)
+// Buffers of one alias draw-order sort chunk of min(k, kSortedChunk) ids.
+pm_status alias_sort_bufs(Temps &tmp, uint64_t k, DrawSortBufs *b)
 {
-    b->chunk = std::min<uint64_t>(k, kSortedChunk);
-    PM_TRY(tmp.get(&b->kin, (size_t)b->chunk));
-    PM_TRY(tmp.get(&b->k0, (size_t)b->chunk));
-    PM_TRY(tmp.get(&b->v0, (size_t)b->chunk));
-    PM_TRY(tmp.get(&b->k1, (size_t)b->chunk));
-    PM_TRY(tmp.get(&b->v1, (size_t)b->chunk));
-    return tmp.get(&b->scr, radix_scratch_bytes((int64_t)b->chunk));
+    const uint64_t chunk = std::min<uint64_t>(k, kSortedChunk);
+    char *base = nullptr;
+    PM_TRY(tmp.get(&base, draw_sort_bytes(chunk)));
+    draw_sort_carve(base, chunk, b);
+    return PM_OK;
 }
 
-// the bucket keys of ids [first, first + kc) and those ids sorted by them
-// (kc <= b.chunk); *ids receives the sorted ids (minus first)
-pm_status alias_sort_chunk(uint64_t N, bool centered, uint64_t seed, uint64_t first, uint64_t kc, unsigned blocks,
-                           hipStream_t s, const AliasSortBufs &b, uint32_t **ids)
+// the ids [first, first + kc) sorted by their bucket keys (kc <= b.chunk);
+// *ids receives the sorted ids (minus first)
+pm_status alias_sort_chunk(uint64_t N, bool centered, uint64_t seed, uint64_t first, uint64_t kc, hipStream_t s,
+                           const DrawSortBufs &b, uint32_t **ids)
 {
     const int nbits = bits_for(N - 1);  // b < N
     const int kshift = nbits > kDrawKeyBits ? nbits - kDrawKeyBits : 0;
     const int kbits = nbits - kshift;
-    const unsigned kb = (unsigned)std::min<uint64_t>((kc + kBlock - 1) / kBlock, blocks);
-    if (centered)
-        hipLaunchKernelGGL((k_alias_keys<true>), dim3(kb), dim3(kBlock), 0, s, N, seed, first, kc, kshift, b.kin);
-    else
-        hipLaunchKernelGGL((k_alias_keys<false>), dim3(kb), dim3(kBlock), 0, s, N, seed, first, kc, kshift, b.kin);
-    PM_HIP(hipGetLastError());
-    uint32_t *ks = nullptr;
-    return radix_sort("alias_draw_sort", b.kin, nullptr, b.k0, b.v0, b.k1, b.v1, (int64_t)kc, kbits, b.scr, s, &ks,
-                      ids, nullptr, nullptr, false);  // only the ids are used
+    return draw_sort("alias_draw_sort", AliasKey{N, seed, first, centered ? 3u : 2u, kshift}, kc, kbits, s, b, ids);
 }
 
 // the samples first + ids[j] for j < kc, into tally
@@ -424,12 +410,12 @@ pm_status launch_alias_sorted(const SamplerView &v, const AliasEntry *T, uint64_
                               uint64_t first, uint64_t k, uint64_t *tally, unsigned blocks, hipStream_t s)
 {
     Temps tmp(s);
-    AliasSortBufs b{};
+    DrawSortBufs b{};
     PM_TRY(alias_sort_bufs(tmp, k, &b));
     for (uint64_t c0 = 0; c0 < k; c0 += b.chunk) {
         const uint64_t kc = std::min(b.chunk, k - c0);
         uint32_t *ids = nullptr;
-        PM_TRY(alias_sort_chunk(N, centered, seed, first + c0, kc, blocks, s, b, &ids));
+        PM_TRY(alias_sort_chunk(N, centered, seed, first + c0, kc, s, b, &ids));
         PM_TRY(alias_sample_chunk(v, T, N, centered, seed, first + c0, kc, ids, tally, blocks, s));
     }
     return PM_OK;
@@ -476,7 +462,7 @@ pm_status sample_alias_async(const pm_graph *g, const pm_params *p, uint64_t *ta
         const AliasEntry *Tp = (const AliasEntry *)g->alias_tau, *Tc = (const AliasEntry *)g->alias_lam;
         const unsigned cap = (unsigned)((uint64_t)sampler_cu_count(g->device) * 4u);
         Temps tmp(s);
-        AliasSortBufs bp{}, bc{};
+        DrawSortBufs bp{}, bc{};
         PM_TRY(alias_sort_bufs(tmp, p->k_path, &bp));
         PM_TRY(alias_sort_bufs(tmp, p->k_cent, &bc));
         hipStream_t side[2];
@@ -485,8 +471,8 @@ pm_status sample_alias_async(const pm_graph *g, const pm_params *p, uint64_t *ta
         {
             Fork fork(s, side, 1);  // joined before the temporaries are released on s
             PM_HIP(fork.status);
-            PM_TRY(alias_sort_chunk(N, true, p->seed, p->first_id_cent, p->k_cent, cap, side[0], bc, &ids_c));
-            PM_TRY(alias_sort_chunk(N, false, p->seed, p->first_id_path, p->k_path, cap, s, bp, &ids_p));
+            PM_TRY(alias_sort_chunk(N, true, p->seed, p->first_id_cent, p->k_cent, side[0], bc, &ids_c));
+            PM_TRY(alias_sort_chunk(N, false, p->seed, p->first_id_path, p->k_path, s, bp, &ids_p));
             PM_HIP(fork.join());  // before the 3-path kernel, as the main draw does
         }
         {

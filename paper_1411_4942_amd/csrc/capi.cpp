@@ -43,6 +43,8 @@ pm_status count_noalloc(const pm_graph *g, const pm_params *p, pm_result *out, h
 size_t static_scratch_bytes();
 pm_status adjacent(const pm_graph *g, const int32_t *a, const int32_t *b, int64_t count, uint8_t *out, int32_t mode,
                    hipStream_t s);
+pm_status draw_order(const pm_graph *g, int32_t centered, uint64_t seed, uint64_t first, uint64_t k, uint32_t *out,
+                     hipStream_t s);
 pm_status batch_create(const pm_graph *const *graphs, const pm_params *params, int32_t count, const pm_tune *tune,
                        hipStream_t user_stream, pm_batch **out);
 pm_status batch_set_params(pm_batch *b, const pm_params *params);
@@ -353,6 +355,12 @@ pm_status pm_adjacent(const pm_graph *g, const int32_t *a, const int32_t *b, int
                       int32_t mode, void *stream)
 {
     PM_GUARD(return pm::adjacent(g, a, b, count, out, mode, (hipStream_t)stream);)
+}
+
+pm_status pm_draw_order(const pm_graph *g, int32_t centered, uint64_t seed, uint64_t first_id, uint64_t k,
+                        uint32_t *ids_out, void *stream)
+{
+    PM_GUARD(return pm::draw_order(g, centered, seed, first_id, k, ids_out, (hipStream_t)stream);)
 }
 
 pm_status pm_philox_device(const uint32_t *in, uint32_t *out, int64_t count)

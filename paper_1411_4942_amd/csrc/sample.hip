@@ -2,6 +2,7 @@
 // Algorithm 2, and Algorithm 3 (sample-centered) classified as in Algorithm 4
 // (the per-sample body is in sampler.hpp).  One lane per sample, grid-stride
 // over sample ids; per-lane counters, one wave reduction and atomic per class.
+#include "drawsort.hpp"
 #include "graph.hpp"
 #include "profile.hpp"
 #include "radix.hpp"
@@ -13,6 +14,8 @@
 #include <mutex>
 
 namespace pm {
+
+static_assert(draw_sort_tiles(kSortedChunk) <= kDsMaxTiles, "a sort chunk fits the draw sort's column scan");
 
 // U samples per lane per round of the grid-stride loop (U > 1 only
 // unrolls the loop; each sample is independent).
@@ -132,13 +135,17 @@ int sampler_cu_count(int dev)
 // slot), so a sample touches fewer distinct random lines.  Each sample then
 // redraws its r from its id; tallies equal the unsorted kernel's exactly.
 
-template <bool CENTERED>
-__global__ __launch_bounds__(kBlock) void k_draw_keys(SamplerView g, uint64_t seed, uint64_t first, uint64_t k,
-                                                      int kshift, uint32_t *__restrict__ keys)
-{
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += (uint64_t)gridDim.x * blockDim.x)
-        keys[i] = (uint32_t)(draw_bounded(seed, CENTERED ? 1u : 0u, first + i, g.R) >> kshift);
-}
+// the draw key of position i of a sort chunk: the top bits of the r of
+// sample first + i
+struct DrawKey {
+    uint64_t R, seed, first;
+    uint32_t tag;
+    int kshift;
+    __device__ uint32_t operator()(int64_t i) const
+    {
+        return (uint32_t)(draw_bounded(seed, tag, first + (uint64_t)i, R) >> kshift);
+    }
+};
 
 template <bool CENTERED, int SEARCH>
 __global__ __launch_bounds__(kBlock) void k_sample_sorted(SamplerView g, uint64_t seed, uint64_t first, uint64_t k,
@@ -153,34 +160,15 @@ __global__ __launch_bounds__(kBlock) void k_sample_sorted(SamplerView g, uint64_
     tally_flush(cnt, tally);
 }
 
-// Device buffers of the draw-ordered launch: draw keys, the radix sort's
-// key/id ping-pong arrays of `chunk` entries each, and its scratch.
-struct SortBufs {
-    uint32_t *kin, *k0, *v0, *k1, *v1;
-    void *scr;
-    uint64_t chunk;
-};
-
-// The draw keys of ids [first, first + kc) and those ids sorted by them, in
-// b's buffers (kc <= b.chunk); *ids receives the sorted ids (minus first).
+// The ids [first, first + kc) sorted by their draw keys in b's buffers
+// (kc <= b.chunk); *ids receives the sorted ids (minus first).
 static pm_status sort_chunk(const SamplerView &v, bool centered, uint64_t seed, uint64_t first, uint64_t kc,
-                            unsigned blocks, hipStream_t s, const SortBufs &b, uint32_t **ids)
+                            hipStream_t s, const DrawSortBufs &b, uint32_t **ids)
 {
     const int rbits = bits_for(v.R - 1);  // r < R
     const int kshift = rbits > kDrawKeyBits ? rbits - kDrawKeyBits : 0;
     const int kbits = rbits - kshift;
-    const unsigned kb = (unsigned)std::min<uint64_t>((kc + kBlock - 1) / kBlock, blocks);
-    {
-        ProfScope pd("draw_keys", s);
-        if (centered)
-            hipLaunchKernelGGL((k_draw_keys<true>), dim3(kb), dim3(kBlock), 0, s, v, seed, first, kc, kshift, b.kin);
-        else
-            hipLaunchKernelGGL((k_draw_keys<false>), dim3(kb), dim3(kBlock), 0, s, v, seed, first, kc, kshift, b.kin);
-        PM_HIP(hipGetLastError());
-    }
-    uint32_t *ks = nullptr;
-    return radix_sort("draw_sort", b.kin, nullptr, b.k0, b.v0, b.k1, b.v1, (int64_t)kc, kbits, b.scr, s, &ks, ids,
-                      nullptr, nullptr, false);  // only the ids are used
+    return draw_sort("draw_sort", DrawKey{v.R, seed, first, centered ? 1u : 0u, kshift}, kc, kbits, s, b, ids);
 }
 
 // The samples first + ids[j] for j < kc, into tally.
@@ -214,30 +202,24 @@ static pm_status sample_chunk(const SamplerView &v, bool centered, uint64_t seed
 }
 
 static pm_status launch_sorted_in(const SamplerView &v, bool centered, uint64_t seed, uint64_t first, uint64_t k,
-                                  uint64_t *tally, unsigned blocks, hipStream_t s, const SortBufs &b)
+                                  uint64_t *tally, unsigned blocks, hipStream_t s, const DrawSortBufs &b)
 {
     for (uint64_t c0 = 0; c0 < k; c0 += b.chunk) {
         const uint64_t kc = std::min(b.chunk, k - c0);
         uint32_t *ids = nullptr;
-        PM_TRY(sort_chunk(v, centered, seed, first + c0, kc, blocks, s, b, &ids));
+        PM_TRY(sort_chunk(v, centered, seed, first + c0, kc, s, b, &ids));
         PM_TRY(sample_chunk(v, centered, seed, first + c0, kc, ids, tally, blocks, s));
     }
     return PM_OK;
 }
 
 // buffers of one draw-order sort chunk of min(k, kSortedChunk) ids from tmp
-static pm_status sort_bufs(Temps &tmp, uint64_t k, SortBufs *b)
+static pm_status sort_bufs(Temps &tmp, uint64_t k, DrawSortBufs *b)
 {
     const uint64_t chunk = std::min<uint64_t>(k, kSortedChunk);
-    char *scr = nullptr;
-    PM_TRY(tmp.get(&b->kin, (size_t)chunk));
-    PM_TRY(tmp.get(&b->k0, (size_t)chunk));
-    PM_TRY(tmp.get(&b->v0, (size_t)chunk));
-    PM_TRY(tmp.get(&b->k1, (size_t)chunk));
-    PM_TRY(tmp.get(&b->v1, (size_t)chunk));
-    PM_TRY(tmp.get(&scr, radix_scratch_bytes((int64_t)chunk)));
-    b->scr = scr;
-    b->chunk = chunk;
+    char *base = nullptr;
+    PM_TRY(tmp.get(&base, draw_sort_bytes(chunk)));
+    draw_sort_carve(base, chunk, b);
     return PM_OK;
 }
 
@@ -246,7 +228,7 @@ static pm_status launch_sorted(const SamplerView &v, bool centered, uint64_t see
                                uint64_t *tally, unsigned blocks, hipStream_t s)
 {
     Temps tmp(s);
-    SortBufs b{};
+    DrawSortBufs b{};
     PM_TRY(sort_bufs(tmp, k, &b));
     return launch_sorted_in(v, centered, seed, first, k, tally, blocks, s, b);
 }
@@ -255,7 +237,7 @@ static pm_status launch_sorted(const SamplerView &v, bool centered, uint64_t see
 // Draw-ordered launches take their buffers from `fixed` when given, else
 // from the allocator.
 static pm_status launch_sampler(const pm_graph *g, bool centered, uint64_t seed, uint64_t first, uint64_t k,
-                                uint64_t *tally, hipStream_t s, const SortBufs *fixed = nullptr)
+                                uint64_t *tally, hipStream_t s, const DrawSortBufs *fixed = nullptr)
 {
     const SamplerView v = view_of(g, centered);
     if (v.R == 0 || k == 0) return PM_OK;
@@ -348,6 +330,29 @@ pm_status adjacent(const pm_graph *g, const int32_t *a, const int32_t *b, int64_
     return PM_OK;
 }
 
+// The sorted ids of one draw-order sort chunk, copied to out (device).
+pm_status draw_order(const pm_graph *g, int32_t centered, uint64_t seed, uint64_t first, uint64_t k, uint32_t *out,
+                     hipStream_t s)
+{
+    if (!g || !out || k == 0 || k > kSortedChunk) {
+        set_error("draw order: null argument, or k outside [1, 2^24]");
+        return PM_EINVAL;
+    }
+    PM_TRY(check_device(g));
+    const SamplerView v = view_of(g, centered != 0);
+    if (v.R < 2) {
+        set_error("draw order: the sampler's total weight is below 2");
+        return PM_EINVAL;
+    }
+    Temps tmp(s);
+    DrawSortBufs b{};
+    PM_TRY(sort_bufs(tmp, k, &b));
+    uint32_t *ids = nullptr;
+    PM_TRY(sort_chunk(v, centered != 0, seed, first, k, s, b, &ids));
+    PM_HIP(hipMemcpyAsync(out, ids, sizeof(uint32_t) * k, hipMemcpyDeviceToDevice, s));
+    return PM_OK;
+}
+
 // Is a sampler's launch draw-ordered in a single sort chunk?
 static bool one_sorted_chunk(const SamplerView &v, uint64_t k)
 {
@@ -367,7 +372,7 @@ static pm_status sample_pair_overlapped(const pm_graph *g, const pm_params *p, u
     const SamplerView vp = view_of(g, false), vc = view_of(g, true);
     const unsigned cap = (unsigned)((uint64_t)sampler_cu_count(g->device) * (uint64_t)g_blocks_per_cu.load());
     Temps tmp(s);
-    SortBufs bp{}, bc{};
+    DrawSortBufs bp{}, bc{};
     PM_TRY(sort_bufs(tmp, p->k_path, &bp));
     PM_TRY(sort_bufs(tmp, p->k_cent, &bc));
     hipStream_t side[2];
@@ -377,8 +382,8 @@ static pm_status sample_pair_overlapped(const pm_graph *g, const pm_params *p, u
         ProfScope prof("draw_sorts", s);
         Fork fork(s, side, 1);  // joined before the temporaries are released on s
         PM_HIP(fork.status);
-        PM_TRY(sort_chunk(vc, true, p->seed, p->first_id_cent, p->k_cent, cap, side[0], bc, &ids_c));
-        PM_TRY(sort_chunk(vp, false, p->seed, p->first_id_path, p->k_path, cap, s, bp, &ids_p));
+        PM_TRY(sort_chunk(vc, true, p->seed, p->first_id_cent, p->k_cent, side[0], bc, &ids_c));
+        PM_TRY(sort_chunk(vp, false, p->seed, p->first_id_path, p->k_path, s, bp, &ids_p));
         // joined before the 3-path kernel: a sort still running beside it
         // slows it by more than the join costs
         PM_HIP(fork.join());
@@ -587,8 +592,7 @@ pm_status count_on_graph(const pm_graph *g, const pm_params *p, pm_result *out, 
 
 constexpr uint64_t kStaticChunk = 1ull << 22;
 constexpr size_t kStaticTallyBytes = 256;  // 2 x PM_NUM_TALLIES u64, padded to 256
-constexpr size_t kStaticRadixBytes = 2u << 20;
-constexpr size_t kStaticScratchBytes = kStaticTallyBytes + 5 * sizeof(uint32_t) * kStaticChunk + kStaticRadixBytes;
+constexpr size_t kStaticScratchBytes = kStaticTallyBytes + draw_sort_bytes(kStaticChunk);
 static_assert(2 * PM_NUM_TALLIES * sizeof(uint64_t) <= kStaticTallyBytes, "tallies fit their slice");
 
 static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
@@ -635,22 +639,11 @@ pm_status count_noalloc(const pm_graph *g, const pm_params *p, pm_result *out, h
         return PM_EINVAL;
     }
     PM_TRY(check_device(g));
-    if (radix_scratch_bytes((int64_t)kStaticChunk) > kStaticRadixBytes) {
-        set_error("pm_count_noalloc: the sort chunk's radix scratch exceeds its fixed slice");
-        return PM_EDEVICE;
-    }
     unsigned char *base = nullptr;
     PM_TRY(scratch_on_device(g->device, &base));
     uint64_t *tally = reinterpret_cast<uint64_t *>(base);
-    uint32_t *ids = reinterpret_cast<uint32_t *>(base + kStaticTallyBytes);
-    SortBufs b{};
-    b.kin = ids;
-    b.k0 = ids + kStaticChunk;
-    b.v0 = ids + 2 * kStaticChunk;
-    b.k1 = ids + 3 * kStaticChunk;
-    b.v1 = ids + 4 * kStaticChunk;
-    b.scr = ids + 5 * kStaticChunk;
-    b.chunk = kStaticChunk;
+    DrawSortBufs b{};
+    draw_sort_carve(base + kStaticTallyBytes, kStaticChunk, &b);
     // the tallies keep the last call's contents: clear them (a fill kernel)
     PM_TRY(fill_async<uint64_t>(tally, 0ull, 2 * PM_NUM_TALLIES, s));
     PM_TRY(launch_sampler(g, false, p->seed, p->first_id_path, p->k_path, tally, s, &b));

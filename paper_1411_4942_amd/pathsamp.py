@@ -137,6 +137,8 @@ _SIGNATURES = {
     "pm_count_noalloc": (ctypes.c_int32, [_P, ctypes.POINTER(Params), ctypes.POINTER(Result), _P]),
     "pm_static_scratch_bytes": (ctypes.c_uint64, []),
     "pm_adjacent": (ctypes.c_int32, [_P, _P, _P, ctypes.c_int64, _P, ctypes.c_int32, _P]),
+    "pm_draw_order": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, _P,
+                                       _P]),
     "pm_release_cached_memory": (ctypes.c_int32, []),
     "pm_profile_enable": (ctypes.c_int32, [ctypes.c_int32]),
     "pm_profile_read": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
@@ -376,6 +378,16 @@ class Graph:
         out = torch.empty(a.numel(), dtype=torch.uint8, device=a.device)
         _check(lib().pm_adjacent(self._h, a.data_ptr(), b.data_ptr(), a.numel(), out.data_ptr(), mode,
                                  _stream_ptr(stream)), "pm_adjacent")
+        return out
+
+    def draw_order(self, centered: bool, seed: int, k: int, first: int = 0, stream=None):
+        """pm_draw_order: int32 CUDA tensor of the k sample offsets (id - first)
+        of one sort chunk in the order a draw-ordered launch runs them."""
+        import torch
+
+        out = torch.empty(k, dtype=torch.int32, device="cuda")
+        _check(lib().pm_draw_order(self._h, 1 if centered else 0, seed, first, k, out.data_ptr(),
+                                   _stream_ptr(stream)), "pm_draw_order")
         return out
 
     def destroy(self):

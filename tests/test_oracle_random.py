@@ -125,3 +125,11 @@ def test_tags_and_seeds_give_distinct_streams():
     c = [oracle.draw(2, 0, i, 2 ** 40) for i in range(64)]
     assert a != b and a != c
     assert len(set(a)) == 64
+
+
+def test_batch_draws_equal_single_draws():
+    """oracle.draws (one C loop) is draw() id by id, from any first id."""
+    for first, R in ((0, 1000), (2 ** 33 - 5, 2 ** 63 + 12345), (77, 4098)):
+        got = oracle.draws(3, 1, first, 300, R)
+        assert got.dtype == np.uint64
+        assert got.tolist() == [oracle.draw(3, 1, first + i, R) for i in range(300)]

@@ -32,7 +32,12 @@ def _graph(off, col):
 
 
 def test_noalloc_equals_count_on_two_calls_the_second_smaller():
-    assert ps.static_scratch_bytes() == 256 + 5 * 4 * (1 << 22) + (2 << 20)
+    # tallies (256 B), then one sort chunk of 2^22 ids: keys (4 B each),
+    # bucketed pairs (8 B), sorted ids (4 B), two count tables of 256 tiles
+    # x 2048 buckets (4 B), the bucket totals and starts (2048 and 2049
+    # words, each slice rounded up to 256 B)
+    c = 1 << 22
+    assert ps.static_scratch_bytes() == 256 + (4 + 8 + 4) * c + 2 * 4 * 256 * 2048 + 4 * 2048 + 8448
     _say("noalloc: call 1, R-MAT scale 16, k = 2^23 + 777 per sampler (draw order, three sort chunks)")
     g1 = _graph(*synth.rmat(16, 16, seed=4))
     k1 = (1 << 23) + 777
