@@ -28,7 +28,6 @@
 #include "graph.hpp"
 #include "profile.hpp"
 #include "drawsort.hpp"
-#include "radix.hpp"
 #include "sampler.hpp"
 #include "scan.hpp"
 #include "streams.hpp"

@@ -144,6 +144,14 @@ inline int grid_for(int64_t n, int threads, int max_blocks = 65536)
     return (int)b;
 }
 
+// bits needed for the values 0 .. max_key
+inline int bits_for(uint64_t max_key)
+{
+    int b = 0;
+    while (b < 64 && (max_key >> b) != 0) ++b;
+    return b;
+}
+
 template <typename T>
 inline pm_status fill_async(T *p, T value, int64_t n, hipStream_t s)
 {

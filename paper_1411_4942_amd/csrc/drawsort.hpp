@@ -34,9 +34,9 @@ constexpr int kDsLowBits = 13;                  // the widest low digit (24-bit 
 constexpr int kDsThreads = 1024;                // keys and scatter blocks
 constexpr int kDsItems = 16;                    // positions per thread there
 constexpr int64_t kDsTile = (int64_t)kDsThreads * kDsItems;
-constexpr int kDsScanBuckets = kWave;  // buckets per column-scan block (one per lane)
-constexpr int kDsScanParts = 16;       // tile ranges per bucket there (one per wave)
-constexpr int kDsScanRows = 64;        // tiles per range, at most
+constexpr int kDsScanBuckets = 16;    // buckets per column-scan block
+constexpr int kDsScanParts = kWave;   // tile ranges per bucket there
+constexpr int kDsScanRows = 16;       // tiles per range, at most
 constexpr int64_t kDsMaxTiles = (int64_t)kDsScanParts * kDsScanRows;
 #ifndef PM_DS_SORT_THREADS
 #define PM_DS_SORT_THREADS 1024
@@ -154,18 +154,22 @@ static __global__ __launch_bounds__(kDsThreads) void ds_keys(KeyFn kf, int64_t k
     for (int b = t; b < kDsBuckets; b += kDsThreads) counts[(int64_t)blockIdx.x * kDsBuckets + b] = hist[b];
 }
 
-// Block b covers buckets [64 b, 64 b + 64); wave p of it the tiles
-// [p per, (p + 1) per) of each (per <= kDsScanRows), lane j bucket 64 b + j
-// (each row read is 256 contiguous bytes).  A thread's counts are all loaded
-// at once and kept for the rewrite.
+// Block b covers buckets [16 b, 16 b + 16): thread (p, j) sums bucket
+// 16 b + j over the tiles [p per, (p + 1) per) (per <= kDsScanRows; a row
+// read is 64 contiguous bytes), keeping its counts in registers; wave j then
+// scans bucket 16 b + j's 64 part sums across its lanes, and each thread
+// rewrites its tiles' counts as starts.
 static __global__ __launch_bounds__(kDsScanBuckets *kDsScanParts) void ds_colscan(
     const uint32_t *__restrict__ counts, int64_t tiles, uint32_t *__restrict__ colpre, uint32_t *__restrict__ totals)
 {
-    __shared__ uint32_t s_part[kDsScanParts][kDsScanBuckets];
+    static_assert(kDsScanParts == kWave && kDsScanBuckets * kDsScanParts / kWave == kDsScanBuckets,
+                  "one wave per bucket scans its parts");
+    __shared__ uint32_t s_part[kDsScanParts][kDsScanBuckets + 1];
     const int j = threadIdx.x % kDsScanBuckets, p = threadIdx.x / kDsScanBuckets;
-    const int64_t b = (int64_t)blockIdx.x * kDsScanBuckets + j;
-    const int64_t per = (tiles + kDsScanParts - 1) / kDsScanParts;  // <= kDsScanRows (checked by the host)
-    const int64_t t0 = std::min<int64_t>((int64_t)p * per, tiles), t1 = std::min<int64_t>(t0 + per, tiles);
+    const uint32_t b = blockIdx.x * kDsScanBuckets + j;
+    const uint32_t nt = (uint32_t)tiles;
+    const uint32_t per = (nt + kDsScanParts - 1) / kDsScanParts;  // <= kDsScanRows (checked by the host)
+    const uint32_t t0 = std::min<uint32_t>(p * per, nt), t1 = std::min<uint32_t>(t0 + per, nt);
     uint32_t v[kDsScanRows];
     uint32_t acc = 0;
 #pragma unroll
@@ -175,15 +179,18 @@ static __global__ __launch_bounds__(kDsScanBuckets *kDsScanParts) void ds_colsca
     }
     s_part[p][j] = acc;
     __syncthreads();
-    if (p == 0) {
-        uint32_t run = 0;
+    {
+        // wave w: bucket 16 b + w, lane q: part q
+        const int w = threadIdx.x / kWave, q = lane_id();
+        const uint32_t x = s_part[q][w];
+        uint32_t incl = x;
 #pragma unroll
-        for (int q = 0; q < kDsScanParts; ++q) {
-            const uint32_t x = s_part[q][j];
-            s_part[q][j] = run;
-            run += x;
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t o = __shfl_up(incl, d, kWave);
+            if (q >= d) incl += o;
         }
-        totals[b] = run;
+        s_part[q][w] = incl - x;
+        if (q == kWave - 1) totals[blockIdx.x * kDsScanBuckets + w] = incl;
     }
     __syncthreads();
     uint32_t run = s_part[p][j];
@@ -286,10 +293,12 @@ static __global__ __launch_bounds__(kDsSortThreads) void ds_bucket_sort(const ui
                                                                       const uint32_t *__restrict__ bstart,
                                                                       int lobits, uint32_t *__restrict__ ids)
 {
+    // 80 KiB in all, so that two blocks share a CU's 160 KiB: the block-scan
+    // words live in the staging space, which holds nothing during the scan
     __shared__ uint32_t cnt[1 << (kDsLowBits - 1)];
     __shared__ uint32_t s_ids[kDsSub];  // the staging space (32-bit counters of a large bucket)
-    __shared__ uint32_t s_w[kDsSortThreads / kWave];
-    static_assert(kDsSub >= (1u << kDsLowBits), "a large bucket's counters fit the staging space");
+    static_assert(kDsSub >= (1u << kDsLowBits) + kDsSortThreads / kWave,
+                  "a large bucket's counters and the scan words fit the staging space");
     const int t = threadIdx.x;
     const uint32_t lo = bstart[blockIdx.x], hi = bstart[blockIdx.x + 1];
     if (hi <= lo + 1) {  // the block's bounds are uniform: nothing to order
@@ -325,7 +334,7 @@ static __global__ __launch_bounds__(kDsSortThreads) void ds_bucket_sort(const ui
             const uint32_t x = cnt[w];
             sum += (x & 0xFFFFu) + (x >> 16);
         }
-        uint32_t run = ds_block_excl<kDsSortThreads>(sum, s_w);
+        uint32_t run = ds_block_excl<kDsSortThreads>(sum, s_ids);  // staging still empty
         for (int w = w0; w < w1; ++w) {
             const uint32_t x = cnt[w];
             const uint32_t a = run, b = run + (x & 0xFFFFu);
@@ -363,7 +372,7 @@ static __global__ __launch_bounds__(kDsSortThreads) void ds_bucket_sort(const ui
     const int d0 = std::min(t * per, nlo), d1 = std::min(d0 + per, nlo);
     uint32_t sum = 0;
     for (int d = d0; d < d1; ++d) sum += c32[d];
-    uint32_t run = ds_block_excl<kDsSortThreads>(sum, s_w);
+    uint32_t run = ds_block_excl<kDsSortThreads>(sum, s_ids + (1 << kDsLowBits));  // past the counters
     for (int d = d0; d < d1; ++d) {
         const uint32_t x = c32[d];
         c32[d] = run;

@@ -327,13 +327,6 @@ static __global__ __launch_bounds__(kBlock) void radix_chunk_apply(const uint32_
     }
 }
 
-inline int bits_for(uint64_t max_key)
-{
-    int b = 0;
-    while (b < 64 && (max_key >> b) != 0) ++b;
-    return b;
-}
-
 // Device scratch needed by radix_sort for N elements.
 inline size_t radix_scratch_bytes(int64_t N)
 {

@@ -5,7 +5,6 @@
 #include "drawsort.hpp"
 #include "graph.hpp"
 #include "profile.hpp"
-#include "radix.hpp"
 #include "sampler.hpp"
 #include "streams.hpp"
 
