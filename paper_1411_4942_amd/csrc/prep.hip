@@ -120,8 +120,13 @@ struct OffOut {
 //   16 < degree <= 64     one wave per row, a sorting network across lanes
 //   64 < degree <= 256    one wave per row, a sorting network on 2 (up to
 //                         128) or 4 keys per lane
-//   256 < degree <= 16384 one block per row sized to the class (64, 256,
-//                         512 or 1024 threads), stable LSD radix sort in LDS
+//   256 < degree <= 8192  one block per row sized to the class (64, 256 or
+//                         512 threads), stable LSD radix sort with the keys
+//                         in registers and one LDS exchange buffer (a third
+//                         of the LDS of a two-buffer sort, so more blocks
+//                         share a CU)
+//   8192 < degree <= 16384  one block of 1024 per row, stable LSD radix sort
+//                         between two LDS buffers
 //   16384 < degree <= 32768  one block of 1024 per row, keys in registers
 //                         and one LDS exchange buffer (128 KB)
 //   degree > 32768        (the few hub rows, all at the end of the order)
@@ -1354,17 +1359,17 @@ pm_status graph_create(const pm_csr_view *csr, uint32_t flags, hipStream_t s, pm
         }
         if (cls[5] > cls[4]) {
             ProfScope pc("build_rows.b1024", s);
-            hipLaunchKernelGGL((k_rows_block<64, 16>), dim3((unsigned)(cls[5] - cls[4])), dim3(64), 0, s, off_in,
+            hipLaunchKernelGGL((k_rows_block_reg<64, 16>), dim3((unsigned)(cls[5] - cls[4])), dim3(64), 0, s, off_in,
                                col_in, order, g->rank, g->off, n, cls[4], vbits, g->col, edge, ladder1, st);
         }
         if (cls[6] > cls[5]) {
             ProfScope pc("build_rows.b4096", s);
-            hipLaunchKernelGGL((k_rows_block<256, 16>), dim3((unsigned)(cls[6] - cls[5])), dim3(256), 0, s, off_in,
+            hipLaunchKernelGGL((k_rows_block_reg<256, 16>), dim3((unsigned)(cls[6] - cls[5])), dim3(256), 0, s, off_in,
                                col_in, order, g->rank, g->off, n, cls[5], vbits, g->col, edge, ladder1, st);
         }
         if (cls[7] > cls[6]) {
             ProfScope pc("build_rows.b8192", s);
-            hipLaunchKernelGGL((k_rows_block<512, 16>), dim3((unsigned)(cls[7] - cls[6])), dim3(512), 0, s, off_in,
+            hipLaunchKernelGGL((k_rows_block_reg<512, 16>), dim3((unsigned)(cls[7] - cls[6])), dim3(512), 0, s, off_in,
                                col_in, order, g->rank, g->off, n, cls[6], vbits, g->col, edge, ladder1, st);
         }
         const hipError_t launched = hipGetLastError();

@@ -10,9 +10,13 @@
 
 namespace pm {
 
-constexpr int kHashChunk = 2048;             // slots per block of the small-row kernel
+constexpr int kHashChunk = 2047;             // slots per block of the small-row kernel
 constexpr int kHashSmall = kHashSmallBound;  // degree bound of the small-row kernel
-constexpr int kHashSpan = 2 * (kHashChunk + kHashSmall);  // entries a small-row block can own
+// entries a small-row block can own: its rows start at most kHashChunk - 1
+// slots into its chunk and end at most kHashSmall slots later (this bound and
+// the chunk of 2047 slots keep the block's LDS within 32 KiB, so that five
+// blocks share a CU)
+constexpr int kHashSpan = 2 * (kHashChunk - 1 + kHashSmall);
 // slots per thread of a small-row block: its rows start in one chunk, so they
 // span fewer than kHashChunk + kHashSmall slots
 constexpr int kHashRun = (kHashChunk + kHashSmall + kBlock - 1) / kBlock;
@@ -54,12 +58,11 @@ __global__ __launch_bounds__(kBlock) void k_rowhash_small(const uint32_t *__rest
                                                           const uint32_t *__restrict__ col, int64_t r_begin,
                                                           int64_t r_end, int64_t s_end, uint32_t *__restrict__ H)
 {
-    __shared__ uint32_t t[kHashSpan];
+    __shared__ uint32_t t[kHashSpan];  // its first two words carry the block's row range first
     __shared__ uint32_t roff[kHashChunk + 1];
-    __shared__ int64_t s_rows[2];
     const int64_t s0 = (int64_t)blockIdx.x * kHashChunk;
     const int64_t s1 = s0 + kHashChunk < s_end ? s0 + kHashChunk : s_end;
-    if (threadIdx.x < 2) {  // first row starting at or after s0 (resp. s1)
+    if (threadIdx.x < 2) {  // first row starting at or after s0 (resp. s1); rows < 2^31
         const int64_t target = threadIdx.x == 0 ? s0 : s1;
         int64_t lo = r_begin, hi = r_end;
         while (lo < hi) {
@@ -69,10 +72,11 @@ __global__ __launch_bounds__(kBlock) void k_rowhash_small(const uint32_t *__rest
             else
                 lo = mid + 1;
         }
-        s_rows[threadIdx.x] = lo;
+        t[threadIdx.x] = (uint32_t)lo;
     }
     __syncthreads();
-    const int64_t a0 = s_rows[0], a1 = s_rows[1];
+    // read before the barrier that precedes the table's first write
+    const int64_t a0 = t[0], a1 = t[1];
     if (a0 >= a1) return;  // no row starts here (block-uniform)
     const int64_t nrows = a1 - a0;
     for (int64_t i = threadIdx.x; i <= nrows; i += blockDim.x) roff[i] = off[a0 + i];
@@ -207,10 +211,11 @@ __global__ __launch_bounds__(kBlock) void k_rowhash_window(const uint32_t *__res
                                                            const uint32_t *__restrict__ wstart, SpillList *spill,
                                                            uint32_t *__restrict__ H)
 {
+    // 32 KiB in all, so that five blocks share a CU: the table's first word
+    // carries the block's row first
     __shared__ uint32_t t[kHashWin];
-    __shared__ int64_t s_row;
     const uint64_t b = blockIdx.x;
-    if (threadIdx.x == 0) {  // last row whose window base is <= b
+    if (threadIdx.x == 0) {  // last row whose window base is <= b (rows < 2^31)
         int64_t lo = r_begin, hi = r_end;
         while (hi - lo > 1) {
             const int64_t mid = (lo + hi) >> 1;
@@ -219,10 +224,11 @@ __global__ __launch_bounds__(kBlock) void k_rowhash_window(const uint32_t *__res
             else
                 hi = mid;
         }
-        s_row = lo;
+        t[0] = (uint32_t)lo;
     }
     __syncthreads();
-    const int64_t a = s_row;
+    const int64_t a = t[0];
+    __syncthreads();  // every thread holds a before the table is cleared
     const uint32_t rb = off[a], d = off[a + 1] - rb, size = 2u * d, nwin = window_count(d);
     const uint64_t wb = window_base(off, r_begin, a);
     const uint32_t wi = (uint32_t)(b - wb);
