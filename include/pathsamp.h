@@ -450,7 +450,7 @@ pm_status pm_set_sampler_shape(int32_t samples_per_lane, int32_t blocks_per_cu);
 
 /* Draw-ordered sampling in pm_count, pm_sample_async and pm_count_alias
  * (this process; on by default).  When a sampler draws at least min_samples
- * samples (0: the default 6 * 2^20, about where the sort starts to pay on
+ * samples (0: the default 2^21, about where the sort starts to pay on
  * MI355X), their ids are first sorted, in chunks of 2^24, by the top 24 bits
  * of each sample's first draw (r of Algorithm 1 step 2 / Algorithm 3 step 2,
  * or the alias bucket), so that neighbouring lanes read neighbouring parts of

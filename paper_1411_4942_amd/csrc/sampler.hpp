@@ -213,10 +213,10 @@ __device__ __forceinline__ uint32_t sample_class_wave(const SamplerView &g, uint
 // Draw-ordered sampling (pm_count, pm_sample_async, pm_count_alias): for at
 // least draw_order_min() samples of one sampler, ids are sorted in chunks of
 // kSortedChunk by the top kDrawKeyBits bits of their first draw before they
-// run.  Measured on MI355X the sort pays from about 4M samples, for graphs
-// from 1e6 to 2.4e8 slots alike (its fixed cost dominates below).
+// run.  Measured on MI355X the sort pays from about 2M samples, for graphs
+// from 7e6 to 2.4e8 slots alike (its fixed cost dominates below).
 constexpr int kDrawKeyBits = 24;
-constexpr uint64_t kSortedMinDefault = 6ull << 20;
+constexpr uint64_t kSortedMinDefault = 1ull << 21;
 constexpr uint64_t kSortedChunk = 1ull << 24;  // samples per sort (bounds the temporaries)
 
 bool draw_order_enabled();
