@@ -69,6 +69,18 @@ def test_rmat_full_keys_ragged_tiles(centered):
     g.destroy()
 
 
+@pytest.mark.parametrize("k", [1, 2, 3, 16384, 16385])
+def test_tiny_and_tile_edge_chunks(k):
+    # one sample, two, three; exactly one tile, one tile and one sample
+    off, col = synth.rmat(10, 8, seed=5)
+    og = oracle.Graph(off, col)
+    g = _graph(off, col)
+    _say("draw order: R-MAT 10, k", k)
+    _check_order(g, og, False, 2, k, 40)
+    _check_order(g, og, True, 2, k, 40)
+    g.destroy()
+
+
 @pytest.mark.parametrize("n,k", [(500, 100_000), (1500, 200_003)])
 def test_small_weight_keys_are_all_of_r(n, k):
     # a cycle: every slot has weight 1, R = 2n; keys of 10 bits take the
