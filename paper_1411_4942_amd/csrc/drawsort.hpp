@@ -38,14 +38,10 @@ constexpr int kDsScanBuckets = 16;    // buckets per column-scan block
 constexpr int kDsScanParts = kWave;   // tile ranges per bucket there
 constexpr int kDsScanRows = 16;       // tiles per range, at most
 constexpr int64_t kDsMaxTiles = (int64_t)kDsScanParts * kDsScanRows;
-#ifndef PM_DS_SORT_THREADS
-#define PM_DS_SORT_THREADS 1024
-#endif
-#ifndef PM_DS_SORT_ITEMS
-#define PM_DS_SORT_ITEMS 16
-#endif
-constexpr int kDsSortThreads = PM_DS_SORT_THREADS;                     // bucket-sort block
-constexpr int kDsSortItems = PM_DS_SORT_ITEMS;                         // pairs per thread there
+// bucket-sort block and pairs per thread there (1024 x 16 measured fastest
+// of 1024 x 16, 512 x 32 and 256 x 64)
+constexpr int kDsSortThreads = 1024;
+constexpr int kDsSortItems = 16;
 constexpr uint32_t kDsSub = (uint32_t)kDsSortThreads * kDsSortItems;  // buckets ordered in LDS, at most
 static_assert(kDsSub < 65536, "the counts of a bucket ordered in LDS fit 16 bits");
 static_assert(kDsThreads * 2 == kDsBuckets, "the scatter block scans the buckets two per thread");
