@@ -122,3 +122,29 @@ def test_errors():
     with pytest.raises(ps.PathSampError):
         s.draw_order(False, 1, 1000)
     s.destroy()
+
+
+def test_default_threshold_is_2_pow_21():
+    # pm_count sorts a sampler's ids from 2^21 samples on (the default of
+    # pm_set_draw_order); below, the samples run in id order.  Tallies are
+    # the same either way, so the launch is told apart by its timed scopes.
+    off, col = synth.rmat(10, 8, seed=5)
+    g = _graph(off, col)
+    ps.set_draw_order(True, 0)
+    runs = {}
+    try:
+        for k in ((1 << 21) - 1, 1 << 21):
+            _say("draw order: default threshold, k", k)
+            ps.profile_enable(True)
+            r = g.count(k, k, seed=3)
+            torch.cuda.synchronize()
+            runs[k] = (ps.profile_read(), r)
+            ps.profile_enable(False)
+    finally:
+        ps.profile_enable(False)
+    below, at = runs[(1 << 21) - 1][0], runs[1 << 21][0]
+    assert "sample_path.sorted" not in below and "draw_sort.keys" not in below
+    assert below["sample_path"][0] == 1
+    assert at["sample_path.sorted"][0] == 1 and at["sample_centered.sorted"][0] == 1
+    assert at["draw_sort.keys"][0] == 2  # one sort per sampler
+    g.destroy()
