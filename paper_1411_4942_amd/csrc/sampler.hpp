@@ -16,8 +16,9 @@ namespace pm {
 
 // The adjacency tests a sample still needs after its picks: three row
 // windows [lo, hi) with the key to look for, each the row of the pair's
-// smaller id (after the relabel the shorter or equal row).  3-path: x =
-// [u'~v], y = [u~v'], z = [u'~v']; centered: the same three, z first.
+// smaller id (after the relabel the shorter or equal row), except the
+// 3-path sampler's y under the row hash (below).  3-path: x = [u'~v],
+// y = [u~v'], z = [u'~v']; centered: the same three, z first.
 struct SampleTests {
     uint32_t lo[3], hi[3], key[3];
 };
@@ -39,8 +40,11 @@ __device__ __forceinline__ void test_window(SampleTests &t, int i, uint32_t a, u
 // Algorithms 2 and 4.  Returns PM_TALLY_TRI when the picks coincide (the
 // triangle outcome), else kUndecided with the tests filled.  Every record
 // carries its column's row bounds, so each test knows its row without
-// another load.
-template <bool CENTERED>
+// another load.  With ROW_U_FOR_Y (the row hash, where a test costs one line
+// whatever the row's length) the 3-path sampler's y = [u~v'] probes row u
+// itself: samples in draw order run through row u's slots one after another,
+// so that row's hash lines are the ones most likely cached.
+template <bool CENTERED, bool ROW_U_FOR_Y = false>
 __device__ __forceinline__ uint32_t sample_picks(const SamplerView &g, uint32_t s, uint64_t o, uint64_t ws,
                                                  SampleTests &t)
 {
@@ -73,7 +77,13 @@ __device__ __forceinline__ uint32_t sample_picks(const SamplerView &g, uint32_t 
     // centered: v < u' and u < v' by construction, so x and y search the
     // rows of v and u
     test_window(t, 0, up, pu.coff, pu.cdeg, v, ov, dv);
-    test_window(t, 1, u, ou, du, vp, pv.coff, pv.cdeg);
+    if (!CENTERED && ROW_U_FOR_Y) {
+        t.lo[1] = ou;
+        t.hi[1] = ou + du;
+        t.key[1] = vp;
+    } else {
+        test_window(t, 1, u, ou, du, vp, pv.coff, pv.cdeg);
+    }
     test_window(t, 2, up, pu.coff, pu.cdeg, vp, pv.coff, pv.cdeg);
     return kUndecided;
 }
@@ -104,7 +114,7 @@ template <bool CENTERED, int SEARCH = PM_SEARCH_HASH>
 __device__ __forceinline__ uint32_t sample_decode(const SamplerView &g, uint32_t s, uint64_t o, uint64_t ws)
 {
     SampleTests t;
-    const uint32_t pre = sample_picks<CENTERED>(g, s, o, ws, t);
+    const uint32_t pre = sample_picks<CENTERED, SEARCH == PM_SEARCH_HASH>(g, s, o, ws, t);
     if (pre != kUndecided) return pre;
     if (!CENTERED) {
         const uint32_t x = row_contains<SEARCH>(g, t, 0);
